@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Throughput of the sketched-ANLS (DSANLS) hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one outer iteration of the method (update_U then update_V, Alg. 2
+with one node) on synthetic data already resident in HBM.  The default
+workload is the dense 20000 x 10000 planted matrix, k = 64, Gaussian sketch
+d = d' = 1024, one prox-CD sweep per update, in FP32.  W warm-up iterations
+run first, then U and V are reset to U^0, V^0 and exactly K iterations
+t = 0 .. K-1 are timed between two device synchronisations.  One JSON line
+is printed: the throughput, the roofline of the dominant kernel (its
+duration taken from HIP events recorded around it in the timed region), the
+relative objective reached, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32_mfma_tflops": 157.3, "bf16_mfma_tflops": 2500.0, "hbm_gbs": 8000.0,
+        "fp32_valu_tflops": 78.6}
+
+WORKLOADS = {
+    # the small FP64-checkable case (parity configuration)
+    "dense-200x150": dict(kind="dense", m=200, n=150, k=10, d=40, iters=20, solver="pgd",
+                          gen="uniform", precision="fp32"),
+    # plain FP32 on one GPU (the default bench line)
+    "dense-20000x10000": dict(kind="dense", m=20000, n=10000, k=64, d=1024, iters=50, solver="prox_cd",
+                              gen="planted", noise=0.01, noise_relative=False, precision="fp32"),
+    # precision form: planted rank-128 + 1% noise, FP32 and BF16 sketch GEMM
+    "dense-50000x20000-fp32": dict(kind="dense", m=50000, n=20000, k=128, d=4096, iters=30,
+                                   solver="prox_cd", gen="planted", noise=0.01, noise_relative=True,
+                                   precision="fp32"),
+    "dense-50000x20000-bf16": dict(kind="dense", m=50000, n=20000, k=128, d=4096, iters=30,
+                                   solver="prox_cd", gen="planted", noise=0.01, noise_relative=True,
+                                   precision="bf16"),
+}
+DEFAULT = "dense-20000x10000"
+
+
+def describe(name, w):
+    if w["kind"] == "dense":
+        gen = ("uniform[0,1)" if w["gen"] == "uniform" else
+               f"planted rank-{w['k']} |N(0,1)| factors + noise")
+        return (f"dense {w['m']}x{w['n']} {gen}, k={w['k']}, Gaussian sketch d=d'={w['d']}, "
+                f"{'prox-CD 1 sweep' if w['solver'] == 'prox_cd' else 'PGD'}, "
+                f"sketch GEMM {w['precision'].upper()}, {w['iters']} iterations")
+    return name
+
+
+def make_dense(w, seed=0):
+    from paper_2009_02845_amd import synth
+    m, n, k = w["m"], w["n"], w["k"]
+    if w["gen"] == "uniform":
+        M = synth.dense_uniform(m, n, seed)
+    else:
+        M = synth.planted_dense(m, n, k, seed, noise_sd=w["noise"], noise_relative=w["noise_relative"])
+    U0, V0 = synth.init_factors(m, n, k, seed)
+    return M, U0, V0
+
+
+def cpu_baseline(w, M, U0, V0, budget_s=12.0, max_iters=5):
+    """The FP64 oracle, untuned, timed on the host's cores over whole iterations."""
+    from oracle import dsanls as O
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    cfg = O.Config(k=w["k"], d=w["d"], d_prime=w["d"], sketch=O.SKETCH_GAUSSIAN, solver=w["solver"])
+    M64 = M.astype(np.float64)
+    U, V = U0.astype(np.float64), V0.astype(np.float64)
+    done, t0 = 0, time.perf_counter()
+    while done < max_iters:
+        U = O.update_U(M64, U, V, done, cfg)
+        V = O.update_V(M64, U, V, done, cfg)
+        done += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "iterations/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{done} full iterations (t=0..{done - 1}) of the same workload in FP64 numpy, "
+                      f"{el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed iterations (default: the workload's)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the method's multi-GPU form (an all-reduce of the k x d "
+              f"sketch product per half-iteration) is not built; --gpus {args.gpus} is not supported.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2009_02845_amd import binding as B
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(2)
+    B.load()
+    w = WORKLOADS[args.workload]
+    K = args.steps if args.steps is not None else w["iters"]
+    W = args.warmup
+    print(f"[bench] workload {args.workload}: generating data", file=sys.stderr, flush=True)
+    M, U0, V0 = make_dense(w, args.seed)
+    m, n, k, d = w["m"], w["n"], w["k"], w["d"]
+    dev = torch.device("cuda", 0)
+    Md = torch.from_numpy(M).to(dev)
+    U0d, V0d = torch.from_numpy(U0).to(dev), torch.from_numpy(V0).to(dev)
+    U, V = U0d.clone(), V0d.clone()
+    cfg = B.make_config(m, n, k, d, d, sketch="gaussian", solver=w["solver"], precision=w["precision"],
+                        sweeps=1, alpha=1.0, beta=1.0, seed=0)
+    solver = B.Solver(cfg, B.dense_matrix(Md), U, V, tensors=[Md])
+    print(f"[bench] warmup {W} iterations", file=sys.stderr, flush=True)
+    for t in range(W):
+        solver.iteration(t)
+    torch.cuda.synchronize()
+    U.copy_(U0d)
+    V.copy_(V0d)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {K} iterations", file=sys.stderr, flush=True)
+    solver.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(K):
+        solver.iteration(t)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    solver.set_timing(False)
+    tm = solver.timing()
+    rel = solver.objective()
+    its = K / el
+    launches = 2 * K
+    prod_avg_s = tm["product_ms"] / 1e3 / launches
+    flops_launch = 2.0 * m * n * d          # A = M S (m x n x d) and A' = M^T S' (n x m x d')
+    peak = PEAK["bf16_mfma_tflops"] if w["precision"] == "bf16" else PEAK["fp32_mfma_tflops"]
+    achieved = flops_launch / prod_avg_s / 1e12
+    out = {
+        "metric": "sketched-ANLS iterations/s (and NNLS rows/s) to a fixed relative objective",
+        "value": its,
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * el / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-sketch/f32" if w["precision"] == "bf16" else "f32",
+        "data": "synthetic",
+        "config": {"workload": describe(args.workload, w), "m": m, "n": n, "k": k, "d": d,
+                   "iterations": K, "parallelism": "single GPU"},
+        "rel_objective": rel,
+        "nnls_rows_per_s": (m + n) * K / (tm["nnls_ms"] / 1e3) if tm["nnls_ms"] > 0 else None,
+        "phase_ms_per_step": {p: tm[p + "_ms"] / K for p in ("sketch", "product", "small", "nnls")},
+        "roofline": {"kernel": "sketch GEMM A = M S (gemm_nt_kernel)", "bound": "mfma",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None,
+                     "flops_per_launch": flops_launch, "avg_launch_ms": prod_avg_s * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, M, U0, V0)
+    solver.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,249 @@
+/*
+ * dsanls.h -- C ABI of the MI355X (gfx950) sketched-ANLS library.
+ *
+ * The library runs the per-node hot path of DSANLS (Alg. 2 of "Fast and
+ * Secure Distributed Nonnegative Matrix Factorization", arXiv 2009.02845) on
+ * one GPU, for the problem min_{U>=0, V>=0} ||M - U V^T||_F (eq. problem):
+ *
+ *   update_U(t):  S^t (n x d) random sketch            (Sec. 3.3)
+ *                 A = M S^t,  B = V^T S^t              (eq. def_A_B)
+ *                 G = B B^T,  R = A B^T                (eq. gradient_descent)
+ *                 U <- prox-CD sweep(s) or PGD step    (Alg. 3 / eq. gradient_descent)
+ *   update_V(t):  the same on M^T with S'^t (m x d') and the current U.
+ *   objective:    ||M - U V^T||_F / ||M||_F            (Sec. 5.1)
+ *
+ * Conventions (all entry points):
+ *   - Matrices are row-major.  "Device" pointers are HIP device memory owned
+ *     by the caller; the library never allocates or frees device memory: all
+ *     scratch space lives in the caller's workspace.
+ *   - Work is enqueued on the caller's HIP stream (hip_stream may be NULL
+ *     for the null stream) and is asynchronous unless stated otherwise.
+ *   - Every call returns a dsanls_status; nothing is thrown across the ABI.
+ *     dsanls_last_error() returns a message for the calling thread's last
+ *     failure.  A context is not thread-safe; separate contexts on separate
+ *     streams are independent.
+ */
+#ifndef DSANLS_H
+#define DSANLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DSANLS_OK = 0,
+  DSANLS_E_INVALID_ARG = 1,  /* bad pointer, enum or parameter value           */
+  DSANLS_E_SHAPE = 2,        /* inconsistent or unsupported sizes              */
+  DSANLS_E_WORKSPACE = 3,    /* workspace missing, misaligned or too small     */
+  DSANLS_E_HIP = 4,          /* a HIP runtime call failed                      */
+  DSANLS_E_NONFINITE = 5,    /* NaN/Inf found in M, U or V                     */
+  DSANLS_E_STATE = 6,        /* call out of order (e.g. before init)           */
+  DSANLS_E_UNSUPPORTED = 7   /* valid request this build does not implement    */
+} dsanls_status;
+
+/* Kind of random sketch (Sec. 3.3).  IDENTITY (S = I, needs d = n and
+ * d' = m) turns the method into exact-product ANLS and is meant for tests. */
+typedef enum {
+  DSANLS_SKETCH_GAUSSIAN = 0,   /* i.i.d. N(0, 1/d) entries                   */
+  DSANLS_SKETCH_SUBSAMPLE = 1,  /* d columns e_j without replacement, x sqrt(n/d) */
+  DSANLS_SKETCH_IDENTITY = 2
+} dsanls_sketch;
+
+/* Subproblem solver (Sec. 3.4). */
+typedef enum {
+  DSANLS_SOLVER_PROX_CD = 0,    /* proximal coordinate descent, Alg. 3        */
+  DSANLS_SOLVER_PGD = 1         /* one projected-gradient step                */
+} dsanls_solver;
+
+/* Arithmetic of the dense sketch product A = M S. */
+typedef enum {
+  DSANLS_PREC_FP32 = 0,         /* FP32 MFMA, FP32 accumulation               */
+  DSANLS_PREC_BF16_SKETCH = 1   /* M and S rounded to BF16, BF16 MFMA, FP32
+                                   accumulation; B, G, R and the solver FP32  */
+} dsanls_precision;
+
+typedef enum { DSANLS_DENSE = 0, DSANLS_CSR = 1 } dsanls_format;
+
+/*
+ * Problem and method parameters.
+ *   m, n       M is m x n; U is m x k and V is n x k (row-major, ld = k).
+ *   d, d_prime sketch sizes of the U- and V-subproblems (eq. sketched_u/v).
+ *   alpha,beta proximal weight mu_t = alpha + beta * t (Sec. 5.1), used by
+ *              prox-CD and, through the step 1/(2(L_t + mu_t)), by PGD.
+ *   sweeps     prox-CD sweeps per update (the paper uses 1); 0 sweeps each
+ *              row until its relative KKT residual <= tol or max_sweeps.
+ *   clip_upper nonzero clips U, V to sqrt(2 ||M||_F) (eq. extra_con).
+ *   seed       key of the counter-based generator: equal seeds give equal
+ *              S^t on every node (Sec. 3.3).
+ */
+typedef struct {
+  int64_t m, n, k, d, d_prime;
+  int32_t sketch;      /* dsanls_sketch    */
+  int32_t solver;      /* dsanls_solver    */
+  int32_t precision;   /* dsanls_precision */
+  int32_t sweeps;
+  int32_t max_sweeps;
+  int32_t clip_upper;
+  double tol;
+  double alpha, beta;
+  uint64_t seed;
+} dsanls_config;
+
+/*
+ * The local data of one node: Alg. 2 takes both M_{I_r:} and M_{:J_r} as
+ * input; with one node these are M and M^T.
+ *   DENSE: dense (m x n, leading dimension ld >= n).  dense_t (n x m, ld_t)
+ *          may be NULL, in which case init builds M^T in the workspace.
+ *   CSR:   rowptr[m+1] (int64), colidx[nnz] (int32, sorted within each row,
+ *          no duplicates), vals[nnz]; plus the same arrays of CSR(M^T)
+ *          (t_rowptr[n+1], t_colidx, t_vals), which are required.
+ * All arrays are device memory, read-only, and must outlive the context.
+ */
+typedef struct {
+  int32_t format;      /* dsanls_format */
+  const float* dense;
+  int64_t ld;
+  const float* dense_t;
+  int64_t ld_t;
+  const int64_t* rowptr;
+  const int32_t* colidx;
+  const float* vals;
+  int64_t nnz;
+  const int64_t* t_rowptr;
+  const int32_t* t_colidx;
+  const float* t_vals;
+} dsanls_matrix;
+
+typedef struct dsanls_ctx dsanls_ctx;
+
+/* Counters accumulated since init (read with dsanls_get_stats). */
+typedef struct {
+  int64_t updates;          /* half-iterations run                           */
+  int64_t rows_updated;     /* NNLS rows solved                              */
+  int64_t sweeps_total;     /* prox-CD row-sweeps run (to-tol mode: counted) */
+  int64_t rows_unconverged; /* to-tol rows that hit max_sweeps               */
+  int64_t warm_fallbacks;   /* warm-started rows restarted from U^t          */
+} dsanls_stats;
+
+/* Size in bytes of the device workspace init needs for (cfg, M). */
+dsanls_status dsanls_workspace_bytes(const dsanls_config* cfg, const dsanls_matrix* M,
+                                     size_t* bytes);
+
+/*
+ * Validate the problem, carve the workspace (device memory of at least
+ * dsanls_workspace_bytes, 256-byte aligned), prepare M^T / BF16 copies and
+ * ||M||_F^2, and return a context.  U (m x k) and V (n x k) are device
+ * arrays holding U^0 >= 0 and V^0 >= 0; they are updated in place by the
+ * update calls.  Synchronises the stream once (for ||M||_F^2).
+ * Errors: INVALID_ARG (null pointers, alpha/beta < 0, mu_0 = 0 without
+ * to-tol mode, bad enums), SHAPE (sizes, d > n for subsampling, d != n for
+ * identity), WORKSPACE, UNSUPPORTED (Gaussian sketch on CSR input, BF16 on
+ * CSR input, k > 128), HIP.
+ */
+dsanls_status dsanls_init(const dsanls_config* cfg, const dsanls_matrix* M, float* U, float* V,
+                          void* workspace, size_t workspace_bytes, void* hip_stream,
+                          dsanls_ctx** out);
+
+/* One U half-iteration at outer iteration t (Alg. 2, U-side, N = 1):
+ * U <- update(M, U, V).  Asynchronous. */
+dsanls_status dsanls_sketch_update_U(dsanls_ctx* ctx, int64_t t);
+
+/* One V half-iteration at outer iteration t on M^T with the current U
+ * (which is U^{t+1} after update_U(t), as in Alg. 1).  Asynchronous. */
+dsanls_status dsanls_sketch_update_V(dsanls_ctx* ctx, int64_t t);
+
+/* Relative error ||M - U V^T||_F / ||M||_F of the current U, V (Sec. 5.1).
+ * Synchronises the stream.  Returns NONFINITE if the residual is NaN/Inf. */
+dsanls_status dsanls_objective(dsanls_ctx* ctx, double* rel_err);
+
+dsanls_status dsanls_get_stats(dsanls_ctx* ctx, dsanls_stats* out);
+
+/* Per-phase GPU time of the updates run while timing was enabled, from HIP
+ * events recorded on the context's stream around each phase:
+ *   sketch   -- drawing S^t (Philox Gaussian sketch or subsample selection)
+ *   product  -- the sketch product: A = M S on MFMA (dense), the gathered
+ *               columns (dense subsample), or R from the CSR stream (sparse)
+ *   small    -- B = W^T S, G = B B^T, R = A B^T and the transposes
+ *   nnls     -- the batched NNLS update (prox-CD or PGD)
+ * launches counts the half-iterations timed.  get_timing synchronises. */
+typedef struct {
+  double sketch_ms, product_ms, small_ms, nnls_ms;
+  int64_t launches;
+} dsanls_timing;
+dsanls_status dsanls_set_timing(dsanls_ctx* ctx, int32_t enable);
+dsanls_status dsanls_get_timing(dsanls_ctx* ctx, dsanls_timing* out);
+
+/* Copy an intermediate of the last update to host memory (synchronises).
+ * which: 0 = S^T as d x n (Gaussian) or sampled indices (int32, subsample),
+ *        1 = A (rows x d, dense paths), 2 = B (k x d), 3 = G (k x k),
+ *        4 = R (rows x k).  bytes must equal the object's size. */
+dsanls_status dsanls_debug_fetch(dsanls_ctx* ctx, int32_t which, void* dst, size_t bytes);
+
+/* Release the context (host memory only; caller buffers untouched). */
+dsanls_status dsanls_destroy(dsanls_ctx* ctx);
+
+const char* dsanls_status_string(dsanls_status s);
+const char* dsanls_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Stand-alone kernels of the path, exported for tests and benchmarks.
+ * ------------------------------------------------------------------------- */
+
+/* Philox4x32-10 block function (Salmon et al., SC'11) on count counters:
+ * ctr[4*count], key[2*count] in, out[4*count] out (device, uint32). */
+dsanls_status dsanls_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out,
+                                   int64_t count, void* hip_stream);
+
+/* Gaussian sketch S (n x d, N(0, 1/d), Sec. 3.3) written transposed: St is
+ * d x n with leading dimension ld_st >= n (device, FP32).  Row j of S uses
+ * counters (q, j, side, t) with key = seed. */
+dsanls_status dsanls_gaussian_sketch_t(uint64_t seed, int64_t t, int32_t side, int64_t n,
+                                       int64_t d, float* St, int64_t ld_st, void* hip_stream);
+
+/* Subsampling sketch (Sec. 3.3): the d indices of [0, n) with the smallest
+ * 64-bit Philox keys (ties by index), written ascending to idx[d] (device
+ * int32).  workspace: device memory of dsanls_subsample_workspace_bytes(n). */
+size_t dsanls_subsample_workspace_bytes(int64_t n);
+dsanls_status dsanls_subsample_indices(uint64_t seed, int64_t t, int32_t side, int64_t n,
+                                       int64_t d, int32_t* idx, void* workspace,
+                                       size_t workspace_bytes, void* hip_stream);
+
+/* C = X Y^T (FP32 MFMA, FP32 accumulation): X is rows x K (ldx), Y is
+ * cols x K (ldy), C is rows x cols (ldc); all device FP32.  X and Y may be
+ * NULL when K = 0 (C is then set to zero).  workspace may be NULL (no
+ * split-K) or hold dsanls_gemm_workspace_bytes(rows, cols, K) bytes. */
+size_t dsanls_gemm_workspace_bytes(int64_t rows, int64_t cols, int64_t K);
+dsanls_status dsanls_gemm_nt(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* C,
+                             int64_t ldc, int64_t rows, int64_t cols, int64_t K, void* workspace,
+                             size_t workspace_bytes, void* hip_stream);
+
+/* Batched row-wise NNLS of the regularised sketched subproblem (eq. reg_sub):
+ * for every row i of U (rows x k, in place), starting from U[i] and with
+ * proximal centre C[i] (C may equal U), run prox-CD sweeps (Alg. 3) on
+ * min_{u>=0} u G u^T - 2 r_i u^T + mu ||u - c_i||^2 with G (k x k; column j
+ * of G is used for coordinate j) and R (rows x k).  sweeps >= 1: exactly
+ * that many; sweeps = 0: until the relative KKT residual
+ * ||pg|| / ||r_i + mu c_i|| <= tol or max_sweeps.  sweeps_used (device
+ * int32[rows]) may be NULL.  upper > 0 clips entries to upper.  1 <= k <= 128
+ * (else UNSUPPORTED).  workspace: device memory of
+ * dsanls_nnls_workspace_bytes(k) bytes for the prepared Gram. */
+size_t dsanls_nnls_workspace_bytes(int32_t k);
+dsanls_status dsanls_nnls_prox_cd(const float* G, const float* R, const float* C, float* U,
+                                  int64_t rows, int32_t k, float mu, int32_t sweeps, float tol,
+                                  int32_t max_sweeps, float upper, int32_t* sweeps_used,
+                                  void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* One projected-gradient step (eq. gradient_descent) with eta computed on
+ * the device as 1 / (2 (max_j sum_l |G_lj| + mu)):
+ * U <- max(U - 2 eta (U G - R), 0), in place.  Workspace as above. */
+dsanls_status dsanls_pgd_step(const float* G, const float* R, float* U, int64_t rows, int32_t k,
+                              float mu, float upper, void* workspace, size_t workspace_bytes,
+                              void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSANLS_H */

@@ -1,0 +1,559 @@
+// Host side of the C ABI: validation, workspace planning and the sequence
+// of kernels of one half-iteration (Alg. 2 with N = 1).
+#include "common.hpp"
+
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace dsanls {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+dsanls_status fail(dsanls_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+dsanls_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return DSANLS_E_HIP;
+}
+
+namespace {
+
+constexpr int64_t kMaxRank = 128;
+
+int64_t r4(int64_t x) { return (x + 3) / 4 * 4; }
+int64_t r8(int64_t x) { return (x + 7) / 8 * 8; }
+
+// Device buffers carved from the caller's workspace.
+struct Layout {
+  float* Mt = nullptr;              // n x ldmt, resident M^T (dense, when not supplied)
+  int64_t ldmt = 0;
+  __hip_bfloat16* Mb = nullptr;     // m x ldmb (BF16 copy of M)
+  __hip_bfloat16* Mtb = nullptr;    // n x ldmtb
+  int64_t ldmb = 0, ldmtb = 0;
+  float* St = nullptr;              // d x lds, sketch transposed
+  __hip_bfloat16* Sb = nullptr;     // d x ldsb
+  float* A = nullptr;               // rows x lda
+  float* Wt = nullptr;              // k x ldw, fixed factor transposed
+  float* B = nullptr;               // k x ldb
+  float* G = nullptr;               // k x k
+  float* Gobj = nullptr;            // 2 x k x k (objective Grams)
+  float* R = nullptr;               // rows x k
+  void* gemm_ws = nullptr;
+  size_t gemm_ws_bytes = 0;
+  void* nnls_ws = nullptr;
+  size_t nnls_ws_bytes = 0;
+  int32_t* idx = nullptr;
+  int32_t* slot = nullptr;
+  void* sub_ws = nullptr;
+  size_t sub_ws_bytes = 0;
+  float* partials = nullptr;
+  float* red = nullptr;             // 64 floats of small results
+  int* err = nullptr;               // 16 ints of device flags
+  unsigned long long* counters = nullptr;
+  size_t total = 0;
+};
+
+bool dense(const dsanls_matrix* M) { return M->format == DSANLS_DENSE; }
+
+Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes, 256);
+    return p;
+  };
+  const int64_t m = c.m, n = c.n, k = c.k;
+  const int64_t lngmax = std::max(m, n), rowsmax = std::max(m, n), dmax = std::max(c.d, c.d_prime);
+  const bool is_dense = dense(&M);
+  const bool gauss = c.sketch == DSANLS_SKETCH_GAUSSIAN;
+  const bool sub = c.sketch == DSANLS_SKETCH_SUBSAMPLE;
+  const bool bf16 = c.precision == DSANLS_PREC_BF16_SKETCH;
+  if (is_dense && M.dense_t == nullptr) {
+    L.ldmt = r4(m);
+    L.Mt = reinterpret_cast<float*>(take(sizeof(float) * n * L.ldmt));
+  }
+  if (is_dense && bf16) {
+    L.ldmb = r8(n);
+    L.ldmtb = r8(m);
+    L.Mb = reinterpret_cast<__hip_bfloat16*>(take(2 * m * L.ldmb));
+    L.Mtb = reinterpret_cast<__hip_bfloat16*>(take(2 * n * L.ldmtb));
+  }
+  if (gauss) {
+    L.St = reinterpret_cast<float*>(take(sizeof(float) * dmax * r4(lngmax)));
+    if (bf16) L.Sb = reinterpret_cast<__hip_bfloat16*>(take(2 * dmax * r8(lngmax)));
+  }
+  if (is_dense && (gauss || sub)) L.A = reinterpret_cast<float*>(take(sizeof(float) * rowsmax * r4(dmax)));
+  L.Wt = reinterpret_cast<float*>(take(sizeof(float) * k * r4(lngmax)));
+  L.B = reinterpret_cast<float*>(take(sizeof(float) * k * r4(dmax)));
+  L.G = reinterpret_cast<float*>(take(sizeof(float) * k * k));
+  L.Gobj = reinterpret_cast<float*>(take(sizeof(float) * 2 * k * k));
+  L.R = reinterpret_cast<float*>(take(sizeof(float) * rowsmax * k));
+  size_t gws = 0;
+  for (int side = 0; side < 2; ++side) {
+    const int64_t rows = side == 0 ? m : n, lng = side == 0 ? n : m, d = side == 0 ? c.d : c.d_prime;
+    const int64_t kdim = c.sketch == DSANLS_SKETCH_IDENTITY ? lng : d;
+    gws = std::max(gws, gemm_ws_bytes(rows, d, lng));
+    gws = std::max(gws, gemm_ws_bytes(k, d, lng));
+    gws = std::max(gws, gemm_ws_bytes(rows, k, kdim));
+  }
+  L.gemm_ws_bytes = gws;
+  L.gemm_ws = gws ? take(gws) : nullptr;
+  L.nnls_ws_bytes = align_up(nnls_ws_bytes(static_cast<int>(std::min<int64_t>(k, kMaxRank))), 256);
+  L.nnls_ws = take(L.nnls_ws_bytes);
+  if (sub) {
+    L.idx = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * dmax));
+    L.slot = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * lngmax));
+    L.sub_ws_bytes = subsample_ws_bytes(lngmax);
+    L.sub_ws = take(L.sub_ws_bytes);
+  }
+  int64_t np = std::max<int64_t>(sumsq_partials(is_dense ? m : 1, is_dense ? n : std::max<int64_t>(M.nnz, 1)),
+                                 csr_cross_partials(m));
+  if (is_dense) np = std::max(np, residual_partials(m, n));
+  L.partials = reinterpret_cast<float*>(take(sizeof(float) * 4 * np));
+  L.red = reinterpret_cast<float*>(take(sizeof(float) * 64));
+  L.err = reinterpret_cast<int*>(take(sizeof(int) * 16));
+  L.counters = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * 8));
+  L.total = off;
+  return L;
+}
+
+dsanls_status validate(const dsanls_config* c, const dsanls_matrix* M) {
+  if (!c || !M) return fail(DSANLS_E_INVALID_ARG, "config or matrix is NULL");
+  if (c->m < 1 || c->n < 1 || c->k < 1 || c->d < 1 || c->d_prime < 1)
+    return fail(DSANLS_E_SHAPE, "m, n, k, d, d_prime must be >= 1");
+  if (c->k > kMaxRank) return fail(DSANLS_E_UNSUPPORTED, "k > 128 is not supported");
+  if (c->m > INT32_MAX || c->n > INT32_MAX) return fail(DSANLS_E_SHAPE, "m and n must fit int32");
+  if (c->sketch < 0 || c->sketch > 2) return fail(DSANLS_E_INVALID_ARG, "bad sketch kind");
+  if (c->solver < 0 || c->solver > 1) return fail(DSANLS_E_INVALID_ARG, "bad solver");
+  if (c->precision < 0 || c->precision > 1) return fail(DSANLS_E_INVALID_ARG, "bad precision");
+  if (c->sketch == DSANLS_SKETCH_SUBSAMPLE && (c->d > c->n || c->d_prime > c->m))
+    return fail(DSANLS_E_SHAPE, "subsampling needs d <= n and d_prime <= m");
+  if (c->sketch == DSANLS_SKETCH_IDENTITY && (c->d != c->n || c->d_prime != c->m))
+    return fail(DSANLS_E_SHAPE, "identity sketch needs d == n and d_prime == m");
+  if (c->sketch == DSANLS_SKETCH_GAUSSIAN && std::max(c->d, c->d_prime) > 4 * 65535)
+    return fail(DSANLS_E_SHAPE, "Gaussian sketch supports d <= 262140");
+  if (!(c->alpha >= 0.0) || !(c->beta >= 0.0) || !std::isfinite(c->alpha) || !std::isfinite(c->beta))
+    return fail(DSANLS_E_INVALID_ARG, "alpha and beta must be finite and >= 0");
+  if (c->solver == DSANLS_SOLVER_PROX_CD) {
+    if (c->sweeps < 0) return fail(DSANLS_E_INVALID_ARG, "sweeps must be >= 0");
+    if (c->sweeps == 0 && (c->max_sweeps < 1 || !(c->tol >= 0.0)))
+      return fail(DSANLS_E_INVALID_ARG, "to-tolerance mode needs max_sweeps >= 1 and tol >= 0");
+  }
+  if (M->format == DSANLS_DENSE) {
+    if (!M->dense || M->ld < c->n) return fail(DSANLS_E_INVALID_ARG, "dense M: NULL or ld < n");
+    if (M->dense_t && M->ld_t < c->m) return fail(DSANLS_E_INVALID_ARG, "dense M^T: ld_t < m");
+  } else if (M->format == DSANLS_CSR) {
+    if (!M->rowptr || !M->t_rowptr || M->nnz < 0 || (M->nnz > 0 && (!M->colidx || !M->vals || !M->t_colidx || !M->t_vals)))
+      return fail(DSANLS_E_INVALID_ARG, "CSR M: CSR(M) and CSR(M^T) arrays are required");
+    if (c->sketch == DSANLS_SKETCH_GAUSSIAN)
+      return fail(DSANLS_E_UNSUPPORTED, "Gaussian sketch on CSR input is not supported");
+    if (c->precision != DSANLS_PREC_FP32)
+      return fail(DSANLS_E_UNSUPPORTED, "BF16 sketch applies to dense input only");
+  } else {
+    return fail(DSANLS_E_INVALID_ARG, "bad matrix format");
+  }
+  return DSANLS_OK;
+}
+
+}  // namespace
+}  // namespace dsanls
+
+using namespace dsanls;
+
+struct dsanls_ctx {
+  dsanls_config cfg;
+  dsanls_matrix mat;
+  float* U;
+  float* V;
+  hipStream_t stream;
+  Layout L;
+  const float* Mt;  // resident M^T (caller's or ours)
+  int64_t ldmt;
+  double normM2;
+  float upper;
+  // record of the last update, for debug_fetch
+  int last_side = -1;
+  int64_t last_rows = 0, last_d = 0, last_lds = 0, last_lda = 0, last_ldb = 0;
+  const float* last_A = nullptr;
+  const float* last_B = nullptr;
+  dsanls_stats stats{};
+  // phase timing: per phase, event pairs recorded while timing is on
+  bool timing = false;
+  std::vector<hipEvent_t> ev[4];
+  int64_t timed_updates = 0;
+  ~dsanls_ctx() {
+    for (auto& v : ev)
+      for (hipEvent_t e : v) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+enum Phase { kPhSketch = 0, kPhProduct = 1, kPhSmall = 2, kPhNnls = 3 };
+
+// Record an event on the stream (start or end of a phase) when timing is on.
+dsanls_status mark(dsanls_ctx* ctx, int phase) {
+  if (!ctx->timing) return DSANLS_OK;
+  hipEvent_t e;
+  DSANLS_HIP(hipEventCreate(&e));
+  ctx->ev[phase].push_back(e);
+  DSANLS_HIP(hipEventRecord(e, ctx->stream));
+  return DSANLS_OK;
+}
+
+dsanls_status read_scalars(dsanls_ctx* ctx, float* host_red, int n_red, int* host_err) {
+  hipStream_t s = ctx->stream;
+  DSANLS_HIP(hipMemcpyAsync(host_red, ctx->L.red, sizeof(float) * n_red, hipMemcpyDeviceToHost, s));
+  DSANLS_HIP(hipMemcpyAsync(host_err, ctx->L.err, sizeof(int), hipMemcpyDeviceToHost, s));
+  DSANLS_HIP(hipStreamSynchronize(s));
+  return DSANLS_OK;
+}
+
+// One half-iteration: side 0 updates U from (M, V) with S^t (n x d), side 1
+// updates V from (M^T, U) with S'^t (m x d').
+dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
+  const dsanls_config& c = ctx->cfg;
+  const Layout& L = ctx->L;
+  hipStream_t s = ctx->stream;
+  const bool is_dense = ctx->mat.format == DSANLS_DENSE;
+  const bool bf16 = c.precision == DSANLS_PREC_BF16_SKETCH;
+  const int64_t k = c.k;
+  const int64_t rows = side == 0 ? c.m : c.n;
+  const int64_t lng = side == 0 ? c.n : c.m;
+  const int64_t d = side == 0 ? c.d : c.d_prime;
+  float* Wself = side == 0 ? ctx->U : ctx->V;
+  const float* Wother = side == 0 ? ctx->V : ctx->U;
+  const float* X = side == 0 ? ctx->mat.dense : ctx->Mt;
+  const int64_t ldx = side == 0 ? ctx->mat.ld : ctx->ldmt;
+  const __hip_bfloat16* Xb = side == 0 ? L.Mb : L.Mtb;
+  const int64_t ldxb = side == 0 ? L.ldmb : L.ldmtb;
+  const int64_t* rowptr = side == 0 ? ctx->mat.rowptr : ctx->mat.t_rowptr;
+  const int32_t* colidx = side == 0 ? ctx->mat.colidx : ctx->mat.t_colidx;
+  const float* vals = side == 0 ? ctx->mat.vals : ctx->mat.t_vals;
+  const uint32_t tt = static_cast<uint32_t>(t);
+  const double mu = c.alpha + c.beta * static_cast<double>(t);
+  const int64_t lds = r4(lng), ldsb = r8(lng), lda = r4(d), ldb = r4(d), ldw = r4(lng);
+  dsanls_status st = DSANLS_OK;
+#define CHECK(x)                      \
+  do {                                \
+    if ((st = (x)) != DSANLS_OK) return st; \
+  } while (0)
+
+  const float* Bp = L.B;
+  int64_t Bld = ldb, Bk = d;   // B is k x Bk with leading dimension Bld
+  const float* Ap = L.A;
+  int64_t Ald = lda;
+  if (c.sketch == DSANLS_SKETCH_GAUSSIAN) {
+    // S^t transposed (d x lng) and A = X S (rows x d) on MFMA
+    CHECK(mark(ctx, kPhSketch));
+    CHECK(launch_gaussian_sketch_t(c.seed, tt, side, lng, d, L.St, lds, bf16 ? L.Sb : nullptr, s));
+    CHECK(mark(ctx, kPhSketch));
+    CHECK(mark(ctx, kPhProduct));
+    if (bf16) {
+      CHECK(launch_gemm_nt_bf16(Xb, ldxb, L.Sb, ldsb, L.A, lda, rows, d, lng, s));
+    } else {
+      CHECK(launch_gemm_nt(X, ldx, L.St, lds, L.A, lda, rows, d, lng, L.gemm_ws, L.gemm_ws_bytes, s));
+    }
+    CHECK(mark(ctx, kPhProduct));
+    // B = W^T S (k x d), split over the long dimension
+    CHECK(mark(ctx, kPhSmall));
+    CHECK(launch_transpose(Wother, k, L.Wt, ldw, lng, k, s));
+    CHECK(launch_gemm_nt(L.Wt, ldw, L.St, lds, L.B, ldb, k, d, lng, L.gemm_ws, L.gemm_ws_bytes, s));
+  } else if (c.sketch == DSANLS_SKETCH_SUBSAMPLE) {
+    CHECK(mark(ctx, kPhSketch));
+    CHECK(launch_subsample(c.seed, tt, side, lng, d, L.idx, is_dense ? nullptr : L.slot, L.sub_ws,
+                           L.sub_ws_bytes, L.err, s));
+    CHECK(mark(ctx, kPhSketch));
+    const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
+    if (is_dense) {
+      CHECK(mark(ctx, kPhProduct));
+      CHECK(launch_gather_cols(X, ldx, L.idx, rows, d, scale, L.A, lda, s));
+      CHECK(mark(ctx, kPhProduct));
+    }
+    CHECK(mark(ctx, kPhSmall));
+    CHECK(launch_gather_rows_t(Wother, k, L.idx, d, scale, L.B, ldb, s));
+  } else {
+    // identity: A = X, B = W^T
+    CHECK(mark(ctx, kPhSmall));
+    CHECK(launch_transpose(Wother, k, L.Wt, ldw, lng, k, s));
+    Bp = L.Wt;
+    Bld = ldw;
+    Bk = lng;
+    Ap = X;
+    Ald = ldx;
+  }
+  CHECK(launch_gram(Bp, Bld, k, Bk, L.G, s));
+  if (is_dense) {
+    CHECK(launch_gemm_nt(Ap, Ald, Bp, Bld, L.R, k, rows, k, Bk, L.gemm_ws, L.gemm_ws_bytes, s));
+    CHECK(mark(ctx, kPhSmall));
+  } else {
+    CHECK(mark(ctx, kPhSmall));
+    const bool sub = c.sketch == DSANLS_SKETCH_SUBSAMPLE;
+    const float scale = sub ? static_cast<float>(static_cast<double>(lng) / static_cast<double>(d)) : 1.0f;
+    CHECK(mark(ctx, kPhProduct));
+    CHECK(launch_csr_sketch_rhs(rowptr, colidx, vals, rows, sub ? L.slot : nullptr, Wother, k, scale,
+                                L.R, s));
+    CHECK(mark(ctx, kPhProduct));
+  }
+  const bool pgd = c.solver == DSANLS_SOLVER_PGD;
+  CHECK(mark(ctx, kPhNnls));
+  CHECK(launch_nnls(pgd, L.G, L.R, Wself, Wself, rows, static_cast<int>(k), static_cast<float>(mu),
+                    c.sweeps, static_cast<float>(c.tol), c.max_sweeps, ctx->upper, nullptr,
+                    L.counters, L.nnls_ws, L.nnls_ws_bytes, s));
+  CHECK(mark(ctx, kPhNnls));
+  if (ctx->timing) ctx->timed_updates += 1;
+#undef CHECK
+  ctx->last_side = side;
+  ctx->last_rows = rows;
+  ctx->last_d = Bk;
+  ctx->last_lds = lds;
+  ctx->last_A = is_dense ? Ap : nullptr;
+  ctx->last_lda = Ald;
+  ctx->last_B = Bp;
+  ctx->last_ldb = Bld;
+  ctx->stats.updates += 1;
+  ctx->stats.rows_updated += rows;
+  return DSANLS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dsanls_status_string(dsanls_status s) {
+  switch (s) {
+    case DSANLS_OK: return "ok";
+    case DSANLS_E_INVALID_ARG: return "invalid argument";
+    case DSANLS_E_SHAPE: return "bad shape";
+    case DSANLS_E_WORKSPACE: return "workspace too small or misaligned";
+    case DSANLS_E_HIP: return "HIP runtime error";
+    case DSANLS_E_NONFINITE: return "non-finite value";
+    case DSANLS_E_STATE: return "call out of order";
+    case DSANLS_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* dsanls_last_error(void) { return g_last_error.c_str(); }
+
+dsanls_status dsanls_workspace_bytes(const dsanls_config* cfg, const dsanls_matrix* M, size_t* bytes) {
+  if (!bytes) return fail(DSANLS_E_INVALID_ARG, "bytes is NULL");
+  const dsanls_status st = validate(cfg, M);
+  if (st != DSANLS_OK) return st;
+  *bytes = plan(*cfg, *M, nullptr).total;
+  return DSANLS_OK;
+}
+
+dsanls_status dsanls_init(const dsanls_config* cfg, const dsanls_matrix* M, float* U, float* V,
+                          void* workspace, size_t workspace_bytes, void* hip_stream,
+                          dsanls_ctx** out) {
+  if (!out) return fail(DSANLS_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  dsanls_status st = validate(cfg, M);
+  if (st != DSANLS_OK) return st;
+  if (!U || !V) return fail(DSANLS_E_INVALID_ARG, "U or V is NULL");
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(DSANLS_E_WORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+  const size_t need = plan(*cfg, *M, nullptr).total;
+  if (workspace_bytes < need)
+    return fail(DSANLS_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  dsanls_ctx* ctx = new (std::nothrow) dsanls_ctx();
+  if (!ctx) return fail(DSANLS_E_INVALID_ARG, "out of host memory");
+  ctx->cfg = *cfg;
+  ctx->mat = *M;
+  ctx->U = U;
+  ctx->V = V;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->L = plan(*cfg, *M, static_cast<char*>(workspace));
+  const Layout& L = ctx->L;
+  hipStream_t s = ctx->stream;
+  const dsanls_config& c = *cfg;
+  auto bail = [&](dsanls_status e) {
+    delete ctx;
+    return e;
+  };
+  if (hipMemsetAsync(L.err, 0, sizeof(int) * 16, s) != hipSuccess ||
+      hipMemsetAsync(L.counters, 0, sizeof(unsigned long long) * 8, s) != hipSuccess)
+    return bail(fail(DSANLS_E_HIP, "init: memset failed"));
+  if (M->format == DSANLS_DENSE) {
+    if (M->dense_t) {
+      ctx->Mt = M->dense_t;
+      ctx->ldmt = M->ld_t;
+    } else {
+      if ((st = launch_transpose(M->dense, M->ld, L.Mt, L.ldmt, c.m, c.n, s)) != DSANLS_OK) return bail(st);
+      ctx->Mt = L.Mt;
+      ctx->ldmt = L.ldmt;
+    }
+    if (c.precision == DSANLS_PREC_BF16_SKETCH) {
+      if ((st = launch_to_bf16(M->dense, M->ld, L.Mb, L.ldmb, c.m, c.n, s)) != DSANLS_OK) return bail(st);
+      if ((st = launch_to_bf16(ctx->Mt, ctx->ldmt, L.Mtb, L.ldmtb, c.n, c.m, s)) != DSANLS_OK) return bail(st);
+    }
+    if ((st = launch_sumsq(M->dense, M->ld, c.m, c.n, L.partials, s)) != DSANLS_OK) return bail(st);
+    if ((st = launch_combine_partials(L.partials, sumsq_partials(c.m, c.n), 2, L.red, L.err, s)) != DSANLS_OK)
+      return bail(st);
+  } else {
+    const int64_t nnz = std::max<int64_t>(M->nnz, 1);
+    if (M->nnz > 0) {
+      if ((st = launch_sumsq(M->vals, nnz, 1, nnz, L.partials, s)) != DSANLS_OK) return bail(st);
+      if ((st = launch_combine_partials(L.partials, sumsq_partials(1, nnz), 2, L.red, L.err, s)) != DSANLS_OK)
+        return bail(st);
+    } else if (hipMemsetAsync(L.red, 0, 2 * sizeof(float), s) != hipSuccess) {
+      return bail(fail(DSANLS_E_HIP, "init: memset failed"));
+    }
+  }
+  if ((st = launch_check_finite(U, c.m * c.k, L.err, s)) != DSANLS_OK) return bail(st);
+  if ((st = launch_check_finite(V, c.n * c.k, L.err, s)) != DSANLS_OK) return bail(st);
+  float red[2];
+  int err = 0;
+  if ((st = read_scalars(ctx, red, 2, &err)) != DSANLS_OK) return bail(st);
+  if (err) return bail(fail(DSANLS_E_NONFINITE, "init: M, U or V holds NaN/Inf"));
+  ctx->normM2 = static_cast<double>(red[0]) + static_cast<double>(red[1]);
+  ctx->upper = c.clip_upper ? static_cast<float>(std::sqrt(2.0 * std::sqrt(ctx->normM2))) : 0.0f;
+  *out = ctx;
+  return DSANLS_OK;
+}
+
+dsanls_status dsanls_sketch_update_U(dsanls_ctx* ctx, int64_t t) {
+  if (!ctx) return fail(DSANLS_E_STATE, "update_U: context is NULL");
+  if (t < 0 || t > UINT32_MAX) return fail(DSANLS_E_INVALID_ARG, "update_U: t out of range");
+  return half_iteration(ctx, 0, t);
+}
+
+dsanls_status dsanls_sketch_update_V(dsanls_ctx* ctx, int64_t t) {
+  if (!ctx) return fail(DSANLS_E_STATE, "update_V: context is NULL");
+  if (t < 0 || t > UINT32_MAX) return fail(DSANLS_E_INVALID_ARG, "update_V: t out of range");
+  return half_iteration(ctx, 1, t);
+}
+
+dsanls_status dsanls_objective(dsanls_ctx* ctx, double* rel_err) {
+  if (!ctx) return fail(DSANLS_E_STATE, "objective: context is NULL");
+  if (!rel_err) return fail(DSANLS_E_INVALID_ARG, "objective: rel_err is NULL");
+  const dsanls_config& c = ctx->cfg;
+  const Layout& L = ctx->L;
+  hipStream_t s = ctx->stream;
+  dsanls_status st;
+  if ((st = launch_check_finite(ctx->U, c.m * c.k, L.err, s)) != DSANLS_OK) return st;
+  if ((st = launch_check_finite(ctx->V, c.n * c.k, L.err, s)) != DSANLS_OK) return st;
+  double resid = 0.0;
+  if (ctx->mat.format == DSANLS_DENSE) {
+    if ((st = launch_residual_sq(ctx->mat.dense, ctx->mat.ld, ctx->U, ctx->V, c.m, c.n, c.k, L.partials, s)) != DSANLS_OK)
+      return st;
+    if ((st = launch_combine_partials(L.partials, residual_partials(c.m, c.n), 2, L.red, L.err, s)) != DSANLS_OK)
+      return st;
+    float red[2];
+    int err = 0;
+    if ((st = read_scalars(ctx, red, 2, &err)) != DSANLS_OK) return st;
+    if (err) return fail(DSANLS_E_NONFINITE, "objective: non-finite values in U, V or the residual");
+    resid = static_cast<double>(red[0]) + static_cast<double>(red[1]);
+  } else {
+    // ||M||^2 - 2 sum_nnz M_ij <u_i, v_j> + <U^T U, V^T V>
+    const int64_t k = c.k;
+    if ((st = launch_csr_cross(ctx->mat.rowptr, ctx->mat.colidx, ctx->mat.vals, c.m, ctx->U, ctx->V, k,
+                               L.partials, s)) != DSANLS_OK)
+      return st;
+    if ((st = launch_combine_partials(L.partials, csr_cross_partials(c.m), 4, L.red, L.err, s)) != DSANLS_OK)
+      return st;
+    float* GU = L.Gobj;
+    float* GV = L.Gobj + k * k;
+    if ((st = launch_transpose(ctx->U, k, L.Wt, r4(c.m), c.m, k, s)) != DSANLS_OK) return st;
+    if ((st = launch_gram(L.Wt, r4(c.m), k, c.m, GU, s)) != DSANLS_OK) return st;
+    if ((st = launch_transpose(ctx->V, k, L.Wt, r4(c.n), c.n, k, s)) != DSANLS_OK) return st;
+    if ((st = launch_gram(L.Wt, r4(c.n), k, c.n, GV, s)) != DSANLS_OK) return st;
+    if ((st = launch_frob_dot(GU, GV, k * k, L.red + 4, s)) != DSANLS_OK) return st;
+    float red[6];
+    int err = 0;
+    if ((st = read_scalars(ctx, red, 6, &err)) != DSANLS_OK) return st;
+    if (err) return fail(DSANLS_E_NONFINITE, "objective: non-finite values in U, V or the residual");
+    const double cross = static_cast<double>(red[0]) + static_cast<double>(red[1]);
+    const double gg = static_cast<double>(red[4]) + static_cast<double>(red[5]);
+    resid = std::max(0.0, ctx->normM2 - 2.0 * cross + gg);
+  }
+  if (!std::isfinite(resid)) return fail(DSANLS_E_NONFINITE, "objective: residual is not finite");
+  *rel_err = ctx->normM2 > 0 ? std::sqrt(resid / ctx->normM2) : std::sqrt(resid);
+  return DSANLS_OK;
+}
+
+dsanls_status dsanls_get_stats(dsanls_ctx* ctx, dsanls_stats* out) {
+  if (!ctx) return fail(DSANLS_E_STATE, "get_stats: context is NULL");
+  if (!out) return fail(DSANLS_E_INVALID_ARG, "get_stats: out is NULL");
+  unsigned long long cnt[2] = {0, 0};
+  DSANLS_HIP(hipMemcpyAsync(cnt, ctx->L.counters, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
+  DSANLS_HIP(hipStreamSynchronize(ctx->stream));
+  *out = ctx->stats;
+  out->sweeps_total = static_cast<int64_t>(cnt[0]);
+  out->rows_unconverged = static_cast<int64_t>(cnt[1]);
+  return DSANLS_OK;
+}
+
+dsanls_status dsanls_set_timing(dsanls_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(DSANLS_E_STATE, "set_timing: context is NULL");
+  ctx->timing = enable != 0;
+  return DSANLS_OK;
+}
+
+dsanls_status dsanls_get_timing(dsanls_ctx* ctx, dsanls_timing* out) {
+  if (!ctx) return fail(DSANLS_E_STATE, "get_timing: context is NULL");
+  if (!out) return fail(DSANLS_E_INVALID_ARG, "get_timing: out is NULL");
+  DSANLS_HIP(hipStreamSynchronize(ctx->stream));
+  double ms[4] = {0, 0, 0, 0};
+  for (int p = 0; p < 4; ++p) {
+    auto& v = ctx->ev[p];
+    for (size_t i = 0; i + 1 < v.size(); i += 2) {
+      float e = 0.f;
+      DSANLS_HIP(hipEventElapsedTime(&e, v[i], v[i + 1]));
+      ms[p] += e;
+    }
+  }
+  out->sketch_ms = ms[kPhSketch];
+  out->product_ms = ms[kPhProduct];
+  out->small_ms = ms[kPhSmall];
+  out->nnls_ms = ms[kPhNnls];
+  out->launches = ctx->timed_updates;
+  return DSANLS_OK;
+}
+
+dsanls_status dsanls_debug_fetch(dsanls_ctx* ctx, int32_t which, void* dst, size_t bytes) {
+  if (!ctx) return fail(DSANLS_E_STATE, "debug_fetch: context is NULL");
+  if (!dst) return fail(DSANLS_E_INVALID_ARG, "debug_fetch: dst is NULL");
+  if (ctx->last_side < 0) return fail(DSANLS_E_STATE, "debug_fetch: no update has run");
+  const dsanls_config& c = ctx->cfg;
+  const int64_t k = c.k, rows = ctx->last_rows, d = ctx->last_d;
+  const int64_t lng = ctx->last_side == 0 ? c.n : c.m;
+  hipStream_t s = ctx->stream;
+  auto copy2d = [&](const void* src, int64_t ld_elems, int64_t h, int64_t w, size_t esz) -> dsanls_status {
+    if (bytes != static_cast<size_t>(h * w) * esz) return fail(DSANLS_E_INVALID_ARG, "debug_fetch: wrong byte count");
+    DSANLS_HIP(hipMemcpy2DAsync(dst, w * esz, src, ld_elems * esz, w * esz, h, hipMemcpyDeviceToHost, s));
+    DSANLS_HIP(hipStreamSynchronize(s));
+    return DSANLS_OK;
+  };
+  switch (which) {
+    case 0:
+      if (c.sketch == DSANLS_SKETCH_GAUSSIAN) return copy2d(ctx->L.St, ctx->last_lds, d, lng, sizeof(float));
+      if (c.sketch == DSANLS_SKETCH_SUBSAMPLE) return copy2d(ctx->L.idx, d, 1, d, sizeof(int32_t));
+      return fail(DSANLS_E_UNSUPPORTED, "debug_fetch: identity sketch has no stored S");
+    case 1:
+      if (!ctx->last_A) return fail(DSANLS_E_UNSUPPORTED, "debug_fetch: A is not formed on the CSR path");
+      return copy2d(ctx->last_A, ctx->last_lda, rows, d, sizeof(float));
+    case 2: return copy2d(ctx->last_B, ctx->last_ldb, k, d, sizeof(float));
+    case 3: return copy2d(ctx->L.G, k, k, k, sizeof(float));
+    case 4: return copy2d(ctx->L.R, k, rows, k, sizeof(float));
+  }
+  return fail(DSANLS_E_INVALID_ARG, "debug_fetch: bad selector");
+}
+
+dsanls_status dsanls_destroy(dsanls_ctx* ctx) {
+  if (!ctx) return fail(DSANLS_E_STATE, "destroy: context is NULL");
+  delete ctx;
+  return DSANLS_OK;
+}
+
+}  // extern "C"

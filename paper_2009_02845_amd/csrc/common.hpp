@@ -1,0 +1,116 @@
+// Internal declarations shared by the HIP translation units of libdsanls.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "../../include/dsanls.h"
+
+namespace dsanls {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+dsanls_status fail(dsanls_status s, const std::string& msg);
+dsanls_status hip_fail(hipError_t e, const char* what);
+
+#define DSANLS_HIP(call)                                          \
+  do {                                                            \
+    hipError_t e_ = (call);                                       \
+    if (e_ != hipSuccess) return ::dsanls::hip_fail(e_, #call);   \
+  } while (0)
+
+// Check the launch that was just enqueued.
+#define DSANLS_LAUNCHED(name)                                        \
+  do {                                                               \
+    hipError_t e_ = hipGetLastError();                               \
+    if (e_ != hipSuccess) return ::dsanls::hip_fail(e_, name);       \
+  } while (0)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Number of XCDs of an MI355X: workgroups are dispatched round-robin over
+// them and each has its own L2, so tile schedules remap workgroup ids.
+constexpr int kNumXcd = 8;
+
+// ---------------------------------------------------------------- philox.hip
+dsanls_status launch_gaussian_sketch_t(uint64_t seed, uint32_t t, int side, int64_t n, int64_t d,
+                                       float* St, int64_t ld, __hip_bfloat16* St_bf16,
+                                       hipStream_t s);
+// Workspace layout of the subsample selection.
+size_t subsample_ws_bytes(int64_t n);
+// idx[d] ascending; slot (may be null) gets slot[j] = column of index j or -1.
+dsanls_status launch_subsample(uint64_t seed, uint32_t t, int side, int64_t n, int64_t d,
+                               int32_t* idx, int32_t* slot, void* ws, size_t ws_bytes,
+                               int* err_flag, hipStream_t s);
+
+// ---------------------------------------------------------------- gemm.hip
+// C[rows x cols] = X[rows x K] * Y[cols x K]^T, FP32 MFMA.
+size_t gemm_ws_bytes(int64_t rows, int64_t cols, int64_t K);
+dsanls_status launch_gemm_nt(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* C,
+                             int64_t ldc, int64_t rows, int64_t cols, int64_t K, void* ws,
+                             size_t ws_bytes, hipStream_t s);
+// BF16 operands, FP32 accumulation.
+dsanls_status launch_gemm_nt_bf16(const __hip_bfloat16* X, int64_t ldx, const __hip_bfloat16* Y,
+                                  int64_t ldy, float* C, int64_t ldc, int64_t rows, int64_t cols,
+                                  int64_t K, hipStream_t s);
+// Sum over (M - U V^T)^2 into partials (2 floats per workgroup: sum, compensation).
+int64_t residual_partials(int64_t m, int64_t n);
+dsanls_status launch_residual_sq(const float* M, int64_t ldm, const float* U, const float* V,
+                                 int64_t m, int64_t n, int64_t k, float* partials, hipStream_t s);
+
+// ---------------------------------------------------------------- small.hip
+dsanls_status launch_transpose(const float* X, int64_t ldx, float* Y, int64_t ldy, int64_t rows,
+                               int64_t cols, hipStream_t s);
+dsanls_status launch_to_bf16(const float* X, int64_t ldx, __hip_bfloat16* Y, int64_t ldy,
+                             int64_t rows, int64_t cols, hipStream_t s);
+// G = B B^T (k x k) with compensated FP32 sums; B is k x d (ld).
+dsanls_status launch_gram(const float* B, int64_t ld, int64_t k, int64_t d, float* G,
+                          hipStream_t s);
+// Sum of squares of a dense matrix into partials (sum, comp pairs), npart blocks.
+int64_t sumsq_partials(int64_t rows, int64_t cols);
+dsanls_status launch_sumsq(const float* X, int64_t ld, int64_t rows, int64_t cols,
+                           float* partials, hipStream_t s);
+// Combine npart (sum, comp) pairs in a fixed order into out[0..1] (hi, lo)
+// and flag non-finite values.
+dsanls_status launch_combine_partials(const float* partials, int64_t npart, int64_t stride,
+                                      float* out, int* err_flag, hipStream_t s);
+// out[0..1] = compensated sum of X[i] * Y[i] over count entries (one block).
+dsanls_status launch_frob_dot(const float* X, const float* Y, int64_t count, float* out,
+                              hipStream_t s);
+// A[i, c] = scale * X[i, idx[c]] (rows x d), gathered columns.
+dsanls_status launch_gather_cols(const float* X, int64_t ldx, const int32_t* idx, int64_t rows,
+                                 int64_t d, float scale, float* A, int64_t lda, hipStream_t s);
+// B[l, c] = scale * W[idx[c], l] (k x d) from W (rows x k).
+dsanls_status launch_gather_rows_t(const float* W, int64_t k, const int32_t* idx, int64_t d,
+                                   float scale, float* B, int64_t ldb, hipStream_t s);
+dsanls_status launch_check_finite(const float* X, int64_t count, int* err_flag, hipStream_t s);
+
+// ---------------------------------------------------------------- nnls.hip
+size_t nnls_ws_bytes(int k);
+// pgd = false: prox-CD (sweeps >= 1, or 0 = to tol); pgd = true: one PGD step.
+// counters (may be null): [0] += row-sweeps run, [1] += rows left unconverged.
+dsanls_status launch_nnls(bool pgd, const float* G, const float* R, const float* C, float* U,
+                          int64_t rows, int k, float mu, int sweeps, float tol, int max_sweeps,
+                          float upper, int32_t* sweeps_used, unsigned long long* counters,
+                          void* ws, size_t ws_bytes, hipStream_t s);
+
+// ---------------------------------------------------------------- sparse.hip
+// R[i, :] = scale * sum_{e in row i, slot[col_e] >= 0} val_e * W[col_e, :]
+// (slot == nullptr: every column).  CSR rows x ncols, W is ncols x k.
+dsanls_status launch_csr_sketch_rhs(const int64_t* rowptr, const int32_t* colidx,
+                                    const float* vals, int64_t rows, const int32_t* slot,
+                                    const float* W, int64_t k, float scale, float* R,
+                                    hipStream_t s);
+// Sparse objective pieces: sum_nnz M_ij <u_i, v_j> and sum_nnz M_ij^2 as
+// compensated partials.
+int64_t csr_cross_partials(int64_t rows);
+dsanls_status launch_csr_cross(const int64_t* rowptr, const int32_t* colidx, const float* vals,
+                               int64_t rows, const float* U, const float* V, int64_t k,
+                               float* partials, hipStream_t s);
+
+}  // namespace dsanls

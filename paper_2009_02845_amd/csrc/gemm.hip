@@ -1,0 +1,374 @@
+// Dense products of the path on MFMA: the sketch product A = M S (and
+// A' = M^T S'), B = W^T S, R = A B^T, and the residual of the objective.
+//
+// Every product is expressed as C = X Y^T with X (rows x K) and Y (cols x K)
+// both row-major and K-contiguous: S is generated transposed (d x n) and
+// M^T is kept resident next to M, as the paper's node keeps both its row
+// block and its column block of M (Alg. 2 input).
+//
+// Tiling (FP32): 256 threads = 4 waves in a 2 x 2 grid; a workgroup owns a
+// BM x BN tile and each wave a (BM/2) x (BN/2) sub-tile made of 32 x 32
+// v_mfma_f32_32x32x2f32 blocks.  K advances in stages of 32 through a double
+// buffered LDS tile (row stride 36 floats, so the 16-byte fragment reads of
+// 16 consecutive lanes land on distinct banks).  Each lane reads four
+// consecutive k of its row in one ds_read_b128 and feeds them to four MFMAs;
+// lanes 0-31 and 32-63 take interleaved k blocks (k and k+4), which is a
+// permutation of the contraction index shared by X and Y and so leaves the
+// product unchanged.
+#include "common.hpp"
+
+#include <hip/hip_bf16.h>
+
+namespace dsanls {
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBK = 32;
+constexpr int kLds = kBK + 4;
+
+template <int BM, int BN>
+struct TileMap {
+  int row0, col0;
+  __device__ TileMap(int tiles_m, int tiles_n) {
+    // Workgroups are dispatched round-robin over the XCDs; give each XCD a
+    // contiguous run of tiles so the tiles sharing a row block of X meet in
+    // the same L2.
+    const int ntiles = tiles_m * tiles_n;
+    const int wg = blockIdx.x;
+    const int xcd = wg % kNumXcd, local = wg / kNumXcd;
+    const int per = ntiles / kNumXcd, rem = ntiles % kNumXcd;
+    const int logical = xcd * per + (xcd < rem ? xcd : rem) + local;
+    row0 = (logical / tiles_n) * BM;
+    col0 = (logical % tiles_n) * BN;
+  }
+};
+
+template <int NV, bool VEC>
+__device__ __forceinline__ void load_stage(const float* __restrict__ P, int64_t ld, int r0,
+                                           int nrows, int k0, int kend, floatx4 (&reg)[NV]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int id = v * 256 + threadIdx.x;
+    const int r = id >> 3, kq = (id & 7) * 4;
+    const int gr = r0 + r, gk = k0 + kq;
+    floatx4 x = {0.f, 0.f, 0.f, 0.f};
+    if (gr < nrows) {
+      const float* p = P + (int64_t)gr * ld + gk;
+      if (VEC && gk + 3 < kend) {
+        x = *reinterpret_cast<const floatx4*>(p);
+      } else {
+        if (gk + 0 < kend) x[0] = p[0];
+        if (gk + 1 < kend) x[1] = p[1];
+        if (gk + 2 < kend) x[2] = p[2];
+        if (gk + 3 < kend) x[3] = p[3];
+      }
+    }
+    reg[v] = x;
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void store_stage(float* __restrict__ s, const floatx4 (&reg)[NV]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int id = v * 256 + threadIdx.x;
+    const int r = id >> 3, kq = (id & 7) * 4;
+    *reinterpret_cast<floatx4*>(s + r * kLds + kq) = reg[v];
+  }
+}
+
+// Main loop: acc += X[row0.., kbeg..kend) * Y[col0.., kbeg..kend)^T.
+template <int BM, int BN, bool VEC>
+__device__ __forceinline__ void mainloop(const float* __restrict__ X, int64_t ldx,
+                                         const float* __restrict__ Y, int64_t ldy, int rows,
+                                         int cols, int kbeg, int kend, int row0, int col0,
+                                         float* sX, float* sY,
+                                         floatx16 (&acc)[BM / 64][BN / 64]) {
+  constexpr int FM = BM / 64, FN = BN / 64;
+  constexpr int XV = BM * kBK / 4 / 256, YV = BN * kBK / 4 / 256;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lrow = lane & 31, lk = (lane >> 5) * 4;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  if (kbeg >= kend) return;
+
+  floatx4 rx[XV], ry[YV];
+  load_stage<XV, VEC>(X, ldx, row0, rows, kbeg, kend, rx);
+  load_stage<YV, VEC>(Y, ldy, col0, cols, kbeg, kend, ry);
+  store_stage<XV>(sX, rx);
+  store_stage<YV>(sY, ry);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += kBK) {
+    const bool more = k0 + kBK < kend;
+    if (more) {
+      load_stage<XV, VEC>(X, ldx, row0, rows, k0 + kBK, kend, rx);
+      load_stage<YV, VEC>(Y, ldy, col0, cols, k0 + kBK, kend, ry);
+    }
+    const float* cx = sX + buf * (BM * kLds);
+    const float* cy = sY + buf * (BN * kLds);
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += 8) {
+      floatx4 a[FM], b[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        a[i] = *reinterpret_cast<const floatx4*>(cx + (wm * (BM / 2) + i * 32 + lrow) * kLds + kk + lk);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        b[j] = *reinterpret_cast<const floatx4*>(cy + (wn * (BN / 2) + j * 32 + lrow) * kLds + kk + lk);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      store_stage<XV>(sX + (buf ^ 1) * (BM * kLds), rx);
+      store_stage<YV>(sY + (buf ^ 1) * (BN * kLds), ry);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
+// Row of element r of a 32x32 MFMA accumulator held by this lane.
+__device__ __forceinline__ int acc_row(int r, int lane) {
+  return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+}
+
+template <int BM, int BN, bool VEC>
+__global__ __launch_bounds__(256, 2) void gemm_nt_kernel(const float* __restrict__ X, int64_t ldx,
+                                                         const float* __restrict__ Y, int64_t ldy,
+                                                         float* __restrict__ C, int64_t ldc,
+                                                         int64_t split_stride, int rows, int cols,
+                                                         int K, int kchunk, int tiles_m,
+                                                         int tiles_n) {
+  __shared__ __attribute__((aligned(16))) float sX[2 * BM * kLds];
+  __shared__ __attribute__((aligned(16))) float sY[2 * BN * kLds];
+  constexpr int FM = BM / 64, FN = BN / 64;
+  const TileMap<BM, BN> tile(tiles_m, tiles_n);
+  const int kbeg = blockIdx.y * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  floatx16 acc[FM][FN];
+  mainloop<BM, BN, VEC>(X, ldx, Y, ldy, rows, cols, kbeg, kend, tile.row0, tile.col0, sX, sY, acc);
+  float* Cz = C + blockIdx.y * split_stride;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = tile.col0 + wn * (BN / 2) + j * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = tile.row0 + wm * (BM / 2) + i * 32 + acc_row(r, lane);
+        if (row < rows && col < cols) Cz[(int64_t)row * ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+// Fixed-order compensated sum over the split-K partials.
+__global__ void splitk_reduce_kernel(const float* __restrict__ P, int64_t split_stride, int splits,
+                                     int rows, int cols, float* __restrict__ C, int64_t ldc) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows * cols) return;
+  const int r = static_cast<int>(i / cols), c = static_cast<int>(i % cols);
+  float s = 0.f, comp = 0.f;
+  for (int z = 0; z < splits; ++z) {
+    const float x = P[z * split_stride + i];
+    const float t = s + x;
+    comp += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  C[(int64_t)r * ldc + c] = s + comp;
+}
+
+// Neumaier update of (s, c) with x.
+__device__ __forceinline__ void neumaier(float& s, float& c, float x) {
+  const float t = s + x;
+  c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+  s = t;
+}
+
+// Sum over the tile of (M - U V^T)^2; one compensated (sum, comp) pair per
+// workgroup.  The residual is formed entry by entry, so a near-exact fit
+// does not lose its digits to cancellation.
+template <int BM, int BN, bool VEC>
+__global__ __launch_bounds__(256, 2) void residual_kernel(const float* __restrict__ U,
+                                                          const float* __restrict__ V, int k,
+                                                          const float* __restrict__ M,
+                                                          int64_t ldm, int rows, int cols,
+                                                          int tiles_m, int tiles_n,
+                                                          float* __restrict__ partials) {
+  __shared__ __attribute__((aligned(16))) float sX[2 * BM * kLds];
+  __shared__ __attribute__((aligned(16))) float sY[2 * BN * kLds];
+  __shared__ float red[2 * 4];
+  constexpr int FM = BM / 64, FN = BN / 64;
+  const TileMap<BM, BN> tile(tiles_m, tiles_n);
+  floatx16 acc[FM][FN];
+  mainloop<BM, BN, VEC>(U, k, V, k, rows, cols, 0, k, tile.row0, tile.col0, sX, sY, acc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  float s = 0.f, c = 0.f;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = tile.col0 + wn * (BN / 2) + j * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = tile.row0 + wm * (BM / 2) + i * 32 + acc_row(r, lane);
+        if (row < rows && col < cols) {
+          const float e = M[(int64_t)row * ldm + col] - acc[i][j][r];
+          neumaier(s, c, e * e);
+        }
+      }
+    }
+  // wave tree of compensated pairs, then the four waves in order
+  for (int off = 32; off > 0; off >>= 1) {
+    const float os = __shfl_down(s, off, 64), oc = __shfl_down(c, off, 64);
+    neumaier(s, c, os);
+    c += oc;
+  }
+  if (lane == 0) {
+    red[2 * wave] = s;
+    red[2 * wave + 1] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float ts = red[0], tc = red[1];
+    for (int w = 1; w < 4; ++w) {
+      neumaier(ts, tc, red[2 * w]);
+      tc += red[2 * w + 1];
+    }
+    const int64_t b = blockIdx.x;
+    partials[2 * b] = ts;
+    partials[2 * b + 1] = tc;
+  }
+}
+
+template <int BM, int BN>
+dsanls_status gemm_dispatch(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* C,
+                            int64_t ldc, int64_t split_stride, int rows, int cols, int K,
+                            int splits, int kchunk, hipStream_t s) {
+  const int tm = static_cast<int>(ceil_div(rows, BM)), tn = static_cast<int>(ceil_div(cols, BN));
+  dim3 grid(tm * tn, splits);
+  const bool vec = (ldx % 4 == 0) && (ldy % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
+                   (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
+  if (vec)
+    gemm_nt_kernel<BM, BN, true><<<grid, 256, 0, s>>>(X, ldx, Y, ldy, C, ldc, split_stride, rows,
+                                                      cols, K, kchunk, tm, tn);
+  else
+    gemm_nt_kernel<BM, BN, false><<<grid, 256, 0, s>>>(X, ldx, Y, ldy, C, ldc, split_stride, rows,
+                                                       cols, K, kchunk, tm, tn);
+  DSANLS_LAUNCHED("gemm_nt_kernel");
+  return DSANLS_OK;
+}
+
+struct SplitPlan {
+  int splits, kchunk;
+};
+
+SplitPlan plan_split(int64_t rows, int64_t cols, int64_t K, int bm, int bn) {
+  if (K <= 0) return {1, kBK};
+  const int64_t tiles = ceil_div(rows, bm) * ceil_div(cols, bn);
+  int64_t splits = 1;
+  // fewer tiles than half the workgroup slots of the chip and a long K:
+  // split K so that about 512 workgroups run, each with >= 8 stages
+  if (tiles < 256 && K >= 16 * kBK) {
+    splits = std::min<int64_t>(ceil_div(512, tiles), K / (8 * kBK));
+    splits = std::max<int64_t>(1, std::min<int64_t>(splits, 64));
+  }
+  int64_t kchunk = ceil_div(ceil_div(K, splits), kBK) * kBK;
+  splits = ceil_div(K, kchunk);
+  return {static_cast<int>(splits), static_cast<int>(kchunk)};
+}
+
+}  // namespace
+
+size_t gemm_ws_bytes(int64_t rows, int64_t cols, int64_t K) {
+  const int bn = cols <= 64 ? 64 : 128;
+  const SplitPlan p = plan_split(rows, cols, K, 128, bn);
+  return p.splits > 1 ? sizeof(float) * p.splits * rows * cols : 0;
+}
+
+dsanls_status launch_gemm_nt(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* C,
+                             int64_t ldc, int64_t rows, int64_t cols, int64_t K, void* ws,
+                             size_t ws_bytes, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return DSANLS_OK;
+  if (rows > INT32_MAX || cols > INT32_MAX || K > INT32_MAX)
+    return fail(DSANLS_E_SHAPE, "gemm: dimension exceeds int32");
+  if (ceil_div(rows, 64) * ceil_div(cols, 64) > INT32_MAX) return fail(DSANLS_E_SHAPE, "gemm: too many tiles");
+  const int bn = cols <= 64 ? 64 : 128;
+  SplitPlan p = plan_split(rows, cols, K, 128, bn);
+  const size_t need = p.splits > 1 ? sizeof(float) * p.splits * rows * cols : 0;
+  if (p.splits > 1 && (ws == nullptr || ws_bytes < need)) p = {1, static_cast<int>(ceil_div(K, kBK) * kBK)};
+  if (p.splits == 1) {
+    const int kchunk = static_cast<int>(std::max<int64_t>(kBK, ceil_div(K, kBK) * kBK));
+    if (bn == 64)
+      return gemm_dispatch<128, 64>(X, ldx, Y, ldy, C, ldc, 0, (int)rows, (int)cols, (int)K, 1, kchunk, s);
+    return gemm_dispatch<128, 128>(X, ldx, Y, ldy, C, ldc, 0, (int)rows, (int)cols, (int)K, 1, kchunk, s);
+  }
+  float* P = static_cast<float*>(ws);
+  const int64_t stride = rows * cols;
+  dsanls_status st;
+  if (bn == 64)
+    st = gemm_dispatch<128, 64>(X, ldx, Y, ldy, P, cols, stride, (int)rows, (int)cols, (int)K, p.splits, p.kchunk, s);
+  else
+    st = gemm_dispatch<128, 128>(X, ldx, Y, ldy, P, cols, stride, (int)rows, (int)cols, (int)K, p.splits, p.kchunk, s);
+  if (st != DSANLS_OK) return st;
+  splitk_reduce_kernel<<<static_cast<unsigned>(ceil_div(stride, 256)), 256, 0, s>>>(
+      P, stride, p.splits, (int)rows, (int)cols, C, ldc);
+  DSANLS_LAUNCHED("splitk_reduce_kernel");
+  return DSANLS_OK;
+}
+
+int64_t residual_partials(int64_t m, int64_t n) { return ceil_div(m, 128) * ceil_div(n, 128); }
+
+dsanls_status launch_residual_sq(const float* M, int64_t ldm, const float* U, const float* V,
+                                 int64_t m, int64_t n, int64_t k, float* partials, hipStream_t s) {
+  const int tm = static_cast<int>(ceil_div(m, 128)), tn = static_cast<int>(ceil_div(n, 128));
+  const bool vec = (k % 4 == 0) && (reinterpret_cast<uintptr_t>(U) % 16 == 0) &&
+                   (reinterpret_cast<uintptr_t>(V) % 16 == 0);
+  if (vec)
+    residual_kernel<128, 128, true><<<tm * tn, 256, 0, s>>>(U, V, (int)k, M, ldm, (int)m, (int)n, tm, tn, partials);
+  else
+    residual_kernel<128, 128, false><<<tm * tn, 256, 0, s>>>(U, V, (int)k, M, ldm, (int)m, (int)n, tm, tn, partials);
+  DSANLS_LAUNCHED("residual_kernel");
+  return DSANLS_OK;
+}
+
+dsanls_status launch_gemm_nt_bf16(const __hip_bfloat16*, int64_t, const __hip_bfloat16*, int64_t,
+                                  float*, int64_t, int64_t, int64_t, int64_t, hipStream_t) {
+  return fail(DSANLS_E_UNSUPPORTED, "bf16 gemm not built yet");
+}
+
+}  // namespace dsanls
+
+using namespace dsanls;
+
+extern "C" size_t dsanls_gemm_workspace_bytes(int64_t rows, int64_t cols, int64_t K) {
+  return gemm_ws_bytes(rows, cols, K);
+}
+
+extern "C" dsanls_status dsanls_gemm_nt(const float* X, int64_t ldx, const float* Y, int64_t ldy,
+                                        float* C, int64_t ldc, int64_t rows, int64_t cols,
+                                        int64_t K, void* workspace, size_t workspace_bytes,
+                                        void* hip_stream) {
+  if (rows < 0 || cols < 0 || K < 0) return fail(DSANLS_E_SHAPE, "gemm_nt: negative size");
+  if (rows == 0 || cols == 0) return DSANLS_OK;
+  if ((K > 0 && (!X || !Y)) || !C || ldx < K || ldy < K || ldc < cols)
+    return fail(DSANLS_E_INVALID_ARG, "gemm_nt: null pointer or leading dimension too small");
+  return launch_gemm_nt(X, ldx, Y, ldy, C, ldc, rows, cols, K, workspace, workspace_bytes,
+                        static_cast<hipStream_t>(hip_stream));
+}

@@ -1,0 +1,160 @@
+// Sparse (CSR) side of the path: the sketch right-hand side R = A B^T for a
+// subsampling sketch, and the nnz term of the sparse objective.
+//
+// With S = sqrt(n/d) [e_{j_1} .. e_{j_d}], A = M S keeps only the sampled
+// columns of M and B = V^T S the sampled rows of V, so
+//     R[i, :] = (A B^T)[i, :] = (n/d) * sum_{j sampled, M_ij != 0} M_ij V[j, :]
+// (Sec. 3.3: subsampling keeps the sparsity of M).  One wave streams the
+// nnz of a row in coalesced 64-entry chunks, tests each column against the
+// sampled-slot map, and folds the hits, in ascending column order, into a
+// k-vector held across the lanes (two components per lane for k <= 128).
+#include "common.hpp"
+
+namespace dsanls {
+
+namespace {
+
+__device__ __forceinline__ void neumaier(float& s, float& c, float x) {
+  const float t = s + x;
+  c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+  s = t;
+}
+
+__global__ __launch_bounds__(256) void csr_rhs_kernel(const int64_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ colidx,
+                                                      const float* __restrict__ vals,
+                                                      int64_t rows,
+                                                      const int32_t* __restrict__ slot,
+                                                      const float* __restrict__ W, int k,
+                                                      float scale, float* __restrict__ R) {
+  const int64_t row = blockIdx.x * 4ll + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const int64_t beg = rowptr[row], end = rowptr[row + 1];
+  float a0 = 0.f, a1 = 0.f;
+  for (int64_t base = beg; base < end; base += 64) {
+    const int64_t e = base + lane;
+    int32_t col = -1;
+    float v = 0.f;
+    if (e < end) {
+      col = colidx[e];
+      if (slot != nullptr && slot[col] < 0) col = -1;
+      if (col >= 0) v = vals[e];
+    }
+    unsigned long long mask = __ballot(col >= 0);
+    while (mask != 0ull) {
+      const int b = __ffsll(mask) - 1;
+      mask &= mask - 1ull;
+      const int32_t c = __shfl(col, b, 64);
+      const float x = __shfl(v, b, 64);
+      const float* w = W + (int64_t)c * k;
+      if (lane < k) a0 += x * w[lane];
+      if (lane + 64 < k) a1 += x * w[lane + 64];
+    }
+  }
+  float* r = R + row * k;
+  if (lane < k) r[lane] = scale * a0;
+  if (lane + 64 < k) r[lane + 64] = scale * a1;
+}
+
+constexpr int kCrossBlocks = 2048;
+
+// Per wave, rows i = wave_id, wave_id + total_waves, ...: (M V)_i is
+// accumulated across the lanes, dotted with u_i, and added (compensated)
+// to the wave's running sum; sum of M_ij^2 alongside.  Partials: four
+// floats per block (cross sum, comp, square sum, comp).
+__global__ __launch_bounds__(256) void csr_cross_kernel(const int64_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ colidx,
+                                                        const float* __restrict__ vals,
+                                                        int64_t rows, const float* __restrict__ U,
+                                                        const float* __restrict__ V, int k,
+                                                        float* __restrict__ partials) {
+  __shared__ float red[4 * 4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  float cs = 0.f, cc = 0.f, qs = 0.f, qc = 0.f;
+  for (int64_t row = blockIdx.x * 4ll + wave; row < rows; row += nw) {
+    const int64_t beg = rowptr[row], end = rowptr[row + 1];
+    float a0 = 0.f, a1 = 0.f, sq = 0.f, sqc = 0.f;
+    for (int64_t base = beg; base < end; base += 64) {
+      const int64_t e = base + lane;
+      int32_t col = 0;
+      float v = 0.f;
+      if (e < end) {
+        col = colidx[e];
+        v = vals[e];
+      }
+      neumaier(sq, sqc, v * v);
+      const int cnt = static_cast<int>(end - base < 64 ? end - base : 64);
+      for (int b = 0; b < cnt; ++b) {
+        const int32_t c = __shfl(col, b, 64);
+        const float x = __shfl(v, b, 64);
+        const float* w = V + (int64_t)c * k;
+        if (lane < k) a0 += x * w[lane];
+        if (lane + 64 < k) a1 += x * w[lane + 64];
+      }
+    }
+    const float* u = U + row * k;
+    float dot = 0.f;
+    if (lane < k) dot += u[lane] * a0;
+    if (lane + 64 < k) dot += u[lane + 64] * a1;
+    for (int off = 32; off > 0; off >>= 1) dot += __shfl_down(dot, off, 64);
+    for (int off = 32; off > 0; off >>= 1) {
+      const float os = __shfl_down(sq, off, 64), oc = __shfl_down(sqc, off, 64);
+      neumaier(sq, sqc, os);
+      sqc += oc;
+    }
+    if (lane == 0) {
+      neumaier(cs, cc, dot);
+      neumaier(qs, qc, sq);
+      qc += sqc;
+    }
+  }
+  if (lane == 0) {
+    red[4 * wave] = cs;
+    red[4 * wave + 1] = cc;
+    red[4 * wave + 2] = qs;
+    red[4 * wave + 3] = qc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float a = red[0], ac = red[1], b = red[2], bc = red[3];
+    for (int w = 1; w < 4; ++w) {
+      neumaier(a, ac, red[4 * w]);
+      ac += red[4 * w + 1];
+      neumaier(b, bc, red[4 * w + 2]);
+      bc += red[4 * w + 3];
+    }
+    partials[4 * blockIdx.x] = a;
+    partials[4 * blockIdx.x + 1] = ac;
+    partials[4 * blockIdx.x + 2] = b;
+    partials[4 * blockIdx.x + 3] = bc;
+  }
+}
+
+}  // namespace
+
+dsanls_status launch_csr_sketch_rhs(const int64_t* rowptr, const int32_t* colidx, const float* vals,
+                                    int64_t rows, const int32_t* slot, const float* W, int64_t k,
+                                    float scale, float* R, hipStream_t s) {
+  if (rows <= 0) return DSANLS_OK;
+  if (k > 128) return fail(DSANLS_E_UNSUPPORTED, "CSR path supports k <= 128");
+  csr_rhs_kernel<<<static_cast<unsigned>(ceil_div(rows, 4)), 256, 0, s>>>(
+      rowptr, colidx, vals, rows, slot, W, static_cast<int>(k), scale, R);
+  DSANLS_LAUNCHED("csr_rhs_kernel");
+  return DSANLS_OK;
+}
+
+int64_t csr_cross_partials(int64_t) { return kCrossBlocks; }
+
+dsanls_status launch_csr_cross(const int64_t* rowptr, const int32_t* colidx, const float* vals,
+                               int64_t rows, const float* U, const float* V, int64_t k,
+                               float* partials, hipStream_t s) {
+  if (k > 128) return fail(DSANLS_E_UNSUPPORTED, "CSR path supports k <= 128");
+  csr_cross_kernel<<<kCrossBlocks, 256, 0, s>>>(rowptr, colidx, vals, rows, U, V,
+                                                static_cast<int>(k), partials);
+  DSANLS_LAUNCHED("csr_cross_kernel");
+  return DSANLS_OK;
+}
+
+}  // namespace dsanls

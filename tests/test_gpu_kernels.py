@@ -1,0 +1,162 @@
+"""GPU parity of the stand-alone kernels against the FP64 oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+from oracle import dsanls as O
+from oracle import philox as P
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = np.finfo(np.float32).eps
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_02845_amd import binding
+    binding.load()
+    return torch, binding
+
+
+def test_philox_bit_exact(torch_dev):
+    torch, B = torch_dev
+    g = np.random.default_rng(0)
+    cnt = 10000
+    ctr = g.integers(0, 2 ** 32, size=(cnt, 4), dtype=np.uint64)
+    key = g.integers(0, 2 ** 32, size=(cnt, 2), dtype=np.uint64)
+    ctr[0] = 0
+    key[0] = 0
+    ctr[1] = 0xFFFFFFFF
+    key[1] = 0xFFFFFFFF
+    out = B.philox4x32_10(torch.from_numpy(ctr.astype(np.uint32).view(np.int32)).cuda(),
+                          torch.from_numpy(key.astype(np.uint32).view(np.int32)).cuda())
+    got = out.cpu().numpy().view(np.uint32).astype(np.uint64)
+    ref = np.stack(P.philox4x32(ctr[:, 0], ctr[:, 1], ctr[:, 2], ctr[:, 3], key[:, 0], key[:, 1]), axis=1)
+    assert np.array_equal(got, ref)
+    assert [hex(int(x)) for x in got[0]] == ["0x6627e8d5", "0xe169c58d", "0xbc57ac4c", "0x9b00dbd8"]
+
+
+@pytest.mark.parametrize("n,d,side,t", [(150, 40, 0, 0), (200, 40, 1, 7), (1000, 37, 0, 3), (3, 1, 1, 9)])
+def test_gaussian_sketch_matches_oracle(torch_dev, n, d, side, t):
+    torch, B = torch_dev
+    St = B.gaussian_sketch_t(12345, t, side, n, d).cpu().numpy()
+    ref = P.gaussian_sketch(12345, t, side, n, d).T
+    # same Philox words; FP32 log/sqrt/sincospi vs FP64: a few ulp of the value
+    assert np.max(np.abs(St - ref)) <= 1e-6 * max(1.0, np.max(np.abs(ref))) * 8
+
+
+@pytest.mark.parametrize("n,d", [(10, 3), (257, 40), (1000, 1000), (64, 1), (200000, 2000), (500000, 2000),
+                                 (70000, 7000)])
+def test_subsample_indices_exact(torch_dev, n, d):
+    torch, B = torch_dev
+    for side, t in ((0, 0), (1, 5)):
+        idx = B.subsample_indices(99, t, side, n, d).cpu().numpy()
+        ref = P.subsample_indices(99, t, side, n, d)
+        assert np.array_equal(idx, ref)
+
+
+def _gemm_check(X, Y, C):
+    ref = X.astype(np.float64) @ Y.astype(np.float64).T
+    K = X.shape[1]
+    bound = 2 * EPS32 * max(K, 1) * (np.abs(X).astype(np.float64) @ np.abs(Y).astype(np.float64).T) + 1e-30
+    assert np.all(np.abs(C - ref) <= bound)
+    if np.linalg.norm(ref) > 0:
+        assert np.linalg.norm(C - ref) / np.linalg.norm(ref) < 1e-5
+
+
+@pytest.mark.parametrize("rows,cols,K", [(1, 1, 1), (200, 40, 150), (257, 130, 1001), (64, 1024, 10000),
+                                         (3000, 64, 1024), (128, 128, 32), (129, 129, 33), (500, 700, 0),
+                                         (10, 600, 5000)])
+def test_gemm_nt_matches_fp64(torch_dev, rows, cols, K):
+    torch, B = torch_dev
+    g = np.random.default_rng(rows + cols + K)
+    X = g.standard_normal((rows, K)).astype(np.float32)
+    Y = g.standard_normal((cols, K)).astype(np.float32)
+    C = B.gemm_nt(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()).cpu().numpy()
+    if K == 0:
+        assert np.all(C == 0)
+    else:
+        _gemm_check(X, Y, C)
+
+
+def test_gemm_nt_unaligned_leading_dimension(torch_dev):
+    torch, B = torch_dev
+    g = np.random.default_rng(1)
+    Xf = g.random((300, 151)).astype(np.float32)
+    Yf = g.random((77, 151)).astype(np.float32)
+    X = torch.from_numpy(Xf).cuda()[:, 1:150]      # ld 151, offset 1: no vector loads
+    Y = torch.from_numpy(Yf).cuda()[:, 1:150]
+    C = B.gemm_nt(X, Y).cpu().numpy()
+    _gemm_check(Xf[:, 1:150], Yf[:, 1:150], C)
+
+
+def _nnls_problem(rows, k, d, seed, mu_scale=1.0):
+    g = np.random.default_rng(seed)
+    Bm = g.standard_normal((k, d)) / np.sqrt(d)
+    A = g.standard_normal((rows, d)) + 0.3
+    G, R = Bm @ Bm.T, A @ Bm.T
+    U0 = g.random((rows, k))
+    return G.astype(np.float32), R.astype(np.float32), U0.astype(np.float32)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+@pytest.mark.parametrize("k", [1, 3, 4, 10, 16, 33, 64, 100, 128])
+@pytest.mark.parametrize("sweeps", [1, 3])
+def test_prox_cd_matches_oracle(torch_dev, k, sweeps):
+    torch, B = torch_dev
+    rows, mu = 1000 + 37, 0.7
+    G, R, U0 = _nnls_problem(rows, k, 3 * k + 5, k)
+    U = torch.from_numpy(U0.copy()).cuda()
+    B.nnls_prox_cd(torch.from_numpy(G).cuda(), torch.from_numpy(R).cuda(), U.clone(), U, mu, sweeps=sweeps)
+    ref, _ = O.prox_cd_solve(U0.astype(np.float64), U0.astype(np.float64), G.astype(np.float64),
+                             R.astype(np.float64), mu, sweeps)
+    assert _rel(U.cpu().numpy(), ref) < 1e-4
+    assert U.min().item() >= 0
+
+
+@pytest.mark.parametrize("k", [4, 10, 64, 100])
+def test_prox_cd_to_tolerance(torch_dev, k):
+    torch, B = torch_dev
+    rows, mu = 513, 2.0
+    G, R, U0 = _nnls_problem(rows, k, 3 * k + 5, 100 + k)
+    U = torch.from_numpy(U0.copy()).cuda()
+    used = B.nnls_prox_cd(torch.from_numpy(G).cuda(), torch.from_numpy(R).cuda(), U.clone(), U, mu,
+                          sweeps=0, tol=1e-5, max_sweeps=500, want_sweeps=True)
+    Ud = U.cpu().numpy().astype(np.float64)
+    G64, R64, C64 = G.astype(np.float64), R.astype(np.float64), U0.astype(np.float64)
+    exact, _ = O.prox_cd_solve(C64, C64, G64, R64, mu, 0, tol=1e-13, max_sweeps=20000)
+    assert _rel(Ud, exact) < 1e-3
+    assert np.max(O.kkt_residual(Ud, C64, G64, R64, mu)) < 5e-5
+    _, ref_used = O.prox_cd_solve(C64, C64, G64, R64, mu, 0, tol=1e-5, max_sweeps=500)
+    u = used.cpu().numpy()
+    assert np.all(u >= 1) and abs(u.mean() - ref_used.mean()) <= 1.0
+
+
+@pytest.mark.parametrize("k", [1, 10, 64, 100, 128])
+def test_pgd_matches_oracle(torch_dev, k):
+    torch, B = torch_dev
+    rows, mu = 777, 1.5
+    G, R, U0 = _nnls_problem(rows, k, 2 * k + 3, 7 + k)
+    U = torch.from_numpy(U0.copy()).cuda()
+    B.pgd_step(torch.from_numpy(G).cuda(), torch.from_numpy(R).cuda(), U, mu)
+    G64 = G.astype(np.float64)
+    ref = O.pgd_step(U0.astype(np.float64), G64, R.astype(np.float64), O.pgd_step_size(G64, mu))
+    assert _rel(U.cpu().numpy(), ref) < 1e-5
+
+
+def test_prox_cd_upper_clip_and_empty(torch_dev):
+    torch, B = torch_dev
+    G, R, U0 = _nnls_problem(64, 8, 20, 3)
+    U = torch.from_numpy(U0.copy()).cuda()
+    B.nnls_prox_cd(torch.from_numpy(G).cuda(), torch.from_numpy(R * 100).cuda(), U.clone(), U, 0.5,
+                   upper=0.25)
+    ref, _ = O.prox_cd_solve(U0.astype(np.float64), U0.astype(np.float64), G.astype(np.float64),
+                             (R * 100).astype(np.float64), 0.5, 1, upper=0.25)
+    assert U.max().item() <= 0.25 and _rel(U.cpu().numpy(), ref) < 1e-4
+    E = torch.empty((0, 8), dtype=torch.float32, device="cuda")
+    B.nnls_prox_cd(torch.from_numpy(G).cuda(), E, E, E, 0.5)
