@@ -41,11 +41,18 @@ WORKLOADS = {
     "dense-50000x20000-bf16": dict(kind="dense", m=50000, n=20000, k=128, d=4096, iters=30,
                                    solver="prox_cd", gen="planted", noise=0.01, noise_relative=True,
                                    precision="bf16"),
+    # text-shaped CSR row block, subsampling sketch (columns sampled and scaled)
+    "sparse-500000x200000": dict(kind="sparse", m=500000, n=200000, k=100, d=2000, iters=30,
+                                 solver="prox_cd", nnz=100_000_000, precision="fp32"),
 }
 DEFAULT = "dense-20000x10000"
 
 
 def describe(name, w):
+    if w["kind"] == "sparse":
+        return (f"CSR {w['m']}x{w['n']}, {w['nnz']:.0e} nnz, power-law rows (alpha=1.5), Zipf(1.1) "
+                f"columns, lognormal values, k={w['k']}, subsampling sketch d=d'={w['d']}, "
+                f"prox-CD 1 sweep, FP32, {w['iters']} iterations")
     if w["kind"] == "dense":
         gen = ("uniform[0,1)" if w["gen"] == "uniform" else
                f"planted rank-{w['k']} |N(0,1)| factors + noise")
@@ -66,7 +73,19 @@ def make_dense(w, seed=0):
     return M, U0, V0
 
 
-def cpu_baseline(w, M, U0, V0, budget_s=12.0, max_iters=5):
+def make_sparse(w, seed=0):
+    import scipy.sparse as sp
+    from paper_2009_02845_amd import synth
+    m, n, k = w["m"], w["n"], w["k"]
+    rp, ci, v = synth.sparse_text(m, n, w["nnz"], seed)
+    M = sp.csr_matrix((v, ci, rp), shape=(m, n))
+    Mt = M.T.tocsr()
+    Mt.sort_indices()
+    U0, V0 = synth.init_factors(m, n, k, seed)
+    return M, Mt, U0, V0
+
+
+def cpu_baseline(w, M, U0, V0, budget_s=12.0, max_iters=5, Mt=None):
     """The FP64 oracle, untuned, timed on the host's cores over whole iterations."""
     from oracle import dsanls as O
     try:
@@ -75,13 +94,15 @@ def cpu_baseline(w, M, U0, V0, budget_s=12.0, max_iters=5):
         cores = max([i.get("num_threads", 1) for i in info] + [1])
     except Exception:
         cores = os.cpu_count() or 1
-    cfg = O.Config(k=w["k"], d=w["d"], d_prime=w["d"], sketch=O.SKETCH_GAUSSIAN, solver=w["solver"])
+    sketch = O.SKETCH_SUBSAMPLE if w["kind"] == "sparse" else O.SKETCH_GAUSSIAN
+    cfg = O.Config(k=w["k"], d=w["d"], d_prime=w["d"], sketch=sketch, solver=w["solver"])
     M64 = M.astype(np.float64)
+    Mt64 = Mt.astype(np.float64) if Mt is not None else None
     U, V = U0.astype(np.float64), V0.astype(np.float64)
     done, t0 = 0, time.perf_counter()
     while done < max_iters:
         U = O.update_U(M64, U, V, done, cfg)
-        V = O.update_V(M64, U, V, done, cfg)
+        V = O.update_V(M64, U, V, done, cfg, Mt=Mt64)
         done += 1
         if time.perf_counter() - t0 >= budget_s:
             break
@@ -89,6 +110,30 @@ def cpu_baseline(w, M, U0, V0, budget_s=12.0, max_iters=5):
     return {"value": done / el, "unit": "iterations/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{done} full iterations (t=0..{done - 1}) of the same workload in FP64 numpy, "
                       f"{el:.1f} s"}
+
+
+def sparse_roofline(w, M, tm, launches):
+    """Roofline of the dominant sparse phase: the NNLS sweep (VALU) or the
+    CSR sketch right-hand side (HBM), whichever takes longer."""
+    m, n, k, d = w["m"], w["n"], w["k"], w["d"]
+    nnz = M.nnz
+    half = launches // 2
+    nnls_avg = tm["nnls_ms"] / 1e3 / launches
+    prod_avg = tm["product_ms"] / 1e3 / launches
+    if nnls_avg >= prod_avg:
+        flops = 2.0 * k * k * (m + n) / 2      # k^2 FMAs per row-sweep, mean over the two sides
+        ach = flops / nnls_avg / 1e12
+        peak = PEAK["fp32_valu_tflops"]
+        return {"kernel": "prox-CD sweep (prox_cd_kernel)", "bound": "alu", "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None, "flops_per_launch": flops,
+                "avg_launch_ms": nnls_avg * 1e3}
+    # CSR stream: column indices of every nnz + row pointers + R written
+    layout = (4.0 * nnz + 8.0 * (m + 1) + 4.0 * k * m + 4.0 * nnz + 8.0 * (n + 1) + 4.0 * k * n) / 2
+    ach = layout / prod_avg / 1e9
+    peak = PEAK["hbm_gbs"]
+    return {"kernel": "CSR sketch right-hand side (csr_rhs_kernel)", "bound": "hbm", "achieved": ach,
+            "peak": peak, "unit": "GB/s", "frac": ach / peak, "traffic": None, "bytes_per_launch": layout,
+            "avg_launch_ms": prod_avg * 1e3, "launches_per_side": half}
 
 
 def main():
@@ -115,15 +160,27 @@ def main():
     K = args.steps if args.steps is not None else w["iters"]
     W = args.warmup
     print(f"[bench] workload {args.workload}: generating data", file=sys.stderr, flush=True)
-    M, U0, V0 = make_dense(w, args.seed)
     m, n, k, d = w["m"], w["n"], w["k"], w["d"]
     dev = torch.device("cuda", 0)
-    Md = torch.from_numpy(M).to(dev)
+    Mt = None
+    if w["kind"] == "dense":
+        M, U0, V0 = make_dense(w, args.seed)
+        Md = torch.from_numpy(M).to(dev)
+        keep = [Md]
+        mat = B.dense_matrix(Md)
+        sketch = "gaussian"
+    else:
+        M, Mt, U0, V0 = make_sparse(w, args.seed)
+        to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a.astype(dt))).to(dev)
+        keep = [to(M.indptr, np.int64), to(M.indices, np.int32), to(M.data, np.float32),
+                to(Mt.indptr, np.int64), to(Mt.indices, np.int32), to(Mt.data, np.float32)]
+        mat = B.csr_matrix(*keep)
+        sketch = "subsample"
     U0d, V0d = torch.from_numpy(U0).to(dev), torch.from_numpy(V0).to(dev)
     U, V = U0d.clone(), V0d.clone()
-    cfg = B.make_config(m, n, k, d, d, sketch="gaussian", solver=w["solver"], precision=w["precision"],
+    cfg = B.make_config(m, n, k, d, d, sketch=sketch, solver=w["solver"], precision=w["precision"],
                         sweeps=1, alpha=1.0, beta=1.0, seed=0)
-    solver = B.Solver(cfg, B.dense_matrix(Md), U, V, tensors=[Md])
+    solver = B.Solver(cfg, mat, U, V, tensors=keep)
     print(f"[bench] warmup {W} iterations", file=sys.stderr, flush=True)
     for t in range(W):
         solver.iteration(t)
@@ -144,10 +201,16 @@ def main():
     rel = solver.objective()
     its = K / el
     launches = 2 * K
-    prod_avg_s = tm["product_ms"] / 1e3 / launches
-    flops_launch = 2.0 * m * n * d          # A = M S (m x n x d) and A' = M^T S' (n x m x d')
-    peak = PEAK["bf16_mfma_tflops"] if w["precision"] == "bf16" else PEAK["fp32_mfma_tflops"]
-    achieved = flops_launch / prod_avg_s / 1e12
+    if w["kind"] == "dense":
+        prod_avg_s = tm["product_ms"] / 1e3 / launches
+        flops_launch = 2.0 * m * n * d      # A = M S (m x n x d) and A' = M^T S' (n x m x d')
+        peak = PEAK["bf16_mfma_tflops"] if w["precision"] == "bf16" else PEAK["fp32_mfma_tflops"]
+        achieved = flops_launch / prod_avg_s / 1e12
+        roof = {"kernel": "sketch GEMM A = M S (gemm_nt_kernel)", "bound": "mfma", "achieved": achieved,
+                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "flops_per_launch": flops_launch, "avg_launch_ms": prod_avg_s * 1e3}
+    else:
+        roof = sparse_roofline(w, M, tm, launches)
     out = {
         "metric": "sketched-ANLS iterations/s (and NNLS rows/s) to a fixed relative objective",
         "value": its,
@@ -166,14 +229,14 @@ def main():
         "rel_objective": rel,
         "nnls_rows_per_s": (m + n) * K / (tm["nnls_ms"] / 1e3) if tm["nnls_ms"] > 0 else None,
         "phase_ms_per_step": {p: tm[p + "_ms"] / K for p in ("sketch", "product", "small", "nnls")},
-        "roofline": {"kernel": "sketch GEMM A = M S (gemm_nt_kernel)", "bound": "mfma",
-                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None,
-                     "flops_per_launch": flops_launch, "avg_launch_ms": prod_avg_s * 1e3},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, M, U0, V0)
+        if w["kind"] == "sparse":
+            out["cpu_baseline"] = cpu_baseline(w, M, U0, V0, budget_s=1.0, max_iters=1, Mt=Mt)
+        else:
+            out["cpu_baseline"] = cpu_baseline(w, M, U0, V0)
     solver.close()
     print(json.dumps(out), flush=True)
 

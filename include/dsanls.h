@@ -220,6 +220,13 @@ dsanls_status dsanls_gemm_nt(const float* X, int64_t ldx, const float* Y, int64_
                              int64_t ldc, int64_t rows, int64_t cols, int64_t K, void* workspace,
                              size_t workspace_bytes, void* hip_stream);
 
+/* C = X Y^T with BF16 operands (raw bfloat16 bit patterns, rows x K and
+ * cols x K, row-major) and FP32 accumulation on MFMA; C is FP32 rows x cols.
+ * The precision form of the sketch product A = M S. */
+dsanls_status dsanls_gemm_nt_bf16(const void* X, int64_t ldx, const void* Y, int64_t ldy, float* C,
+                                  int64_t ldc, int64_t rows, int64_t cols, int64_t K,
+                                  void* hip_stream);
+
 /* Batched row-wise NNLS of the regularised sketched subproblem (eq. reg_sub):
  * for every row i of U (rows x k, in place), starting from U[i] and with
  * proximal centre C[i] (C may equal U), run prox-CD sweeps (Alg. 3) on

@@ -32,6 +32,7 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
+from . import bf16 as _bf16
 from . import philox
 
 SKETCH_GAUSSIAN = "gaussian"
@@ -55,6 +56,7 @@ class Config:
     max_sweeps: int = 100
     clip_upper: bool = False   # optional box of eq. extra_con
     seed: int = 0
+    precision: str = "fp32"    # "bf16": M and S rounded to bfloat16 for A = M S
 
 
 def mu_t(cfg, t):
@@ -231,7 +233,14 @@ def half_iteration(Mx, X, W, t, side, d, cfg, upper=None, rows=None):
     S = sketch_matrix(cfg.sketch, cfg.seed, t, side, n_long, d)
     Msub = Mx if rows is None else Mx[rows]
     Xsub = X if rows is None else X[rows]
-    A, B = sketch_products(Msub, W, S)
+    if cfg.precision == "bf16" and not sp.issparse(S):
+        # precision form: the sketch and M enter the products as bfloat16
+        # values; the products themselves are exact here (FP64)
+        S = _bf16.round_to_bf16(S)
+        A = _bf16.round_to_bf16(Msub) @ S
+        B = W.T @ S
+    else:
+        A, B = sketch_products(Msub, W, S)
     G, R = gram_and_rhs(A, B)
     return solve_subproblem(Xsub, G, R, mu_t(cfg, t), cfg, upper)
 
@@ -241,9 +250,12 @@ def update_U(M, U, V, t, cfg, upper=None, rows=None):
     return half_iteration(M, U, V, t, 0, cfg.d, cfg, upper, rows)
 
 
-def update_V(M, U, V, t, cfg, upper=None, rows=None):
-    """V^{t+1} from M^T, V^t and the current U (= U^{t+1}, Alg. 1)."""
-    Mt = M.T.tocsr() if sp.issparse(M) else M.T
+def update_V(M, U, V, t, cfg, upper=None, rows=None, Mt=None):
+    """V^{t+1} from M^T, V^t and the current U (= U^{t+1}, Alg. 1).
+
+    Mt, if given, is M^T already formed (a caller's cache; same values)."""
+    if Mt is None:
+        Mt = M.T.tocsr() if sp.issparse(M) else M.T
     return half_iteration(Mt, V, U, t, 1, cfg.d_prime, cfg, upper, rows)
 
 

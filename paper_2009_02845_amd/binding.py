@@ -79,6 +79,8 @@ _SIGS = {
     "dsanls_gemm_workspace_bytes": (c_size_t, [c_int64, c_int64, c_int64]),
     "dsanls_gemm_nt": (c_int32, [c_vp, c_int64, c_vp, c_int64, c_vp, c_int64, c_int64, c_int64, c_int64, c_vp,
                                  c_size_t, c_vp]),
+    "dsanls_gemm_nt_bf16": (c_int32, [c_vp, c_int64, c_vp, c_int64, c_vp, c_int64, c_int64, c_int64, c_int64,
+                                      c_vp]),
     "dsanls_nnls_workspace_bytes": (c_size_t, [c_int32]),
     "dsanls_nnls_prox_cd": (c_int32, [c_vp, c_vp, c_vp, c_vp, c_int64, c_int32, c_float, c_int32, c_float,
                                       c_int32, c_float, c_vp, c_vp, c_size_t, c_vp]),
@@ -267,6 +269,18 @@ def gemm_nt(X, Y, out=None, stream=None):
     ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=X.device) if nb else None
     _check("dsanls_gemm_nt", lib.dsanls_gemm_nt(_ptr(X), X.stride(0), _ptr(Y), Y.stride(0), _ptr(C), C.stride(0),
                                                 rows, cols, K, _ptr(ws), nb, _stream(stream)))
+    return C
+
+
+def gemm_nt_bf16(X, Y, stream=None):
+    """C = X Y^T (FP32) for torch.bfloat16 device tensors X (rows x K), Y (cols x K)."""
+    import torch
+    lib = load()
+    rows, K = X.shape
+    cols = Y.shape[0]
+    C = torch.empty((rows, cols), dtype=torch.float32, device=X.device)
+    _check("dsanls_gemm_nt_bf16", lib.dsanls_gemm_nt_bf16(_ptr(X), X.stride(0), _ptr(Y), Y.stride(0), _ptr(C),
+                                                          C.stride(0), rows, cols, K, _stream(stream)))
     return C
 
 

@@ -38,9 +38,9 @@ struct Layout {
   __hip_bfloat16* Mb = nullptr;     // m x ldmb (BF16 copy of M)
   __hip_bfloat16* Mtb = nullptr;    // n x ldmtb
   int64_t ldmb = 0, ldmtb = 0;
-  float* St = nullptr;              // d x lds, sketch transposed
-  __hip_bfloat16* Sb = nullptr;     // d x ldsb
-  float* A = nullptr;               // rows x lda
+  float* St[2] = {nullptr, nullptr};            // per side: d x lds, sketch transposed
+  __hip_bfloat16* Sb[2] = {nullptr, nullptr};   // per side: d x ldsb (BF16 form)
+  float* A[2] = {nullptr, nullptr};             // per side: rows x lda
   float* Wt = nullptr;              // k x ldw, fixed factor transposed
   float* B = nullptr;               // k x ldb
   float* G = nullptr;               // k x k
@@ -87,11 +87,16 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
     L.Mb = reinterpret_cast<__hip_bfloat16*>(take(2 * m * L.ldmb));
     L.Mtb = reinterpret_cast<__hip_bfloat16*>(take(2 * n * L.ldmtb));
   }
-  if (gauss) {
-    L.St = reinterpret_cast<float*>(take(sizeof(float) * dmax * r4(lngmax)));
-    if (bf16) L.Sb = reinterpret_cast<__hip_bfloat16*>(take(2 * dmax * r8(lngmax)));
+  // Side 0 (U-subproblem): S is n x d, A is m x d; side 1: S' is m x d', A' is n x d'.
+  const int64_t side_rows[2] = {m, n}, side_lng[2] = {n, m}, side_d[2] = {c.d, c.d_prime};
+  for (int sd = 0; sd < 2; ++sd) {
+    if (gauss) {
+      L.St[sd] = reinterpret_cast<float*>(take(sizeof(float) * side_d[sd] * r4(side_lng[sd])));
+      if (bf16) L.Sb[sd] = reinterpret_cast<__hip_bfloat16*>(take(2 * side_d[sd] * r8(side_lng[sd])));
+    }
+    if (is_dense && (gauss || sub))
+      L.A[sd] = reinterpret_cast<float*>(take(sizeof(float) * side_rows[sd] * r4(side_d[sd])));
   }
-  if (is_dense && (gauss || sub)) L.A = reinterpret_cast<float*>(take(sizeof(float) * rowsmax * r4(dmax)));
   L.Wt = reinterpret_cast<float*>(take(sizeof(float) * k * r4(lngmax)));
   L.B = reinterpret_cast<float*>(take(sizeof(float) * k * r4(dmax)));
   L.G = reinterpret_cast<float*>(take(sizeof(float) * k * k));
@@ -190,6 +195,9 @@ struct dsanls_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev[4];
   int64_t timed_updates = 0;
+  // outer iteration whose V-side sketch product A' = M^T S'^t is already in
+  // A[1] (computed together with the U side), or -1
+  int64_t lookahead_t = -1;
   ~dsanls_ctx() {
     for (auto& v : ev)
       for (hipEvent_t e : v) (void)hipEventDestroy(e);
@@ -234,14 +242,12 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
   const float* Wother = side == 0 ? ctx->V : ctx->U;
   const float* X = side == 0 ? ctx->mat.dense : ctx->Mt;
   const int64_t ldx = side == 0 ? ctx->mat.ld : ctx->ldmt;
-  const __hip_bfloat16* Xb = side == 0 ? L.Mb : L.Mtb;
-  const int64_t ldxb = side == 0 ? L.ldmb : L.ldmtb;
   const int64_t* rowptr = side == 0 ? ctx->mat.rowptr : ctx->mat.t_rowptr;
   const int32_t* colidx = side == 0 ? ctx->mat.colidx : ctx->mat.t_colidx;
   const float* vals = side == 0 ? ctx->mat.vals : ctx->mat.t_vals;
   const uint32_t tt = static_cast<uint32_t>(t);
   const double mu = c.alpha + c.beta * static_cast<double>(t);
-  const int64_t lds = r4(lng), ldsb = r8(lng), lda = r4(d), ldb = r4(d), ldw = r4(lng);
+  const int64_t lds = r4(lng), lda = r4(d), ldb = r4(d), ldw = r4(lng);
   dsanls_status st = DSANLS_OK;
 #define CHECK(x)                      \
   do {                                \
@@ -250,24 +256,43 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
 
   const float* Bp = L.B;
   int64_t Bld = ldb, Bk = d;   // B is k x Bk with leading dimension Bld
-  const float* Ap = L.A;
+  const float* Ap = L.A[side];
   int64_t Ald = lda;
   if (c.sketch == DSANLS_SKETCH_GAUSSIAN) {
-    // S^t transposed (d x lng) and A = X S (rows x d) on MFMA
-    CHECK(mark(ctx, kPhSketch));
-    CHECK(launch_gaussian_sketch_t(c.seed, tt, side, lng, d, L.St, lds, bf16 ? L.Sb : nullptr, s));
-    CHECK(mark(ctx, kPhSketch));
-    CHECK(mark(ctx, kPhProduct));
-    if (bf16) {
-      CHECK(launch_gemm_nt_bf16(Xb, ldxb, L.Sb, ldsb, L.A, lda, rows, d, lng, s));
-    } else {
-      CHECK(launch_gemm_nt(X, ldx, L.St, lds, L.A, lda, rows, d, lng, L.gemm_ws, L.gemm_ws_bytes, s));
+    // S^t transposed (d x lng) and A = X S (rows x d) on MFMA.  A' = M^T S'^t
+    // of the V side needs only M and t, so the U-side call draws both
+    // sketches and runs both products as one grouped launch (filling the
+    // machine with both tile sets); the V-side call of the same t reuses A'.
+    const bool both = side == 0;
+    if (both || ctx->lookahead_t != t) {
+      CHECK(mark(ctx, kPhSketch));
+      for (int sd = both ? 0 : 1; sd < 2; ++sd) {
+        const int64_t lng_s = sd == 0 ? c.n : c.m, d_s = sd == 0 ? c.d : c.d_prime;
+        CHECK(launch_gaussian_sketch_t(c.seed, tt, sd, lng_s, d_s, L.St[sd], r4(lng_s),
+                                       bf16 ? L.Sb[sd] : nullptr, s));
+      }
+      CHECK(mark(ctx, kPhSketch));
+      CHECK(mark(ctx, kPhProduct));
+      GemmDesc g[2];
+      for (int sd = 0; sd < 2; ++sd) {
+        const int64_t rows_s = sd == 0 ? c.m : c.n, lng_s = sd == 0 ? c.n : c.m;
+        const int64_t d_s = sd == 0 ? c.d : c.d_prime;
+        if (bf16)
+          g[sd] = GemmDesc{sd == 0 ? L.Mb : L.Mtb, sd == 0 ? L.ldmb : L.ldmtb, L.Sb[sd], r8(lng_s), L.A[sd],
+                           r4(d_s), rows_s, d_s, lng_s};
+        else
+          g[sd] = GemmDesc{sd == 0 ? ctx->mat.dense : ctx->Mt, sd == 0 ? ctx->mat.ld : ctx->ldmt, L.St[sd],
+                           r4(lng_s), L.A[sd], r4(d_s), rows_s, d_s, lng_s};
+      }
+      if (!both) g[0].rows = 0;
+      CHECK(launch_gemm_grouped(g[0], g[1], bf16, s));
+      CHECK(mark(ctx, kPhProduct));
+      ctx->lookahead_t = t;
     }
-    CHECK(mark(ctx, kPhProduct));
     // B = W^T S (k x d), split over the long dimension
     CHECK(mark(ctx, kPhSmall));
     CHECK(launch_transpose(Wother, k, L.Wt, ldw, lng, k, s));
-    CHECK(launch_gemm_nt(L.Wt, ldw, L.St, lds, L.B, ldb, k, d, lng, L.gemm_ws, L.gemm_ws_bytes, s));
+    CHECK(launch_gemm_nt(L.Wt, ldw, L.St[side], lds, L.B, ldb, k, d, lng, L.gemm_ws, L.gemm_ws_bytes, s));
   } else if (c.sketch == DSANLS_SKETCH_SUBSAMPLE) {
     CHECK(mark(ctx, kPhSketch));
     CHECK(launch_subsample(c.seed, tt, side, lng, d, L.idx, is_dense ? nullptr : L.slot, L.sub_ws,
@@ -276,7 +301,7 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
     if (is_dense) {
       CHECK(mark(ctx, kPhProduct));
-      CHECK(launch_gather_cols(X, ldx, L.idx, rows, d, scale, L.A, lda, s));
+      CHECK(launch_gather_cols(X, ldx, L.idx, rows, d, scale, L.A[side], lda, s));
       CHECK(mark(ctx, kPhProduct));
     }
     CHECK(mark(ctx, kPhSmall));
@@ -537,7 +562,8 @@ dsanls_status dsanls_debug_fetch(dsanls_ctx* ctx, int32_t which, void* dst, size
   };
   switch (which) {
     case 0:
-      if (c.sketch == DSANLS_SKETCH_GAUSSIAN) return copy2d(ctx->L.St, ctx->last_lds, d, lng, sizeof(float));
+      if (c.sketch == DSANLS_SKETCH_GAUSSIAN)
+        return copy2d(ctx->L.St[ctx->last_side], ctx->last_lds, d, lng, sizeof(float));
       if (c.sketch == DSANLS_SKETCH_SUBSAMPLE) return copy2d(ctx->L.idx, d, 1, d, sizeof(int32_t));
       return fail(DSANLS_E_UNSUPPORTED, "debug_fetch: identity sketch has no stored S");
     case 1:

@@ -54,6 +54,19 @@ size_t gemm_ws_bytes(int64_t rows, int64_t cols, int64_t K);
 dsanls_status launch_gemm_nt(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* C,
                              int64_t ldc, int64_t rows, int64_t cols, int64_t K, void* ws,
                              size_t ws_bytes, hipStream_t s);
+// Two independent products C = X Y^T in one launch (both K-contiguous);
+// element type FP32 or BF16 (raw bits), FP32 output.  A product with
+// rows == 0 is skipped.
+struct GemmDesc {
+  const void* X;
+  int64_t ldx;
+  const void* Y;
+  int64_t ldy;
+  float* C;
+  int64_t ldc;
+  int64_t rows, cols, K;
+};
+dsanls_status launch_gemm_grouped(const GemmDesc& a, const GemmDesc& b, bool bf16, hipStream_t s);
 // BF16 operands, FP32 accumulation.
 dsanls_status launch_gemm_nt_bf16(const __hip_bfloat16* X, int64_t ldx, const __hip_bfloat16* Y,
                                   int64_t ldy, float* C, int64_t ldc, int64_t rows, int64_t cols,

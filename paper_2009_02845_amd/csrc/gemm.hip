@@ -29,22 +29,67 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kBK = 32;
 constexpr int kLds = kBK + 4;
 
+// Workgroups are dispatched round-robin over the XCDs; give each XCD a
+// contiguous run of tiles so the tiles sharing a row block of X meet in the
+// same L2.
+__device__ __forceinline__ int xcd_remap(int wg, int ntiles) {
+  const int xcd = wg % kNumXcd, local = wg / kNumXcd;
+  const int per = ntiles / kNumXcd, rem = ntiles % kNumXcd;
+  return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
 template <int BM, int BN>
 struct TileMap {
   int row0, col0;
   __device__ TileMap(int tiles_m, int tiles_n) {
-    // Workgroups are dispatched round-robin over the XCDs; give each XCD a
-    // contiguous run of tiles so the tiles sharing a row block of X meet in
-    // the same L2.
-    const int ntiles = tiles_m * tiles_n;
-    const int wg = blockIdx.x;
-    const int xcd = wg % kNumXcd, local = wg / kNumXcd;
-    const int per = ntiles / kNumXcd, rem = ntiles % kNumXcd;
-    const int logical = xcd * per + (xcd < rem ? xcd : rem) + local;
+    const int logical = xcd_remap(blockIdx.x, tiles_m * tiles_n);
     row0 = (logical / tiles_n) * BM;
     col0 = (logical % tiles_n) * BN;
   }
 };
+
+// One of the (up to two) products of a grouped launch.
+template <typename T>
+struct Problem {
+  const T* X;
+  int64_t ldx;
+  const T* Y;
+  int64_t ldy;
+  float* C;
+  int64_t ldc;
+  int rows, cols, K, tiles_n, ntiles;
+};
+
+// Pick the problem and tile of this workgroup in a grouped launch.  Each XCD
+// (workgroup id mod 8) owns a contiguous chunk of the first product's tiles
+// followed by a contiguous chunk of the second's, so every XCD gets the same
+// share of both (the host orders the products longest-K first); grid =
+// 8 * (c0 + c1) with c = ceil(ntiles / 8), and the few surplus workgroups
+// return at once.
+template <int BM, int BN, typename T>
+__device__ __forceinline__ bool pick(const Problem<T>& p0, const Problem<T>& p1, Problem<T>& p,
+                                     int& row0, int& col0) {
+  const int wg = blockIdx.x;
+  const int xcd = wg % kNumXcd, local = wg / kNumXcd;
+  const int c0 = (p0.ntiles + kNumXcd - 1) / kNumXcd, c1 = (p1.ntiles + kNumXcd - 1) / kNumXcd;
+  int t;
+  if (local < c0) {
+    t = xcd * c0 + local;
+    if (t >= p0.ntiles) return false;
+    p = p0;
+  } else {
+    t = xcd * c1 + (local - c0);
+    if (local - c0 >= c1 || t >= p1.ntiles) return false;
+    p = p1;
+  }
+  row0 = (t / p.tiles_n) * BM;
+  col0 = (t % p.tiles_n) * BN;
+  return true;
+}
+
+inline int grouped_grid(int n0, int n1) {
+  return kNumXcd * ((n0 + kNumXcd - 1) / kNumXcd + (n1 + kNumXcd - 1) / kNumXcd);
+}
 
 template <int NV, bool VEC>
 __device__ __forceinline__ void load_stage(const float* __restrict__ P, int64_t ld, int r0,
@@ -144,6 +189,31 @@ __device__ __forceinline__ void mainloop(const float* __restrict__ X, int64_t ld
 // Row of element r of a 32x32 MFMA accumulator held by this lane.
 __device__ __forceinline__ int acc_row(int r, int lane) {
   return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+}
+
+template <int BM, int BN, bool VEC>
+__global__ __launch_bounds__(256, 2) void gemm_nt_grouped_kernel(Problem<float> p0, Problem<float> p1) {
+  __shared__ __attribute__((aligned(16))) float sX[2 * BM * kLds];
+  __shared__ __attribute__((aligned(16))) float sY[2 * BN * kLds];
+  constexpr int FM = BM / 64, FN = BN / 64;
+  int row0, col0;
+  Problem<float> p;
+  if (!pick<BM, BN>(p0, p1, p, row0, col0)) return;
+  floatx16 acc[FM][FN];
+  mainloop<BM, BN, VEC>(p.X, p.ldx, p.Y, p.ldy, p.rows, p.cols, 0, p.K, row0, col0, sX, sY, acc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = col0 + wn * (BN / 2) + j * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = row0 + wm * (BM / 2) + i * 32 + acc_row(r, lane);
+        if (row < p.rows && col < p.cols) p.C[(int64_t)row * p.ldc + col] = acc[i][j][r];
+      }
+    }
 }
 
 template <int BM, int BN, bool VEC>
@@ -257,6 +327,128 @@ __global__ __launch_bounds__(256, 2) void residual_kernel(const float* __restric
   }
 }
 
+
+// ---------------------------------------------------------------- BF16
+// A = M S with M and S rounded to BF16 (the precision form): the same
+// 2 x 2 wave layout with v_mfma_f32_32x32x16_bf16 (FP32 accumulation).
+// K advances 64 bf16 (128 bytes per row) per stage; the LDS row stride of
+// 72 bf16 (36 dwords) keeps 16-byte fragment reads conflict-free.  Lane
+// halves take k blocks 0-7 and 8-15 of each 16-wide step for both operands.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short ushortx8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBKh = 64;
+constexpr int kLdsh = kBKh + 8;
+
+template <int NV, bool VEC>
+__device__ __forceinline__ void load_stage_h(const unsigned short* __restrict__ P, int64_t ld, int r0,
+                                             int nrows, int k0, int kend, ushortx8 (&reg)[NV]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int id = v * 256 + threadIdx.x;
+    const int r = id >> 3, kq = (id & 7) * 8;
+    const int gr = r0 + r, gk = k0 + kq;
+    ushortx8 x = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (gr < nrows) {
+      const unsigned short* p = P + (int64_t)gr * ld + gk;
+      if (VEC && gk + 7 < kend) {
+        x = *reinterpret_cast<const ushortx8*>(p);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (gk + e < kend) x[e] = p[e];
+      }
+    }
+    reg[v] = x;
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void store_stage_h(unsigned short* __restrict__ s, const ushortx8 (&reg)[NV]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int id = v * 256 + threadIdx.x;
+    const int r = id >> 3, kq = (id & 7) * 8;
+    *reinterpret_cast<ushortx8*>(s + r * kLdsh + kq) = reg[v];
+  }
+}
+
+template <int BM, int BN, bool VEC>
+__global__ __launch_bounds__(256, 2) void gemm_nt_bf16_kernel(Problem<unsigned short> p0,
+                                                              Problem<unsigned short> p1) {
+  __shared__ __attribute__((aligned(16))) unsigned short sX[2 * BM * kLdsh];
+  __shared__ __attribute__((aligned(16))) unsigned short sY[2 * BN * kLdsh];
+  constexpr int FM = BM / 64, FN = BN / 64;
+  constexpr int XV = BM * kBKh / 8 / 256, YV = BN * kBKh / 8 / 256;
+  int row0, col0;
+  Problem<unsigned short> p;
+  if (!pick<BM, BN>(p0, p1, p, row0, col0)) return;
+  const unsigned short* X = p.X;
+  const unsigned short* Y = p.Y;
+  const int64_t ldx = p.ldx, ldy = p.ldy;
+  const int rows = p.rows, cols = p.cols, K = p.K;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lrow = lane & 31, lk = (lane >> 5) * 8;
+  floatx16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  if (K > 0) {
+    ushortx8 rx[XV], ry[YV];
+    load_stage_h<XV, VEC>(X, ldx, row0, rows, 0, K, rx);
+    load_stage_h<YV, VEC>(Y, ldy, col0, cols, 0, K, ry);
+    store_stage_h<XV>(sX, rx);
+    store_stage_h<YV>(sY, ry);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < K; k0 += kBKh) {
+      const bool more = k0 + kBKh < K;
+      if (more) {
+        load_stage_h<XV, VEC>(X, ldx, row0, rows, k0 + kBKh, K, rx);
+        load_stage_h<YV, VEC>(Y, ldy, col0, cols, k0 + kBKh, K, ry);
+      }
+      const unsigned short* cx = sX + buf * (BM * kLdsh);
+      const unsigned short* cy = sY + buf * (BN * kLdsh);
+#pragma unroll
+      for (int kk = 0; kk < kBKh; kk += 16) {
+        bf16x8 a[FM], b[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          a[i] = *reinterpret_cast<const bf16x8*>(cx + (wm * (BM / 2) + i * 32 + lrow) * kLdsh + kk + lk);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          b[j] = *reinterpret_cast<const bf16x8*>(cy + (wn * (BN / 2) + j * 32 + lrow) * kLdsh + kk + lk);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+      if (more) {
+        store_stage_h<XV>(sX + (buf ^ 1) * (BM * kLdsh), rx);
+        store_stage_h<YV>(sY + (buf ^ 1) * (BN * kLdsh), ry);
+      }
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = col0 + wn * (BN / 2) + j * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = row0 + wm * (BM / 2) + i * 32 + acc_row(r, lane);
+        if (row < rows && col < cols) p.C[(int64_t)row * p.ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
 template <int BM, int BN>
 dsanls_status gemm_dispatch(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* C,
                             int64_t ldc, int64_t split_stride, int rows, int cols, int K,
@@ -348,9 +540,64 @@ dsanls_status launch_residual_sq(const float* M, int64_t ldm, const float* U, co
   return DSANLS_OK;
 }
 
-dsanls_status launch_gemm_nt_bf16(const __hip_bfloat16*, int64_t, const __hip_bfloat16*, int64_t,
-                                  float*, int64_t, int64_t, int64_t, int64_t, hipStream_t) {
-  return fail(DSANLS_E_UNSUPPORTED, "bf16 gemm not built yet");
+namespace {
+
+template <typename T>
+bool make_problem(const GemmDesc& g, int elems_per_vec, Problem<T>& p, bool& vec) {
+  if (g.rows <= 0 || g.cols <= 0) {
+    p = Problem<T>{nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 1, 0};
+    return true;
+  }
+  if (g.rows > INT32_MAX || g.cols > INT32_MAX || g.K > INT32_MAX) return false;
+  const int tm = static_cast<int>(ceil_div(g.rows, 128)), tn = static_cast<int>(ceil_div(g.cols, 128));
+  p = Problem<T>{static_cast<const T*>(g.X), g.ldx, static_cast<const T*>(g.Y), g.ldy, g.C, g.ldc,
+                 static_cast<int>(g.rows), static_cast<int>(g.cols), static_cast<int>(g.K), tn, tm * tn};
+  vec = vec && (g.ldx % elems_per_vec == 0) && (g.ldy % elems_per_vec == 0) &&
+        (reinterpret_cast<uintptr_t>(g.X) % 16 == 0) && (reinterpret_cast<uintptr_t>(g.Y) % 16 == 0);
+  return true;
+}
+
+}  // namespace
+
+dsanls_status launch_gemm_grouped(const GemmDesc& a_in, const GemmDesc& b_in, bool bf16,
+                                  hipStream_t s) {
+  // longest-K product first, so each XCD starts its longest tiles first
+  const bool swap = b_in.rows > 0 && b_in.cols > 0 && b_in.K > a_in.K;
+  const GemmDesc& a = swap ? b_in : a_in;
+  const GemmDesc& b = swap ? a_in : b_in;
+  bool vec = true;
+  if (bf16) {
+    Problem<unsigned short> p0, p1;
+    if (!make_problem(a, 8, p0, vec) || !make_problem(b, 8, p1, vec))
+      return fail(DSANLS_E_SHAPE, "gemm: dimension exceeds int32");
+    if (p0.ntiles + p1.ntiles == 0) return DSANLS_OK;
+    const int grid = grouped_grid(p0.ntiles, p1.ntiles);
+    if (vec)
+      gemm_nt_bf16_kernel<128, 128, true><<<grid, 256, 0, s>>>(p0, p1);
+    else
+      gemm_nt_bf16_kernel<128, 128, false><<<grid, 256, 0, s>>>(p0, p1);
+    DSANLS_LAUNCHED("gemm_nt_bf16_kernel");
+    return DSANLS_OK;
+  }
+  Problem<float> p0, p1;
+  if (!make_problem(a, 4, p0, vec) || !make_problem(b, 4, p1, vec))
+    return fail(DSANLS_E_SHAPE, "gemm: dimension exceeds int32");
+  if (p0.ntiles + p1.ntiles == 0) return DSANLS_OK;
+  const int grid = grouped_grid(p0.ntiles, p1.ntiles);
+  if (vec)
+    gemm_nt_grouped_kernel<128, 128, true><<<grid, 256, 0, s>>>(p0, p1);
+  else
+    gemm_nt_grouped_kernel<128, 128, false><<<grid, 256, 0, s>>>(p0, p1);
+  DSANLS_LAUNCHED("gemm_nt_grouped_kernel");
+  return DSANLS_OK;
+}
+
+dsanls_status launch_gemm_nt_bf16(const __hip_bfloat16* X, int64_t ldx, const __hip_bfloat16* Y,
+                                  int64_t ldy, float* C, int64_t ldc, int64_t rows, int64_t cols,
+                                  int64_t K, hipStream_t s) {
+  const GemmDesc a{X, ldx, Y, ldy, C, ldc, rows, cols, K};
+  const GemmDesc none{nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0};
+  return launch_gemm_grouped(a, none, true, s);
 }
 
 }  // namespace dsanls
@@ -371,4 +618,16 @@ extern "C" dsanls_status dsanls_gemm_nt(const float* X, int64_t ldx, const float
     return fail(DSANLS_E_INVALID_ARG, "gemm_nt: null pointer or leading dimension too small");
   return launch_gemm_nt(X, ldx, Y, ldy, C, ldc, rows, cols, K, workspace, workspace_bytes,
                         static_cast<hipStream_t>(hip_stream));
+}
+
+extern "C" dsanls_status dsanls_gemm_nt_bf16(const void* X, int64_t ldx, const void* Y, int64_t ldy,
+                                             float* C, int64_t ldc, int64_t rows, int64_t cols,
+                                             int64_t K, void* hip_stream) {
+  if (rows < 0 || cols < 0 || K < 0) return fail(DSANLS_E_SHAPE, "gemm_nt_bf16: negative size");
+  if (rows == 0 || cols == 0) return DSANLS_OK;
+  if ((K > 0 && (!X || !Y)) || !C || ldx < K || ldy < K || ldc < cols)
+    return fail(DSANLS_E_INVALID_ARG, "gemm_nt_bf16: null pointer or leading dimension too small");
+  return launch_gemm_nt_bf16(static_cast<const __hip_bfloat16*>(X), ldx,
+                             static_cast<const __hip_bfloat16*>(Y), ldy, C, ldc, rows, cols, K,
+                             static_cast<hipStream_t>(hip_stream));
 }

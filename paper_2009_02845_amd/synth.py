@@ -66,71 +66,94 @@ def planted_dense(m, n, k, seed, noise_sd=0.0, noise_relative=False,
     return M
 
 
-def _pareto_lengths(m, target_nnz, alpha, cap, g):
-    """Row lengths L = ceil(x_min u^(-1/alpha)) capped, with x_min chosen by
-    bisection so that sum(L) is within 0.1% of target_nnz."""
-    u = g.random(m)
-    base = u ** (-1.0 / alpha)
-    lo, hi = 1e-3, float(target_nnz)
-    for _ in range(200):
-        mid = 0.5 * (lo + hi)
-        s = np.minimum(np.ceil(mid * base), cap).sum()
-        if s < target_nnz:
-            lo = mid
-        else:
-            hi = mid
-        if abs(s - target_nnz) <= 1e-3 * target_nnz:
-            break
-    return np.minimum(np.ceil(mid * base), cap).astype(np.int64)
+def _pareto_base(m, alpha, g):
+    """Pareto(alpha) shape u^(-1/alpha) of the row lengths."""
+    return g.random(m) ** (-1.0 / alpha)
+
+
+def _expected_distinct(T, p, chunk=64):
+    """E[#distinct columns] after T i.i.d. draws from p: sum_j 1 - (1 - p_j)^T."""
+    T = np.atleast_1d(np.asarray(T, dtype=np.float64))
+    lq = np.log1p(-p)
+    out = np.empty_like(T)
+    for s in range(0, T.size, chunk):
+        out[s:s + chunk] = np.sum(-np.expm1(np.outer(T[s:s + chunk], lq)), axis=1)
+    return out
 
 
 def sparse_text(m, n, nnz_target, seed, alpha=1.5, zipf_s=1.1, cap=None,
                 dtype=np.float32):
     """Text-like CSR row block (rowptr int64, colidx int32, vals float32).
 
-    * Row i asks for L_i entries, L ~ Pareto(alpha) (power-law document
-      lengths), capped at n/10, total sum(L) ~ nnz_target.
-    * Each entry's column is an i.i.d. draw from Zipf(zipf_s) over n ranks,
-      mapped to columns by a seeded permutation; repeated columns within a
-      row are merged (their values summed), so long rows come out a little
-      shorter than L_i and the realised nnz a little below the target.
-    * Values lognormal(0, 1).  Column indices are sorted within each row.
+    A bag-of-words recipe:
+    * column popularity: word ranks r = 1..n with probability proportional
+      to r^(-zipf_s) (Zipf), mapped to columns by a seeded permutation;
+    * row i is a document of T_i tokens, each an i.i.d. word draw; repeated
+      words merge into one entry whose value is the sum of the tokens'
+      lognormal(0, 1) values;
+    * the token counts are T_i = ceil(c * u_i^(-1/alpha)) (power-law document
+      lengths), capped so that no row expects more than n/10 distinct words,
+      with c set by bisection so that the expected number of distinct
+      entries, sum_i sum_j 1 - (1 - p_j)^T_i, equals nnz_target.
+    Column indices are sorted within each row.
     """
     cap = cap if cap is not None else max(1, n // 10)
-    L = _pareto_lengths(m, nnz_target, alpha, cap, rng(seed, "rows"))
     ranks_p = np.arange(1, n + 1, dtype=np.float64) ** (-zipf_s)
-    cdf = np.cumsum(ranks_p)
+    p = ranks_p / ranks_p.sum()
+    base = _pareto_base(m, alpha, rng(seed, "rows"))
+    # expected distinct count as a function of T on a log grid (monotone)
+    grid = np.unique(np.ceil(np.logspace(0, 8, 400)))
+    dist = _expected_distinct(grid, p)
+    tcap = float(np.interp(cap, dist, grid))
+    def expected_nnz(c):
+        T = np.minimum(np.ceil(c * base), tcap)
+        return float(np.sum(np.interp(T, grid, dist))), T
+    lo, hi = 1e-3, float(nnz_target)
+    for _ in range(100):
+        mid = np.sqrt(lo * hi)
+        e, T = expected_nnz(mid)
+        if e < nnz_target:
+            lo = mid
+        else:
+            hi = mid
+        if abs(e - nnz_target) <= 1e-4 * nnz_target:
+            break
+    L = T.astype(np.int64)
+    cdf = np.cumsum(p)
     cdf /= cdf[-1]
     total = int(L.sum())
     gc = rng(seed, "cols")
+    gv = rng(seed, "vals")
     perm = rng(seed, "perm").permutation(n).astype(np.int64)
-    row_of = np.repeat(np.arange(m, dtype=np.int64), L)
-    col = np.empty(total, dtype=np.int64)
-    chunk = 1 << 24
-    for s in range(0, total, chunk):
-        e = min(total, s + chunk)
-        r = np.searchsorted(cdf, gc.random(e - s), side="right")
-        col[s:e] = perm[np.minimum(r, n - 1)]
-    vals = rng(seed, "vals").lognormal(0.0, 1.0, total)
-    key = row_of * n + col
-    del row_of, col
-    order = np.argsort(key, kind="stable")
-    key = key[order]
-    vals = vals[order]
-    del order
-    first = np.ones(total, dtype=bool)
-    first[1:] = key[1:] != key[:-1]
-    grp = np.cumsum(first) - 1
-    vsum = np.zeros(int(grp[-1]) + 1 if total else 0)
-    np.add.at(vsum, grp, vals) if total < (1 << 22) else _segsum(vsum, grp, vals)
-    ukey = key[first]
-    rows = ukey // n
-    cols = (ukey % n).astype(np.int32)
     rowptr = np.zeros(m + 1, dtype=np.int64)
-    np.cumsum(np.bincount(rows, minlength=m), out=rowptr[1:])
-    return rowptr, cols, vsum.astype(dtype)
-
-
-def _segsum(out, grp, vals):
-    # grp is sorted: bincount with weights is an exact-enough segment sum
-    out[:] = np.bincount(grp, weights=vals, minlength=out.shape[0])
+    cols_out, vals_out = [], []
+    # process rows in chunks so the token arrays stay a few hundred MB
+    starts = np.concatenate([[0], np.cumsum(L)])
+    r0 = 0
+    per_chunk = 1 << 25
+    while r0 < m:
+        r1 = int(np.searchsorted(starts, starts[r0] + per_chunk, side="right")) - 1
+        r1 = max(r1, r0 + 1)
+        r1 = min(r1, m)
+        cnt = L[r0:r1]
+        tot = int(cnt.sum())
+        row_of = np.repeat(np.arange(r0, r1, dtype=np.int64), cnt)
+        r = np.searchsorted(cdf, gc.random(tot), side="right")
+        col = perm[np.minimum(r, n - 1)]
+        v = gv.lognormal(0.0, 1.0, tot)
+        key = row_of * n + col
+        order = np.argsort(key, kind="stable")
+        key, v = key[order], v[order]
+        first = np.ones(tot, dtype=bool)
+        first[1:] = key[1:] != key[:-1]
+        grp = np.cumsum(first) - 1
+        vsum = np.bincount(grp, weights=v)
+        ukey = key[first]
+        rows = ukey // n
+        rowptr[r0 + 1:r1 + 1] = np.bincount(rows - r0, minlength=r1 - r0)
+        cols_out.append((ukey % n).astype(np.int32))
+        vals_out.append(vsum.astype(dtype))
+        r0 = r1
+    np.cumsum(rowptr, out=rowptr)
+    del total
+    return rowptr, np.concatenate(cols_out), np.concatenate(vals_out)

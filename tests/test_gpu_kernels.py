@@ -160,3 +160,18 @@ def test_prox_cd_upper_clip_and_empty(torch_dev):
     assert U.max().item() <= 0.25 and _rel(U.cpu().numpy(), ref) < 1e-4
     E = torch.empty((0, 8), dtype=torch.float32, device="cuda")
     B.nnls_prox_cd(torch.from_numpy(G).cuda(), E, E, E, 0.5)
+
+
+@pytest.mark.parametrize("rows,cols,K", [(200, 40, 150), (257, 130, 1001), (300, 4096, 2048), (128, 128, 64),
+                                         (129, 65, 17)])
+def test_gemm_nt_bf16_matches_fp64(torch_dev, rows, cols, K):
+    torch, B = torch_dev
+    from oracle.bf16 import round_to_bf16
+    g = np.random.default_rng(rows * cols + K)
+    X = round_to_bf16(g.standard_normal((rows, K)))
+    Y = round_to_bf16(g.standard_normal((cols, K)))
+    Xd = torch.from_numpy(X.astype(np.float32)).to(torch.bfloat16).cuda()
+    Yd = torch.from_numpy(Y.astype(np.float32)).to(torch.bfloat16).cuda()
+    C = B.gemm_nt_bf16(Xd, Yd).cpu().numpy()
+    # bf16 x bf16 products are exact in FP32; only the FP32 accumulation rounds
+    _gemm_check(X.astype(np.float32), Y.astype(np.float32), C)

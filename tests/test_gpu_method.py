@@ -249,3 +249,52 @@ def test_sparse_subsample_fetch_indices(env):
     assert np.array_equal(prob.solver.fetch(0, (50,), "int32"), P.subsample_indices(17, 4, 0, 400, 50))
     prob.solver.update_V(4)
     assert np.array_equal(prob.solver.fetch(0, (60,), "int32"), P.subsample_indices(17, 4, 1, 500, 60))
+
+
+def test_bf16_sketch_form_per_update(env):
+    # planted 2000 x 1200 rank-16 + 1% noise, Gaussian d = 256: the BF16 form
+    # matches the oracle of the same form (M, S rounded to bfloat16, exact
+    # products) to FP32 accuracy, and its error against the plain FP64 method
+    # is reported by the bench; here it must stay small
+    m, n, k, d = 2000, 1200, 16, 256
+    M = synth.planted_dense(m, n, k, 2, noise_sd=0.01, noise_relative=True).astype(np.float64)
+    U0, V0 = synth.init_factors(m, n, k, 2, dtype=np.float64)
+    ocfg = _ocfg(k, d, d, O.SKETCH_GAUSSIAN, O.SOLVER_PROX_CD)
+    ocfg.precision = "bf16"
+    prob = Dense(env, M, U0, V0, ocfg, precision="bf16")
+    M64 = M.astype(np.float32).astype(np.float64)
+    U, V = U0.astype(np.float32).astype(np.float64), V0.astype(np.float32).astype(np.float64)
+    plain = _ocfg(k, d, d, O.SKETCH_GAUSSIAN, O.SOLVER_PROX_CD)
+    for t in range(3):
+        prob.set(U, V)
+        prob.solver.update_U(t)
+        Ug, _ = prob.get()
+        Uo = O.update_U(M64, U, V, t, ocfg)
+        assert _rel(Ug, Uo) < 1e-4
+        assert _rel(Ug, O.update_U(M64, U, V, t, plain)) < 2e-2
+        prob.set(Uo, V)
+        prob.solver.update_V(t)
+        _, Vg = prob.get()
+        Vo = O.update_V(M64, Uo, V, t, ocfg)
+        assert _rel(Vg, Vo) < 1e-4
+        U, V = Uo, Vo
+
+
+def test_lookahead_reuse_matches_separate_calls(env):
+    # update_U(t) computes the V-side sketch product too; calling update_V
+    # for another t, or twice, must still give the definition's result
+    M, U0, V0, ocfg = _c1(env, O.SOLVER_PROX_CD)
+    prob = Dense(env, M, U0, V0, ocfg)
+    M64 = M.astype(np.float32).astype(np.float64)
+    U, V = U0.astype(np.float32).astype(np.float64), V0.astype(np.float32).astype(np.float64)
+    prob.set(U, V)
+    prob.solver.update_U(4)
+    prob.solver.update_V(6)          # not the lookahead iteration
+    _, Vg = prob.get()
+    assert _rel(Vg, O.update_V(M64, prob.get()[0], V, 6, ocfg)) < 1e-4
+    prob.set(U, V)
+    prob.solver.update_V(4)          # the lookahead iteration, V-side first
+    prob.solver.update_V(4)
+    _, Vg2 = prob.get()
+    V1 = O.update_V(M64, U, V, 4, ocfg)
+    assert _rel(Vg2, O.update_V(M64, U, V1, 4, ocfg)) < 1e-4

@@ -117,3 +117,15 @@ def test_assumption1_expectation_identity(kind):
     mean = acc / trials
     sd = np.sqrt(np.maximum(acc2 / trials - mean ** 2, 1e-30) / trials)
     assert np.all(np.abs(mean - np.eye(n)) <= 5 * sd + 1e-12)
+
+
+def test_bf16_rounding_matches_torch():
+    import torch
+    from oracle.bf16 import round_to_bf16
+    g = np.random.default_rng(4)
+    x = np.concatenate([g.standard_normal(20000) * 10.0 ** g.integers(-6, 6, 20000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 3.0e38]])
+    # ties: 1 + 2^-8 rounds to 1 (even), 1 + 3 * 2^-8 rounds up
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(round_to_bf16(x), ref)
+    assert round_to_bf16(1.00390625) == 1.0 and round_to_bf16(1.01171875) == 1.015625
