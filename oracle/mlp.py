@@ -5,8 +5,11 @@ subproblem: a two-layer perceptron maps the sketched row a_i (d values,
 sparse for a subsampling sketch) and the current row u_i^t (k values) to a
 starting point for prox-CD,
     h = ReLU(a_i W1a + W1u u_i + b1)        (hidden width H)
-    y = ReLU(W2 h + b2)                     (k outputs, nonnegative)
-trained with the mean squared error against the rows' NNLS solutions and
+    y = ReLU(u_i + W2 h + b2)               (k outputs, nonnegative)
+The second layer predicts a correction to u_i^t (a residual connection from
+the input row to the output pre-activation): the cold start of the solve is
+u_i^t itself, so the network starts from it and learns what to change.
+It is trained with the mean squared error against the rows' NNLS solutions and
 the Adam optimiser (Kingma and Ba, "Adam: a method for stochastic
 optimization", ICLR 2015).  The paper has no such network; this module is
 the plain definition the GPU kernels are checked against.
@@ -25,7 +28,7 @@ def forward(p, A, U):
     """Returns (Hpre, H, Ypre, Y)."""
     Hpre = np.asarray(A @ p["W1a"]) + U @ p["W1u"].T + p["b1"]
     H = np.maximum(Hpre, 0.0)
-    Ypre = H @ p["W2"].T + p["b2"]
+    Ypre = U + H @ p["W2"].T + p["b2"]
     return Hpre, H, Ypre, np.maximum(Ypre, 0.0)
 
 

@@ -161,11 +161,13 @@ def sparse_text(m, n, nnz_target, seed, alpha=1.5, zipf_s=1.1, cap=None,
 
 def mlp_init(d, k, hidden, seed, dtype=np.float32):
     """Initial warm-start network weights: uniform in +-sqrt(6 / fan_in)
-    (He-uniform for the ReLU layers), zero biases.  W1a is d x hidden (row c
-    holds the weights of input column c), W1u hidden x k, W2 k x hidden."""
+    (He-uniform) for the first layer, a 100x smaller range for the output
+    layer (so the initial prediction is close to the input row), zero
+    biases.  W1a is d x hidden (row c holds the weights of input column c),
+    W1u hidden x k, W2 k x hidden."""
     g = rng(seed, "misc")
     lim1 = np.sqrt(6.0 / (d + k))
-    lim2 = np.sqrt(6.0 / hidden)
+    lim2 = 0.01 * np.sqrt(6.0 / hidden)
     return {"W1a": g.uniform(-lim1, lim1, (d, hidden)).astype(dtype),
             "W1u": g.uniform(-lim1, lim1, (hidden, k)).astype(dtype),
             "b1": np.zeros(hidden, dtype=dtype),
