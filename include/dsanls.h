@@ -78,6 +78,10 @@ typedef enum { DSANLS_DENSE = 0, DSANLS_CSR = 1 } dsanls_format;
  *   clip_upper nonzero clips U, V to sqrt(2 ||M||_F) (eq. extra_con).
  *   seed       key of the counter-based generator: equal seeds give equal
  *              S^t on every node (Sec. 3.3).
+ *   warm_hidden hidden width of the warm-start network that
+ *              dsanls_set_warm_start may install later (0: none); it sizes
+ *              the workspace.  Warm starts apply to CSR input with a
+ *              subsampling sketch in to-tolerance mode (sweeps = 0).
  */
 typedef struct {
   int64_t m, n, k, d, d_prime;
@@ -90,6 +94,8 @@ typedef struct {
   double tol;
   double alpha, beta;
   uint64_t seed;
+  int32_t warm_hidden;
+  int32_t reserved;
 } dsanls_config;
 
 /*
@@ -161,6 +167,33 @@ dsanls_status dsanls_objective(dsanls_ctx* ctx, double* rel_err);
 
 dsanls_status dsanls_get_stats(dsanls_ctx* ctx, dsanls_stats* out);
 
+/* Install (params != NULL) or remove (NULL) the learned warm start.  params
+ * is the packed network of the dsanls_mlp_* calls below (device memory,
+ * caller-owned, read at each update), with d = cfg.d = cfg.d_prime, k = cfg.k
+ * and hidden = cfg.warm_hidden.  With a warm start, each to-tolerance update
+ * first forms the sketched rows a_i of A = X S (CSR), runs the network on
+ * [a_i; u_i^t] for every row, starts prox-CD from its output with the
+ * proximal centre kept at u_i^t, and restarts a row from u_i^t when the
+ * warm start is not finite or does not reach tol within max_sweeps
+ * (counted in dsanls_stats.warm_fallbacks).
+ * Errors: STATE (the context cannot take a warm start), SHAPE. */
+dsanls_status dsanls_set_warm_start(dsanls_ctx* ctx, const float* params, int32_t hidden);
+
+/* Keep the sketched rows A = X S (CSR form) of every subsampling update on
+ * CSR input, for dsanls_gather_sketched_rows (used to build training pairs
+ * for the warm-start network).  Warm-start updates keep them anyway. */
+dsanls_status dsanls_set_keep_sketched_rows(dsanls_ctx* ctx, int32_t enable);
+
+/* Copy rows sel[0..nsel) (device int32, indices into the last update's
+ * rows) of the last update's sketched matrix A into a packed CSR: offsets
+ * out_rowptr[nsel + 1], column indices (sketch columns, ascending) and
+ * values, all device arrays; capacity bounds the entries.  Synchronises;
+ * *nnz (host) receives the entry count.  Errors: STATE (rows not kept),
+ * WORKSPACE (capacity too small: nothing is copied beyond the offsets). */
+dsanls_status dsanls_gather_sketched_rows(dsanls_ctx* ctx, const int32_t* sel, int64_t nsel,
+                                          int32_t* out_rowptr, int32_t* out_cols, float* out_vals,
+                                          int64_t capacity, int64_t* nnz);
+
 /* Per-phase GPU time of the updates run while timing was enabled, from HIP
  * events recorded on the context's stream around each phase:
  *   sketch   -- drawing S^t (Philox Gaussian sketch or subsample selection)
@@ -226,6 +259,40 @@ dsanls_status dsanls_gemm_nt(const float* X, int64_t ldx, const float* Y, int64_
 dsanls_status dsanls_gemm_nt_bf16(const void* X, int64_t ldx, const void* Y, int64_t ldy, float* C,
                                   int64_t ldc, int64_t rows, int64_t cols, int64_t K,
                                   void* hip_stream);
+
+/* ---- warm-start network: h = ReLU(a W1a + W1u u + b1),
+ *      y = ReLU(u + W2 h + b2) (a correction to the cold start u)
+ * Packed FP32 parameters: W1a (d x H, row c = input column c) | W1u (H x k)
+ * | b1 (H) | W2 (k x H) | b2 (k), dsanls_mlp_param_count(d, k, H) floats.
+ * A batch: a as CSR (a_rowptr[rows + 1], a_cols, a_vals; int32 offsets),
+ * and for gradients also its CSC form (c_colptr[d + 1], c_rows, c_vals);
+ * U and Y (labels) are rows x k.  All device memory. */
+int64_t dsanls_mlp_param_count(int32_t d, int32_t k, int32_t hidden);
+size_t dsanls_mlp_workspace_bytes(int32_t d, int32_t k, int32_t hidden, int64_t rows);
+/* out (rows x k) = network(a, U). */
+dsanls_status dsanls_mlp_forward(int32_t d, int32_t k, int32_t hidden, const float* params,
+                                 int64_t rows, const int32_t* a_rowptr, const int32_t* a_cols,
+                                 const float* a_vals, const float* U, float* out, void* workspace,
+                                 size_t workspace_bytes, void* hip_stream);
+/* grads (packed like params) of L = (1/rows) sum_b ||y_b - Y_b||^2; loss
+ * (device, 2 floats) receives L as a (hi, lo) pair. */
+dsanls_status dsanls_mlp_gradients(int32_t d, int32_t k, int32_t hidden, const float* params,
+                                   float* grads, int64_t rows, const int32_t* a_rowptr,
+                                   const int32_t* a_cols, const float* a_vals,
+                                   const int32_t* c_colptr, const int32_t* c_rows,
+                                   const float* c_vals, const float* U, const float* Y,
+                                   float* loss, void* workspace, size_t workspace_bytes,
+                                   void* hip_stream);
+/* gradients, then one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, step
+ * t >= 1) on params with moments adam_m, adam_v (packed like params). */
+dsanls_status dsanls_mlp_train_step(int32_t d, int32_t k, int32_t hidden, float* params,
+                                    float* grads, float* adam_m, float* adam_v, int64_t step,
+                                    float lr, int64_t rows, const int32_t* a_rowptr,
+                                    const int32_t* a_cols, const float* a_vals,
+                                    const int32_t* c_colptr, const int32_t* c_rows,
+                                    const float* c_vals, const float* U, const float* Y,
+                                    float* loss, void* workspace, size_t workspace_bytes,
+                                    void* hip_stream);
 
 /* Batched row-wise NNLS of the regularised sketched subproblem (eq. reg_sub):
  * for every row i of U (rows x k, in place), starting from U[i] and with

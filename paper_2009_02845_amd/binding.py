@@ -28,7 +28,7 @@ class Config(ctypes.Structure):
                 ("d_prime", c_int64), ("sketch", c_int32), ("solver", c_int32),
                 ("precision", c_int32), ("sweeps", c_int32), ("max_sweeps", c_int32),
                 ("clip_upper", c_int32), ("tol", c_double), ("alpha", c_double),
-                ("beta", c_double), ("seed", c_uint64)]
+                ("beta", c_double), ("seed", c_uint64), ("warm_hidden", c_int32), ("reserved", c_int32)]
 
 
 class Matrix(ctypes.Structure):
@@ -68,6 +68,19 @@ _SIGS = {
     "dsanls_debug_fetch": (c_int32, [c_vp, c_int32, c_vp, c_size_t]),
     "dsanls_set_timing": (c_int32, [c_vp, c_int32]),
     "dsanls_get_timing": (c_int32, [c_vp, ctypes.POINTER(Timing)]),
+    "dsanls_set_warm_start": (c_int32, [c_vp, c_vp, c_int32]),
+    "dsanls_set_keep_sketched_rows": (c_int32, [c_vp, c_int32]),
+    "dsanls_gather_sketched_rows": (c_int32, [c_vp, c_vp, c_int64, c_vp, c_vp, c_vp, c_int64,
+                                              ctypes.POINTER(c_int64)]),
+    "dsanls_mlp_param_count": (c_int64, [c_int32, c_int32, c_int32]),
+    "dsanls_mlp_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32, c_int64]),
+    "dsanls_mlp_forward": (c_int32, [c_int32, c_int32, c_int32, c_vp, c_int64, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                     c_vp, c_size_t, c_vp]),
+    "dsanls_mlp_gradients": (c_int32, [c_int32, c_int32, c_int32, c_vp, c_vp, c_int64, c_vp, c_vp, c_vp, c_vp,
+                                       c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size_t, c_vp]),
+    "dsanls_mlp_train_step": (c_int32, [c_int32, c_int32, c_int32, c_vp, c_vp, c_vp, c_vp, c_int64, c_float,
+                                        c_int64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                        c_size_t, c_vp]),
     "dsanls_destroy": (c_int32, [c_vp]),
     "dsanls_status_string": (ctypes.c_char_p, [c_int32]),
     "dsanls_last_error": (ctypes.c_char_p, []),
@@ -126,11 +139,12 @@ def _stream(stream=None):
 
 
 def make_config(m, n, k, d, d_prime=None, sketch="gaussian", solver="prox_cd", precision="fp32",
-                sweeps=1, max_sweeps=100, tol=1e-4, alpha=1.0, beta=1.0, clip_upper=False, seed=0):
+                sweeps=1, max_sweeps=100, tol=1e-4, alpha=1.0, beta=1.0, clip_upper=False, seed=0,
+                warm_hidden=0):
     return Config(m=m, n=n, k=k, d=d, d_prime=d if d_prime is None else d_prime,
                   sketch=SKETCH[sketch], solver=SOLVER[solver], precision=PRECISION[precision],
                   sweeps=sweeps, max_sweeps=max_sweeps, clip_upper=int(bool(clip_upper)), tol=tol,
-                  alpha=alpha, beta=beta, seed=seed)
+                  alpha=alpha, beta=beta, seed=seed, warm_hidden=warm_hidden)
 
 
 def dense_matrix(M, Mt=None):
@@ -213,6 +227,27 @@ class Solver:
         out = np.empty(shape, dtype=dtype)
         _check("dsanls_debug_fetch", self.lib.dsanls_debug_fetch(self.ctx, which, out.ctypes.data, out.nbytes))
         return out
+
+    def set_warm_start(self, params, hidden):
+        """Install a packed warm-start network (float32 device tensor), or None."""
+        self._warm = params
+        _check("dsanls_set_warm_start", self.lib.dsanls_set_warm_start(self.ctx, _ptr(params), hidden))
+
+    def keep_sketched_rows(self, enable=True):
+        _check("dsanls_set_keep_sketched_rows", self.lib.dsanls_set_keep_sketched_rows(self.ctx, int(enable)))
+
+    def gather_sketched_rows(self, sel, capacity):
+        """Sketched rows a_i of the last update for row indices sel (int32
+        device tensor): (rowptr, cols, vals) device tensors."""
+        import torch
+        n = sel.numel()
+        rp = torch.empty(n + 1, dtype=torch.int32, device=sel.device)
+        cols = torch.empty(max(capacity, 1), dtype=torch.int32, device=sel.device)
+        vals = torch.empty(max(capacity, 1), dtype=torch.float32, device=sel.device)
+        nnz = c_int64(0)
+        _check("dsanls_gather_sketched_rows", self.lib.dsanls_gather_sketched_rows(
+            self.ctx, _ptr(sel), n, _ptr(rp), _ptr(cols), _ptr(vals), capacity, ctypes.byref(nnz)))
+        return rp, cols[:nnz.value], vals[:nnz.value]
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -308,3 +343,78 @@ def pgd_step(G, R, U, mu, upper=0.0, stream=None):
     ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=U.device)
     _check("dsanls_pgd_step", lib.dsanls_pgd_step(_ptr(G), _ptr(R), _ptr(U), rows, k, mu, upper, _ptr(ws), nb,
                                                   _stream(stream)))
+
+
+# ----------------------------------------------------------------- warm-start network
+
+def mlp_param_count(d, k, hidden):
+    return load().dsanls_mlp_param_count(d, k, hidden)
+
+
+def mlp_pack(p, device="cuda"):
+    """Pack a dict of numpy weights (W1a, W1u, b1, W2, b2) into the flat layout."""
+    import numpy as np
+    import torch
+    flat = np.concatenate([np.ascontiguousarray(p[n], dtype=np.float32).ravel()
+                           for n in ("W1a", "W1u", "b1", "W2", "b2")])
+    return torch.from_numpy(flat).to(device)
+
+
+def mlp_unpack(flat, d, k, hidden):
+    """Inverse of mlp_pack (host numpy float64 arrays)."""
+    import numpy as np
+    x = flat.detach().cpu().numpy().astype(np.float64) if hasattr(flat, "detach") else np.asarray(flat)
+    out, o = {}, 0
+    for name, shape in (("W1a", (d, hidden)), ("W1u", (hidden, k)), ("b1", (hidden,)), ("W2", (k, hidden)),
+                        ("b2", (k,))):
+        n = int(np.prod(shape))
+        out[name] = x[o:o + n].reshape(shape)
+        o += n
+    return out
+
+
+class MLP:
+    """Device-side warm-start network: forward, gradients and Adam steps."""
+
+    def __init__(self, d, k, hidden, params, max_rows, stream=None):
+        import torch
+        self.lib = load()
+        self.d, self.k, self.h = d, k, hidden
+        self.params = params
+        self.grads = torch.zeros_like(params)
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.step = 0
+        self.loss = torch.zeros(4, dtype=torch.float32, device=params.device)
+        self.ws_bytes = self.lib.dsanls_mlp_workspace_bytes(d, k, hidden, max_rows)
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=params.device)
+        self.max_rows = max_rows
+        self.stream = stream
+
+    def forward(self, a_rowptr, a_cols, a_vals, U):
+        import torch
+        rows = U.shape[0]
+        out = torch.empty((rows, self.k), dtype=torch.float32, device=U.device)
+        _check("dsanls_mlp_forward", self.lib.dsanls_mlp_forward(
+            self.d, self.k, self.h, _ptr(self.params), rows, _ptr(a_rowptr), _ptr(a_cols), _ptr(a_vals),
+            _ptr(U), _ptr(out), _ptr(self.ws), self.ws_bytes, _stream(self.stream)))
+        return out
+
+    def gradients(self, batch):
+        a_rp, a_c, a_v, c_cp, c_r, c_v, U, Y = batch
+        _check("dsanls_mlp_gradients", self.lib.dsanls_mlp_gradients(
+            self.d, self.k, self.h, _ptr(self.params), _ptr(self.grads), U.shape[0], _ptr(a_rp), _ptr(a_c),
+            _ptr(a_v), _ptr(c_cp), _ptr(c_r), _ptr(c_v), _ptr(U), _ptr(Y), _ptr(self.loss), _ptr(self.ws),
+            self.ws_bytes, _stream(self.stream)))
+        return self.grads
+
+    def train_step(self, batch, lr):
+        a_rp, a_c, a_v, c_cp, c_r, c_v, U, Y = batch
+        self.step += 1
+        _check("dsanls_mlp_train_step", self.lib.dsanls_mlp_train_step(
+            self.d, self.k, self.h, _ptr(self.params), _ptr(self.grads), _ptr(self.m), _ptr(self.v), self.step,
+            lr, U.shape[0], _ptr(a_rp), _ptr(a_c), _ptr(a_v), _ptr(c_cp), _ptr(c_r), _ptr(c_v), _ptr(U), _ptr(Y),
+            _ptr(self.loss), _ptr(self.ws), self.ws_bytes, _stream(self.stream)))
+
+    def last_loss(self):
+        return float(self.loss[0].item()) + float(self.loss[1].item())

@@ -52,6 +52,15 @@ struct Layout {
   size_t nnls_ws_bytes = 0;
   int32_t* idx = nullptr;
   int32_t* slot = nullptr;
+  // sketched rows of A (CSR input, subsampling): counts, offsets, entries
+  int32_t* a_cnt = nullptr;
+  int32_t* a_rowptr = nullptr;
+  int32_t* a_cols = nullptr;
+  float* a_vals = nullptr;
+  int32_t* scan_ws = nullptr;
+  float* ustart = nullptr;          // warm start, rows x k
+  void* mlp_ws = nullptr;
+  size_t mlp_ws_bytes = 0;
   void* sub_ws = nullptr;
   size_t sub_ws_bytes = 0;
   float* partials = nullptr;
@@ -120,6 +129,18 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
     L.sub_ws_bytes = subsample_ws_bytes(lngmax);
     L.sub_ws = take(L.sub_ws_bytes);
   }
+  if (!is_dense && sub) {
+    L.a_cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (rowsmax + 1)));
+    L.a_rowptr = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (rowsmax + 1)));
+    L.a_cols = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * std::max<int64_t>(M.nnz, 1)));
+    L.a_vals = reinterpret_cast<float*>(take(sizeof(float) * std::max<int64_t>(M.nnz, 1)));
+    L.scan_ws = reinterpret_cast<int32_t*>(take(scan_ws_bytes(rowsmax + 1)));
+    if (c.warm_hidden > 0) {
+      L.ustart = reinterpret_cast<float*>(take(sizeof(float) * rowsmax * k));
+      L.mlp_ws_bytes = mlp_ws_bytes(static_cast<int>(c.d), static_cast<int>(k), c.warm_hidden, rowsmax, true);
+      L.mlp_ws = take(L.mlp_ws_bytes);
+    }
+  }
   int64_t np = std::max<int64_t>(sumsq_partials(is_dense ? m : 1, is_dense ? n : std::max<int64_t>(M.nnz, 1)),
                                  csr_cross_partials(m));
   if (is_dense) np = std::max(np, residual_partials(m, n));
@@ -146,6 +167,9 @@ dsanls_status validate(const dsanls_config* c, const dsanls_matrix* M) {
     return fail(DSANLS_E_SHAPE, "identity sketch needs d == n and d_prime == m");
   if (c->sketch == DSANLS_SKETCH_GAUSSIAN && std::max(c->d, c->d_prime) > 4 * 65535)
     return fail(DSANLS_E_SHAPE, "Gaussian sketch supports d <= 262140");
+  if (c->warm_hidden < 0 || c->warm_hidden > 4096) return fail(DSANLS_E_INVALID_ARG, "warm_hidden out of range");
+  if (c->warm_hidden > 0 && (c->d != c->d_prime || M->format != DSANLS_CSR || c->sketch != DSANLS_SKETCH_SUBSAMPLE))
+    return fail(DSANLS_E_UNSUPPORTED, "warm start needs CSR input, a subsampling sketch and d == d_prime");
   if (!(c->alpha >= 0.0) || !(c->beta >= 0.0) || !std::isfinite(c->alpha) || !std::isfinite(c->beta))
     return fail(DSANLS_E_INVALID_ARG, "alpha and beta must be finite and >= 0");
   if (c->solver == DSANLS_SOLVER_PROX_CD) {
@@ -198,6 +222,10 @@ struct dsanls_ctx {
   // outer iteration whose V-side sketch product A' = M^T S'^t is already in
   // A[1] (computed together with the U side), or -1
   int64_t lookahead_t = -1;
+  // learned warm start (device parameters, caller-owned) and sketched rows
+  const float* warm = nullptr;
+  bool keep_rows = false;
+  int64_t rows_kept = -1;   // rows of the kept sketched matrix, -1 if none
   ~dsanls_ctx() {
     for (auto& v : ev)
       for (hipEvent_t e : v) (void)hipEventDestroy(e);
@@ -330,10 +358,31 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     CHECK(mark(ctx, kPhProduct));
   }
   const bool pgd = c.solver == DSANLS_SOLVER_PGD;
+  const bool warm = ctx->warm != nullptr && !is_dense && c.sketch == DSANLS_SKETCH_SUBSAMPLE &&
+                    !pgd && c.sweeps == 0;
+  ctx->rows_kept = -1;
+  if (!is_dense && c.sketch == DSANLS_SKETCH_SUBSAMPLE && (warm || ctx->keep_rows)) {
+    // sketched rows a_i of A = X S as CSR: (slot, sqrt(lng/d) * value)
+    CHECK(mark(ctx, kPhProduct));
+    const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
+    CHECK(launch_csr_hits_count(rowptr, colidx, rows, L.slot, L.a_cnt, s));
+    CHECK(launch_exclusive_scan(L.a_cnt, L.a_rowptr, rows, L.scan_ws, s));
+    CHECK(launch_csr_hits_fill(rowptr, colidx, vals, rows, L.slot, scale, L.a_rowptr, L.a_cols, L.a_vals, s));
+    CHECK(mark(ctx, kPhProduct));
+    ctx->rows_kept = rows;
+  }
+  const float* start = nullptr;
+  if (warm) {
+    CHECK(mark(ctx, kPhSmall));
+    CHECK(mlp_forward(static_cast<int>(d), static_cast<int>(k), c.warm_hidden, ctx->warm, rows, L.a_rowptr,
+                      L.a_cols, L.a_vals, Wself, L.ustart, L.mlp_ws, L.mlp_ws_bytes, s));
+    CHECK(mark(ctx, kPhSmall));
+    start = L.ustart;
+  }
   CHECK(mark(ctx, kPhNnls));
   CHECK(launch_nnls(pgd, L.G, L.R, Wself, Wself, rows, static_cast<int>(k), static_cast<float>(mu),
                     c.sweeps, static_cast<float>(c.tol), c.max_sweeps, ctx->upper, nullptr,
-                    L.counters, L.nnls_ws, L.nnls_ws_bytes, s));
+                    L.counters, L.nnls_ws, L.nnls_ws_bytes, s, start));
   CHECK(mark(ctx, kPhNnls));
   if (ctx->timing) ctx->timed_updates += 1;
 #undef CHECK
@@ -510,13 +559,58 @@ dsanls_status dsanls_objective(dsanls_ctx* ctx, double* rel_err) {
 dsanls_status dsanls_get_stats(dsanls_ctx* ctx, dsanls_stats* out) {
   if (!ctx) return fail(DSANLS_E_STATE, "get_stats: context is NULL");
   if (!out) return fail(DSANLS_E_INVALID_ARG, "get_stats: out is NULL");
-  unsigned long long cnt[2] = {0, 0};
+  unsigned long long cnt[3] = {0, 0, 0};
   DSANLS_HIP(hipMemcpyAsync(cnt, ctx->L.counters, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
   DSANLS_HIP(hipStreamSynchronize(ctx->stream));
   *out = ctx->stats;
   out->sweeps_total = static_cast<int64_t>(cnt[0]);
   out->rows_unconverged = static_cast<int64_t>(cnt[1]);
+  out->warm_fallbacks = static_cast<int64_t>(cnt[2]);
   return DSANLS_OK;
+}
+
+dsanls_status dsanls_set_warm_start(dsanls_ctx* ctx, const float* params, int32_t hidden) {
+  if (!ctx) return fail(DSANLS_E_STATE, "set_warm_start: context is NULL");
+  if (params == nullptr) {
+    ctx->warm = nullptr;
+    return DSANLS_OK;
+  }
+  if (ctx->cfg.warm_hidden <= 0 || ctx->L.mlp_ws == nullptr)
+    return fail(DSANLS_E_STATE, "set_warm_start: the context was created with warm_hidden = 0");
+  if (hidden != ctx->cfg.warm_hidden) return fail(DSANLS_E_SHAPE, "set_warm_start: hidden != cfg.warm_hidden");
+  ctx->warm = params;
+  return DSANLS_OK;
+}
+
+dsanls_status dsanls_set_keep_sketched_rows(dsanls_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(DSANLS_E_STATE, "set_keep_sketched_rows: context is NULL");
+  if (enable && ctx->L.a_rowptr == nullptr)
+    return fail(DSANLS_E_STATE, "set_keep_sketched_rows: needs CSR input and a subsampling sketch");
+  ctx->keep_rows = enable != 0;
+  return DSANLS_OK;
+}
+
+dsanls_status dsanls_gather_sketched_rows(dsanls_ctx* ctx, const int32_t* sel, int64_t nsel,
+                                          int32_t* out_rowptr, int32_t* out_cols, float* out_vals,
+                                          int64_t capacity, int64_t* nnz) {
+  if (!ctx) return fail(DSANLS_E_STATE, "gather_sketched_rows: context is NULL");
+  if (ctx->rows_kept < 0) return fail(DSANLS_E_STATE, "gather_sketched_rows: the last update kept no rows");
+  if (nsel < 0 || (nsel > 0 && (!sel || !out_cols || !out_vals)) || !out_rowptr || !nnz)
+    return fail(DSANLS_E_INVALID_ARG, "gather_sketched_rows: bad arguments");
+  if (nsel > std::max(ctx->cfg.m, ctx->cfg.n)) return fail(DSANLS_E_SHAPE, "gather_sketched_rows: nsel > max(m, n)");
+  const Layout& L = ctx->L;
+  hipStream_t s = ctx->stream;
+  dsanls_status st;
+  // lengths into out_rowptr, scanned in place through the count buffer
+  if ((st = launch_csr_select_len(L.a_rowptr, ctx->rows_kept, sel, nsel, L.a_cnt, s)) != DSANLS_OK) return st;
+  if ((st = launch_exclusive_scan(L.a_cnt, out_rowptr, nsel, L.scan_ws, s)) != DSANLS_OK) return st;
+  int32_t total = 0;
+  DSANLS_HIP(hipMemcpyAsync(&total, out_rowptr + nsel, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  DSANLS_HIP(hipStreamSynchronize(s));
+  *nnz = total;
+  if (total > capacity) return fail(DSANLS_E_WORKSPACE, "gather_sketched_rows: capacity too small");
+  return launch_csr_select_copy(L.a_rowptr, ctx->rows_kept, L.a_cols, L.a_vals, sel, nsel, out_rowptr, out_cols,
+                                out_vals, s);
 }
 
 dsanls_status dsanls_set_timing(dsanls_ctx* ctx, int32_t enable) {

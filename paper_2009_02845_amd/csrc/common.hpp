@@ -102,15 +102,23 @@ dsanls_status launch_gather_cols(const float* X, int64_t ldx, const int32_t* idx
 dsanls_status launch_gather_rows_t(const float* W, int64_t k, const int32_t* idx, int64_t d,
                                    float scale, float* B, int64_t ldb, hipStream_t s);
 dsanls_status launch_check_finite(const float* X, int64_t count, int* err_flag, hipStream_t s);
+// out[0..n] = exclusive prefix sums of in[0..n) (out[n] = total); ws holds
+// scan_ws_bytes(n) bytes.
+size_t scan_ws_bytes(int64_t n);
+dsanls_status launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* ws,
+                                    hipStream_t s);
 
 // ---------------------------------------------------------------- nnls.hip
 size_t nnls_ws_bytes(int k);
 // pgd = false: prox-CD (sweeps >= 1, or 0 = to tol); pgd = true: one PGD step.
 // counters (may be null): [0] += row-sweeps run, [1] += rows left unconverged.
+// start (may be null: start from U) is a warm start for the to-tolerance
+// mode; rows whose warm start does not converge within max_sweeps, or is
+// not finite, restart from the centre C (counters[2] += 1 per such row).
 dsanls_status launch_nnls(bool pgd, const float* G, const float* R, const float* C, float* U,
                           int64_t rows, int k, float mu, int sweeps, float tol, int max_sweeps,
                           float upper, int32_t* sweeps_used, unsigned long long* counters,
-                          void* ws, size_t ws_bytes, hipStream_t s);
+                          void* ws, size_t ws_bytes, hipStream_t s, const float* start = nullptr);
 
 // ---------------------------------------------------------------- sparse.hip
 // R[i, :] = scale * sum_{e in row i, slot[col_e] >= 0} val_e * W[col_e, :]
@@ -119,6 +127,31 @@ dsanls_status launch_csr_sketch_rhs(const int64_t* rowptr, const int32_t* colidx
                                     const float* vals, int64_t rows, const int32_t* slot,
                                     const float* W, int64_t k, float scale, float* R,
                                     hipStream_t s);
+// Rows of the sketched matrix A = X S for a subsampling sketch, as CSR:
+// row i holds (slot[col], scale * val) for the sampled columns of row i of
+// X, in ascending column order.  count: cnt[i] = hits of row i; fill:
+// writes them at a_rowptr[i].
+dsanls_status launch_csr_hits_count(const int64_t* rowptr, const int32_t* colidx, int64_t rows,
+                                    const int32_t* slot, int32_t* cnt, hipStream_t s);
+dsanls_status launch_csr_hits_fill(const int64_t* rowptr, const int32_t* colidx, const float* vals,
+                                   int64_t rows, const int32_t* slot, float scale,
+                                   const int32_t* a_rowptr, int32_t* a_cols, float* a_vals,
+                                   hipStream_t s);
+// Copy rows sel[0..nsel) of a CSR with nrows rows (int32 offsets) into a
+// packed CSR whose offsets out_rowptr come from a scan of the selected row
+// lengths; indices outside [0, nrows) select an empty row.
+dsanls_status launch_csr_select_len(const int32_t* rowptr, int64_t nrows, const int32_t* sel,
+                                    int64_t nsel, int32_t* len, hipStream_t s);
+dsanls_status launch_csr_select_copy(const int32_t* rowptr, int64_t nrows, const int32_t* cols,
+                                     const float* vals, const int32_t* sel, int64_t nsel,
+                                     const int32_t* out_rowptr, int32_t* out_cols, float* out_vals,
+                                     hipStream_t s);
+// MLP (mlp.hip)
+int64_t mlp_param_count(int d, int k, int hd);
+size_t mlp_ws_bytes(int d, int k, int hd, int64_t rows, bool forward_only);
+dsanls_status mlp_forward(int d, int k, int hd, const float* params, int64_t rows,
+                          const int32_t* a_rowptr, const int32_t* a_cols, const float* a_vals,
+                          const float* U, float* out, void* ws, size_t ws_bytes, hipStream_t s);
 // Sparse objective pieces: sum_nnz M_ij <u_i, v_j> and sum_nnz M_ij^2 as
 // compensated partials.
 int64_t csr_cross_partials(int64_t rows);

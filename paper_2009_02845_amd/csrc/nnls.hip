@@ -171,29 +171,48 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
                                                      const float* __restrict__ den,
                                                      const float* __restrict__ inv,
                                                      const float* __restrict__ R,
-                                                     const float* C, float* U, int64_t rows,
-                                                     int k, float mu, int sweeps, float tol,
-                                                     int max_sweeps, float upper,
+                                                     const float* C, const float* start, float* U,
+                                                     int64_t rows, int k, float mu, int sweeps,
+                                                     float tol, int max_sweeps, float upper,
                                                      int32_t* __restrict__ sweeps_used,
                                                      unsigned long long* __restrict__ counters) {
   // C (the proximal centre) may alias U: every lane reads its own row of C
-  // before it writes that row of U, at the end.
+  // before it writes that row of U, at the end.  start (to-tolerance mode
+  // only) is a warm start; without it the solve starts from U.
   const int64_t row = blockIdx.x * 64ll + threadIdx.x;
   const bool valid = row < rows;
   const int64_t off = row * k;
   RowBlocks<KC, W> u;
-  load_row<KC, W>(U, row, k, valid, u);
+  load_row<KC, W>(TO_TOL && start != nullptr ? start : U, row, k, valid, u);
   int used = 0;
-  bool unconverged = false;
+  bool unconverged = false, fell_back = false;
   if (!TO_TOL) {
     for (int s = 0; s < sweeps; ++s) sweep<KC, W>(gp, inv, R, C, off, k, mu, valid, upper, u);
     used = sweeps;
-  } else {
-    bool active = valid && kkt<KC, W>(gp, den, R, C, off, k, mu, valid, u) > tol;
+  } else if (valid) {
+    bool ok = true;
+    if (start != nullptr) {
+#pragma unroll
+      for (int l = 0; l < KC; ++l) ok = ok && isfinite(u.b[l / W][l % W]);
+    }
+    bool active = ok && kkt<KC, W>(gp, den, R, C, off, k, mu, valid, u) > tol;
     while (active && used < max_sweeps) {
       sweep<KC, W>(gp, inv, R, C, off, k, mu, valid, upper, u);
       ++used;
       active = kkt<KC, W>(gp, den, R, C, off, k, mu, valid, u) > tol;
+    }
+    if (start != nullptr && (!ok || active)) {
+      // the warm start failed: restart from the cold start, the centre U^t
+      fell_back = true;
+      load_row<KC, W>(C, row, k, valid, u);
+      int cold = 0;
+      active = kkt<KC, W>(gp, den, R, C, off, k, mu, valid, u) > tol;
+      while (active && cold < max_sweeps) {
+        sweep<KC, W>(gp, inv, R, C, off, k, mu, valid, upper, u);
+        ++cold;
+        active = kkt<KC, W>(gp, den, R, C, off, k, mu, valid, u) > tol;
+      }
+      used += cold;
     }
     unconverged = active;
   }
@@ -210,13 +229,16 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
     // wave totals, one integer atomic per wave (exact, order-free)
     unsigned long long a = static_cast<unsigned long long>(used);
     unsigned long long b = unconverged ? 1ull : 0ull;
+    unsigned long long f = fell_back ? 1ull : 0ull;
     for (int o = 32; o > 0; o >>= 1) {
       a += __shfl_down(a, o, 64);
       b += __shfl_down(b, o, 64);
+      f += __shfl_down(f, o, 64);
     }
     if (threadIdx.x == 0) {
       atomicAdd(&counters[0], a);
       atomicAdd(&counters[1], b);
+      atomicAdd(&counters[2], f);
     }
   }
 }
@@ -258,7 +280,7 @@ template <int KC, int W>
 dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, float* U,
                      int64_t rows, int k, float mu, int sweeps, float tol, int max_sweeps,
                      float upper, int32_t* sweeps_used, unsigned long long* counters, void* ws,
-                     hipStream_t s) {
+                     hipStream_t s, const float* start) {
   Prep p = carve_prep(ws, KC);
   prep_kernel<<<1, 256, 0, s>>>(G, k, KC, mu, p.gp, p.gdiag, p.den, p.inv, p.eta);
   DSANLS_LAUNCHED("prep_kernel");
@@ -268,12 +290,12 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
     pgd_kernel<KC, W><<<grid, 64, 0, s>>>(p.gp, p.gdiag, p.eta, R, U, rows, k, upper);
     DSANLS_LAUNCHED("pgd_kernel");
   } else if (sweeps > 0) {
-    prox_cd_kernel<KC, W, false><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, U, rows, k, mu, sweeps,
-                                                     tol, max_sweeps, upper, sweeps_used, counters);
+    prox_cd_kernel<KC, W, false><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, nullptr, U, rows, k, mu,
+                                                     sweeps, tol, max_sweeps, upper, sweeps_used, counters);
     DSANLS_LAUNCHED("prox_cd_kernel");
   } else {
-    prox_cd_kernel<KC, W, true><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, U, rows, k, mu, sweeps,
-                                                    tol, max_sweeps, upper, sweeps_used, counters);
+    prox_cd_kernel<KC, W, true><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, start, U, rows, k, mu,
+                                                    sweeps, tol, max_sweeps, upper, sweeps_used, counters);
     DSANLS_LAUNCHED("prox_cd_kernel");
   }
   return DSANLS_OK;
@@ -300,14 +322,14 @@ size_t nnls_ws_bytes(int k) {
 dsanls_status launch_nnls(bool pgd, const float* G, const float* R, const float* C, float* U,
                           int64_t rows, int k, float mu, int sweeps, float tol, int max_sweeps,
                           float upper, int32_t* sweeps_used, unsigned long long* counters,
-                          void* ws, size_t ws_bytes, hipStream_t s) {
+                          void* ws, size_t ws_bytes, hipStream_t s, const float* start) {
   if (k < 1 || k > kMaxK) return fail(DSANLS_E_UNSUPPORTED, "NNLS supports 1 <= k <= 128");
   if (ws_bytes < nnls_ws_bytes(k)) return fail(DSANLS_E_WORKSPACE, "NNLS workspace too small");
   switch (nnls_kc(k)) {
 #define DSANLS_KC(KC, W)                                                                             \
   case KC:                                                                                           \
     return run_kc<KC, W>(pgd, G, R, C, U, rows, k, mu, sweeps, tol, max_sweeps, upper, sweeps_used, \
-                         counters, ws, s);
+                         counters, ws, s, start);
     DSANLS_KC(4, 4)
     DSANLS_KC(8, 8)
     DSANLS_KC(10, 16)

@@ -201,6 +201,72 @@ __global__ __launch_bounds__(256) void frob_dot_kernel(const float* __restrict__
   }
 }
 
+constexpr int kScanTile = 2048;   // 256 threads x 8 items
+
+// Inclusive sum of a block's 256 thread values (wave scans + LDS).
+__device__ __forceinline__ int32_t block_scan_incl(int32_t x, int32_t* wsum) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  int32_t before = 0;
+  for (int w = 0; w < wave; ++w) before += wsum[w];
+  __syncthreads();
+  return x + before;
+}
+
+__global__ __launch_bounds__(256) void scan_sums_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                        int32_t* __restrict__ sums) {
+  __shared__ int32_t wsum[4];
+  const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * 8;
+  int32_t t = 0;
+  for (int e = 0; e < 8; ++e)
+    if (base + e < n) t += in[base + e];
+  t = block_scan_incl(t, wsum);
+  if (threadIdx.x == 255) sums[blockIdx.x] = t;
+}
+
+// exclusive scan of the tile sums in place (one block, any length)
+__global__ __launch_bounds__(256) void scan_tiles_kernel(int32_t* sums, int64_t ntiles) {
+  __shared__ int32_t wsum[4];
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < ntiles; b0 += 256) {
+    const int64_t i = b0 + threadIdx.x;
+    const int32_t v = i < ntiles ? sums[i] : 0;
+    const int32_t incl = block_scan_incl(v, wsum);
+    if (i < ntiles) sums[i] = carry + incl - v;
+    __syncthreads();
+    if (threadIdx.x == 255) carry += incl;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void scan_apply_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                         const int32_t* __restrict__ sums,
+                                                         int32_t* __restrict__ out) {
+  __shared__ int32_t wsum[4];
+  const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * 8;
+  int32_t v[8];
+  int32_t t = 0;
+  for (int e = 0; e < 8; ++e) {
+    v[e] = base + e < n ? in[base + e] : 0;
+    t += v[e];
+  }
+  const int32_t incl = block_scan_incl(t, wsum);
+  int32_t run = sums[blockIdx.x] + incl - t;
+  for (int e = 0; e < 8; ++e) {
+    if (base + e < n) out[base + e] = run;
+    run += v[e];
+  }
+  const int64_t last = (static_cast<int64_t>(gridDim.x) - 1) * kScanTile + 255 * 8;
+  if (base == last) out[n] = run;   // total, written by the last thread of the grid
+}
+
 unsigned grid_for(int64_t total, int64_t per_block, int64_t cap) {
   int64_t g = ceil_div(total, per_block);
   if (g > cap) g = cap;
@@ -276,6 +342,24 @@ dsanls_status launch_frob_dot(const float* X, const float* Y, int64_t count, flo
                               hipStream_t s) {
   frob_dot_kernel<<<1, 256, 0, s>>>(X, Y, count, out);
   DSANLS_LAUNCHED("frob_dot_kernel");
+  return DSANLS_OK;
+}
+
+size_t scan_ws_bytes(int64_t n) { return sizeof(int32_t) * (ceil_div(n, kScanTile) + 1); }
+
+dsanls_status launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* ws,
+                                    hipStream_t s) {
+  if (n <= 0) {
+    DSANLS_HIP(hipMemsetAsync(out, 0, sizeof(int32_t), s));
+    return DSANLS_OK;
+  }
+  const int64_t nt = ceil_div(n, kScanTile);
+  scan_sums_kernel<<<static_cast<unsigned>(nt), 256, 0, s>>>(in, n, ws);
+  DSANLS_LAUNCHED("scan_sums_kernel");
+  scan_tiles_kernel<<<1, 256, 0, s>>>(ws, nt);
+  DSANLS_LAUNCHED("scan_tiles_kernel");
+  scan_apply_kernel<<<static_cast<unsigned>(nt), 256, 0, s>>>(in, n, ws, out);
+  DSANLS_LAUNCHED("scan_apply_kernel");
   return DSANLS_OK;
 }
 

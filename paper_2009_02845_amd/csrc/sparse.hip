@@ -57,6 +57,84 @@ __global__ __launch_bounds__(256) void csr_rhs_kernel(const int64_t* __restrict_
   if (lane + 64 < k) r[lane + 64] = scale * a1;
 }
 
+__global__ __launch_bounds__(256) void csr_hits_count_kernel(const int64_t* __restrict__ rowptr,
+                                                             const int32_t* __restrict__ colidx,
+                                                             int64_t rows,
+                                                             const int32_t* __restrict__ slot,
+                                                             int32_t* __restrict__ cnt) {
+  const int64_t row = blockIdx.x * 4ll + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const int64_t beg = rowptr[row], end = rowptr[row + 1];
+  int32_t c = 0;
+  for (int64_t base = beg; base < end; base += 64) {
+    const int64_t e = base + lane;
+    const bool hit = e < end && slot[colidx[e]] >= 0;
+    c += __popcll(__ballot(hit));
+  }
+  if (lane == 0) cnt[row] = c;
+}
+
+__global__ __launch_bounds__(256) void csr_hits_fill_kernel(const int64_t* __restrict__ rowptr,
+                                                            const int32_t* __restrict__ colidx,
+                                                            const float* __restrict__ vals,
+                                                            int64_t rows,
+                                                            const int32_t* __restrict__ slot,
+                                                            float scale,
+                                                            const int32_t* __restrict__ a_rowptr,
+                                                            int32_t* __restrict__ a_cols,
+                                                            float* __restrict__ a_vals) {
+  const int64_t row = blockIdx.x * 4ll + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const int64_t beg = rowptr[row], end = rowptr[row + 1];
+  int32_t pos = a_rowptr[row];
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int64_t base = beg; base < end; base += 64) {
+    const int64_t e = base + lane;
+    int32_t sl = -1;
+    if (e < end) sl = slot[colidx[e]];
+    const unsigned long long mask = __ballot(sl >= 0);
+    if (sl >= 0) {
+      const int32_t at = pos + __popcll(mask & below);
+      a_cols[at] = sl;
+      a_vals[at] = scale * vals[e];
+    }
+    pos += __popcll(mask);
+  }
+}
+
+__global__ __launch_bounds__(256) void select_len_kernel(const int32_t* __restrict__ rowptr,
+                                                         int64_t nrows,
+                                                         const int32_t* __restrict__ sel, int64_t nsel,
+                                                         int32_t* __restrict__ len) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= nsel) return;
+  const int32_t r = sel[i];
+  len[i] = (r >= 0 && r < nrows) ? rowptr[r + 1] - rowptr[r] : 0;
+}
+
+__global__ __launch_bounds__(256) void select_copy_kernel(const int32_t* __restrict__ rowptr,
+                                                          int64_t nrows,
+                                                          const int32_t* __restrict__ cols,
+                                                          const float* __restrict__ vals,
+                                                          const int32_t* __restrict__ sel,
+                                                          int64_t nsel,
+                                                          const int32_t* __restrict__ out_rowptr,
+                                                          int32_t* __restrict__ out_cols,
+                                                          float* __restrict__ out_vals) {
+  const int64_t i = blockIdx.x * 4ll + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= nsel) return;
+  const int32_t r = sel[i];
+  if (r < 0 || r >= nrows) return;
+  const int32_t beg = rowptr[r], len = rowptr[r + 1] - beg, dst = out_rowptr[i];
+  for (int32_t e = lane; e < len; e += 64) {
+    out_cols[dst + e] = cols[beg + e];
+    out_vals[dst + e] = vals[beg + e];
+  }
+}
+
 constexpr int kCrossBlocks = 2048;
 
 // Per wave, rows i = wave_id, wave_id + total_waves, ...: (M V)_i is
@@ -142,6 +220,46 @@ dsanls_status launch_csr_sketch_rhs(const int64_t* rowptr, const int32_t* colidx
   csr_rhs_kernel<<<static_cast<unsigned>(ceil_div(rows, 4)), 256, 0, s>>>(
       rowptr, colidx, vals, rows, slot, W, static_cast<int>(k), scale, R);
   DSANLS_LAUNCHED("csr_rhs_kernel");
+  return DSANLS_OK;
+}
+
+dsanls_status launch_csr_hits_count(const int64_t* rowptr, const int32_t* colidx, int64_t rows,
+                                    const int32_t* slot, int32_t* cnt, hipStream_t s) {
+  if (rows <= 0) return DSANLS_OK;
+  csr_hits_count_kernel<<<static_cast<unsigned>(ceil_div(rows, 4)), 256, 0, s>>>(rowptr, colidx, rows, slot,
+                                                                                 cnt);
+  DSANLS_LAUNCHED("csr_hits_count_kernel");
+  return DSANLS_OK;
+}
+
+dsanls_status launch_csr_hits_fill(const int64_t* rowptr, const int32_t* colidx, const float* vals,
+                                   int64_t rows, const int32_t* slot, float scale,
+                                   const int32_t* a_rowptr, int32_t* a_cols, float* a_vals,
+                                   hipStream_t s) {
+  if (rows <= 0) return DSANLS_OK;
+  csr_hits_fill_kernel<<<static_cast<unsigned>(ceil_div(rows, 4)), 256, 0, s>>>(
+      rowptr, colidx, vals, rows, slot, scale, a_rowptr, a_cols, a_vals);
+  DSANLS_LAUNCHED("csr_hits_fill_kernel");
+  return DSANLS_OK;
+}
+
+dsanls_status launch_csr_select_len(const int32_t* rowptr, int64_t nrows, const int32_t* sel,
+                                    int64_t nsel, int32_t* len, hipStream_t s) {
+  if (nsel <= 0) return DSANLS_OK;
+  select_len_kernel<<<static_cast<unsigned>(ceil_div(nsel, 256)), 256, 0, s>>>(rowptr, nrows, sel, nsel, len);
+  DSANLS_LAUNCHED("select_len_kernel");
+  return DSANLS_OK;
+}
+
+dsanls_status launch_csr_select_copy(const int32_t* rowptr, int64_t nrows, const int32_t* cols,
+                                     const float* vals, const int32_t* sel, int64_t nsel,
+                                     const int32_t* out_rowptr, int32_t* out_cols, float* out_vals,
+                                     hipStream_t s) {
+  if (nsel <= 0) return DSANLS_OK;
+  select_copy_kernel<<<static_cast<unsigned>(ceil_div(nsel, 4)), 256, 0, s>>>(rowptr, nrows, cols, vals, sel,
+                                                                               nsel, out_rowptr, out_cols,
+                                                                               out_vals);
+  DSANLS_LAUNCHED("select_copy_kernel");
   return DSANLS_OK;
 }
 

@@ -1,0 +1,165 @@
+"""GPU parity of the warm-start network (forward, backward, Adam) and of the
+warm-started to-tolerance update, against the FP64 oracles."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import dsanls as O
+from oracle import mlp as N
+from oracle import philox as P
+from paper_2009_02845_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_02845_amd import binding
+    binding.load()
+    return torch, binding
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def _batch(torch, B, d, k, seed, density=0.002):
+    g = np.random.default_rng(seed)
+    A = sp.random(B, d, density=density, format="csr", random_state=seed, dtype=np.float64)
+    A.data = (g.lognormal(0, 1, A.nnz) * 3).astype(np.float32).astype(np.float64)
+    A.sort_indices()
+    U = g.random((B, k)).astype(np.float32).astype(np.float64)
+    Y = g.random((B, k)).astype(np.float32).astype(np.float64)
+    C = A.tocsc()
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a.astype(dt))).cuda()
+    dev = (t(A.indptr, np.int32), t(A.indices, np.int32), t(A.data, np.float32),
+           t(C.indptr, np.int32), t(C.indices, np.int32), t(C.data, np.float32),
+           t(U, np.float32), t(Y, np.float32))
+    return A, U, Y, dev
+
+
+def _params64(d, k, h, seed):
+    p = {n: v.astype(np.float64) for n, v in synth.mlp_init(d, k, h, seed).items()}
+    g = np.random.default_rng(seed + 100)
+    p["b1"] = (g.standard_normal(h) * 0.1).astype(np.float32).astype(np.float64)
+    p["b2"] = (g.standard_normal(k) * 0.1 + 0.3).astype(np.float32).astype(np.float64)
+    return {n: v.astype(np.float32).astype(np.float64) for n, v in p.items()}
+
+
+@pytest.mark.parametrize("B,d,k,h", [(1000, 2000, 100, 256), (333, 50, 10, 64), (64, 2000, 100, 256)])
+def test_forward_and_gradients_match_oracle(env, B, d, k, h):
+    torch, Bd = env
+    p = _params64(d, k, h, 1)
+    A, U, Y, dev = _batch(torch, B, d, k, 2, density=0.002 if d > 100 else 0.1)
+    net = Bd.MLP(d, k, h, Bd.mlp_pack(p), max_rows=B)
+    out = net.forward(dev[0], dev[1], dev[2], dev[6]).cpu().numpy()
+    ref = N.forward(p, A, U)[3]
+    assert _rel(out, ref) < 1e-5
+    g = Bd.mlp_unpack(net.gradients(dev), d, k, h)
+    gref, lref = N.backward(p, A, U, Y)
+    assert abs(net.last_loss() - lref) / lref < 1e-5
+    for name in N.PARAMS:
+        assert _rel(g[name], gref[name]) < 1e-4, name
+
+
+def test_adam_steps_match_oracle(env):
+    torch, Bd = env
+    d, k, h, B = 300, 20, 64, 512
+    p = _params64(d, k, h, 3)
+    A, U, Y, dev = _batch(torch, B, d, k, 4, density=0.02)
+    net = Bd.MLP(d, k, h, Bd.mlp_pack(p), max_rows=B)
+    m = {n: np.zeros_like(v) for n, v in p.items()}
+    v = {n: np.zeros_like(x) for n, x in p.items()}
+    for t in range(1, 6):
+        net.train_step(dev, 1e-3)
+        gr, _ = N.backward(p, A, U, Y)
+        N.adam_step(p, gr, m, v, t, lr=1e-3)
+    got = Bd.mlp_unpack(net.params, d, k, h)
+    for name in N.PARAMS:
+        assert _rel(got[name], p[name]) < 1e-4, name
+
+
+def _sparse_ctx(env, m, n, k, d, seed, warm_hidden=0, tol=1e-5):
+    torch, Bd = env
+    g = np.random.default_rng(seed)
+    Ms = sp.random(m, n, density=0.02, format="csr", random_state=seed, dtype=np.float64)
+    Ms.data = g.lognormal(0, 1, Ms.nnz)
+    Ms = Ms.astype(np.float32).tocsr()
+    Ms.sort_indices()
+    Mt = Ms.T.tocsr()
+    Mt.sort_indices()
+    U0, V0 = synth.init_factors(m, n, k, seed)
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a.astype(dt))).cuda()
+    arrs = [t(Ms.indptr, np.int64), t(Ms.indices, np.int32), t(Ms.data, np.float32),
+            t(Mt.indptr, np.int64), t(Mt.indices, np.int32), t(Mt.data, np.float32)]
+    U, V = torch.from_numpy(U0).cuda(), torch.from_numpy(V0).cuda()
+    cfg = Bd.make_config(m, n, k, d, d, sketch="subsample", solver="prox_cd", sweeps=0, tol=tol,
+                         max_sweeps=400, alpha=1.0, beta=1.0, seed=7, warm_hidden=warm_hidden)
+    s = Bd.Solver(cfg, Bd.csr_matrix(*arrs), U, V, tensors=arrs)
+    return s, Ms.astype(np.float64), U, V, U0, V0
+
+
+def test_sketched_rows_match_oracle(env):
+    torch, Bd = env
+    s, M64, U, V, U0, V0 = _sparse_ctx(env, 800, 600, 8, 60, 5)
+    s.keep_sketched_rows(True)
+    s.update_U(3)
+    sel = np.array([0, 5, 799, 123, 5, 400], dtype=np.int32)
+    rp, cols, vals = s.gather_sketched_rows(torch.from_numpy(sel).cuda(), capacity=100000)
+    S = P.subsample_sketch(7, 3, 0, 600, 60)
+    A = (M64 @ S).tocsr()
+    A.sort_indices()
+    got = sp.csr_matrix((vals.cpu().numpy().astype(np.float64), cols.cpu().numpy(), rp.cpu().numpy()),
+                        shape=(len(sel), 60))
+    ref = A[sel]
+    assert np.array_equal(got.indptr, ref.indptr) and np.array_equal(got.indices, ref.indices)
+    assert np.allclose(got.data, ref.data, rtol=1e-6, atol=0)
+
+
+def test_warm_start_reaches_the_cold_solution(env):
+    # the regularised row problem has a unique minimiser (mu > 0): warm and
+    # cold to-tolerance solves agree to the tolerance; a network that outputs
+    # NaN falls back to the cold start on every row
+    torch, Bd = env
+    m, n, k, d, h = 700, 500, 10, 80, 32
+    cold, M64, Uc, Vc, U0, V0 = _sparse_ctx(env, m, n, k, d, 9)
+    warm, _, Uw, Vw, _, _ = _sparse_ctx(env, m, n, k, d, 9, warm_hidden=h)
+    p = Bd.mlp_pack(synth.mlp_init(d, k, h, 1))
+    warm.set_warm_start(p, h)
+    for t in range(3):
+        cold.iteration(t)
+        warm.iteration(t)
+        assert _rel(Uw.cpu().numpy(), Uc.cpu().numpy()) < 1e-3
+        assert _rel(Vw.cpu().numpy(), Vc.cpu().numpy()) < 1e-3
+    st = warm.stats()
+    assert st["warm_fallbacks"] < st["rows_updated"]
+    for poison in ("nan", "inf"):
+        bad = p.clone()
+        if poison == "nan":
+            bad[:] = float("nan")
+        else:
+            bad[:] = 0.0
+            bad[-k:] = float("inf")          # output bias: every prediction is +inf
+        Uw.copy_(Uc)
+        Vw.copy_(Vc)
+        warm.set_warm_start(bad, h)
+        before = warm.stats()["warm_fallbacks"]
+        warm.update_U(3)
+        Uref = Uc.clone()
+        cold.update_U(3)
+        assert warm.stats()["warm_fallbacks"] - before == m, poison
+        assert _rel(Uw.cpu().numpy(), Uc.cpu().numpy()) < 1e-6
+        Uc.copy_(Uref)
+
+
+def test_cold_to_tolerance_update_matches_oracle(env):
+    m, n, k, d = 700, 500, 10, 80
+    s, M64, U, V, U0, V0 = _sparse_ctx(env, m, n, k, d, 9, tol=1e-5)
+    ocfg = O.Config(k=k, d=d, d_prime=d, sketch=O.SKETCH_SUBSAMPLE, solver=O.SOLVER_PROX_CD, sweeps=0,
+                    tol=1e-12, max_sweeps=5000, seed=7)
+    s.update_U(0)
+    Uo = O.update_U(M64, U0.astype(np.float64), V0.astype(np.float64), 0, ocfg)
+    assert _rel(U.cpu().numpy(), Uo) < 1e-3
