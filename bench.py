@@ -49,7 +49,7 @@ WORKLOADS = {
     "sparse-500000x200000-warm": dict(kind="warm", m=500000, n=200000, k=100, d=2000, iters=10,
                                       solver="prox_cd", nnz=100_000_000, precision="fp32", hidden=256,
                                       pairs=1_000_000, runs=5, run_iters=20, label_tol=1e-6, tol=1e-4,
-                                      max_sweeps=200, epochs=4, batch=4096, lr=1e-3),
+                                      max_sweeps=200, epochs=6, batch=4096, lr=1e-4),
 }
 DEFAULT = "dense-20000x10000"
 
@@ -194,7 +194,11 @@ def run_warm(args, w, torch, B):
     # 2) training on the GPU (the library's forward/backward/Adam kernels)
     from paper_2009_02845_amd import synth
     t0 = time.perf_counter()
-    params = B.mlp_pack(synth.mlp_init(d, k, H, args.seed), device=dev)
+    p0 = synth.mlp_init(d, k, H, args.seed)
+    # data-dependent scale of the sparse first layer: the sketched values are
+    # sqrt(n/d) M_ij, far from unit scale, so W1a starts divided by their mean
+    p0["W1a"] = (p0["W1a"] / max(float(np.mean(np.abs(A_all.data))), 1e-12)).astype(np.float32)
+    params = B.mlp_pack(p0, device=dev)
     bs = w["batch"]
     perm = np.random.default_rng(5).permutation(A_all.shape[0])
     batches = []
@@ -273,6 +277,9 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES bytes device-to-device three times (calibrates the HBM "
+                         "traffic counters against a transfer of known size) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the method's multi-GPU form (an all-reduce of the k x d "
@@ -284,6 +291,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4, "copies": 3}), flush=True)
+        return
     B.load()
     w = WORKLOADS[args.workload]
     K = args.steps if args.steps is not None else w["iters"]

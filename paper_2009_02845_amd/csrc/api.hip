@@ -53,12 +53,17 @@ struct Layout {
   int32_t* idx = nullptr;
   int32_t* slot = nullptr;
   // sketched rows of A (CSR input, subsampling): counts, offsets, entries
-  int32_t* a_cnt = nullptr;
+  int32_t* a_cnt = nullptr;         // per-row or per-segment counts
+  int32_t* a_pos = nullptr;         // per-segment start positions
   int32_t* a_rowptr = nullptr;
   int32_t* a_cols = nullptr;
   float* a_vals = nullptr;
   int32_t* scan_ws = nullptr;
   float* ustart = nullptr;          // warm start, rows x k
+  // segment tables of CSR(M) (side 0) and CSR(M^T) (side 1), partial sums
+  CsrSegments seg[2];
+  int64_t seg_cap[2] = {0, 0}, multi_cap[2] = {0, 0};
+  float* seg_partials = nullptr;
   void* mlp_ws = nullptr;
   size_t mlp_ws_bytes = 0;
   void* sub_ws = nullptr;
@@ -129,12 +134,30 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
     L.sub_ws_bytes = subsample_ws_bytes(lngmax);
     L.sub_ws = take(L.sub_ws_bytes);
   }
+  if (!is_dense) {
+    const int64_t nnz = std::max<int64_t>(M.nnz, 0);
+    int64_t parts = 0;
+    for (int sd = 0; sd < 2; ++sd) {
+      const int64_t rows = sd == 0 ? m : n;
+      L.seg_cap[sd] = csr_seg_bound(rows, nnz);
+      L.multi_cap[sd] = nnz / kCsrSegment + 1;
+      L.seg[sd].seg_row = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * L.seg_cap[sd]));
+      L.seg[sd].seg_beg = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * L.seg_cap[sd]));
+      L.seg[sd].seg_part = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * L.seg_cap[sd]));
+      L.seg[sd].multi_row = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * L.multi_cap[sd]));
+      L.seg[sd].multi_part = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (L.multi_cap[sd] + 1)));
+      parts = std::max(parts, csr_part_bound(nnz));
+    }
+    L.seg_partials = reinterpret_cast<float*>(take(sizeof(float) * parts * k));
+  }
   if (!is_dense && sub) {
-    L.a_cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (rowsmax + 1)));
+    const int64_t cnt_len = std::max({rowsmax + 1, L.seg_cap[0] + 1, L.seg_cap[1] + 1});
+    L.a_cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * cnt_len));
+    L.a_pos = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * cnt_len));
     L.a_rowptr = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (rowsmax + 1)));
     L.a_cols = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * std::max<int64_t>(M.nnz, 1)));
     L.a_vals = reinterpret_cast<float*>(take(sizeof(float) * std::max<int64_t>(M.nnz, 1)));
-    L.scan_ws = reinterpret_cast<int32_t*>(take(scan_ws_bytes(rowsmax + 1)));
+    L.scan_ws = reinterpret_cast<int32_t*>(take(scan_ws_bytes(cnt_len)));
     if (c.warm_hidden > 0) {
       L.ustart = reinterpret_cast<float*>(take(sizeof(float) * rowsmax * k));
       L.mlp_ws_bytes = mlp_ws_bytes(static_cast<int>(c.d), static_cast<int>(k), c.warm_hidden, rowsmax, true);
@@ -235,6 +258,49 @@ struct dsanls_ctx {
 namespace {
 
 enum Phase { kPhSketch = 0, kPhProduct = 1, kPhSmall = 2, kPhNnls = 3 };
+
+// Split the rows of a CSR matrix (device rowptr) into segments of at most
+// kCsrSegment nnz and upload the table (init only; synchronous copies).
+dsanls_status build_segments(const int64_t* d_rowptr, int64_t rows, int64_t cap, int64_t multi_cap,
+                             CsrSegments& sg, hipStream_t s) {
+  std::vector<int64_t> rp(rows + 1);
+  DSANLS_HIP(hipMemcpyAsync(rp.data(), d_rowptr, sizeof(int64_t) * (rows + 1), hipMemcpyDeviceToHost, s));
+  DSANLS_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> row, part, mrow, mpart;
+  std::vector<int64_t> beg;
+  row.reserve(rows);
+  beg.reserve(rows);
+  part.reserve(rows);
+  int32_t np = 0;
+  for (int64_t i = 0; i < rows; ++i) {
+    const int64_t len = rp[i + 1] - rp[i];
+    if (len < 0) return fail(DSANLS_E_INVALID_ARG, "CSR rowptr is not non-decreasing");
+    const int64_t ns = len <= kCsrSegment ? 1 : (len + kCsrSegment - 1) / kCsrSegment;
+    if (ns > 1) {
+      mrow.push_back(static_cast<int32_t>(i));
+      mpart.push_back(np);
+    }
+    for (int64_t q = 0; q < ns; ++q) {
+      row.push_back(static_cast<int32_t>(i));
+      beg.push_back(rp[i] + q * kCsrSegment);
+      part.push_back(ns > 1 ? np++ : -1);
+    }
+  }
+  mpart.push_back(np);
+  if (static_cast<int64_t>(row.size()) > cap || static_cast<int64_t>(mrow.size()) > multi_cap)
+    return fail(DSANLS_E_SHAPE, "CSR segment table exceeds its bound (rowptr inconsistent with nnz?)");
+  sg.nseg = static_cast<int64_t>(row.size());
+  sg.nmulti = static_cast<int64_t>(mrow.size());
+  sg.nparts = np;
+  DSANLS_HIP(hipMemcpyAsync(sg.seg_row, row.data(), sizeof(int32_t) * row.size(), hipMemcpyHostToDevice, s));
+  DSANLS_HIP(hipMemcpyAsync(sg.seg_beg, beg.data(), sizeof(int64_t) * beg.size(), hipMemcpyHostToDevice, s));
+  DSANLS_HIP(hipMemcpyAsync(sg.seg_part, part.data(), sizeof(int32_t) * part.size(), hipMemcpyHostToDevice, s));
+  if (!mrow.empty())
+    DSANLS_HIP(hipMemcpyAsync(sg.multi_row, mrow.data(), sizeof(int32_t) * mrow.size(), hipMemcpyHostToDevice, s));
+  DSANLS_HIP(hipMemcpyAsync(sg.multi_part, mpart.data(), sizeof(int32_t) * mpart.size(), hipMemcpyHostToDevice, s));
+  DSANLS_HIP(hipStreamSynchronize(s));
+  return DSANLS_OK;
+}
 
 // Record an event on the stream (start or end of a phase) when timing is on.
 dsanls_status mark(dsanls_ctx* ctx, int phase) {
@@ -353,8 +419,8 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     const bool sub = c.sketch == DSANLS_SKETCH_SUBSAMPLE;
     const float scale = sub ? static_cast<float>(static_cast<double>(lng) / static_cast<double>(d)) : 1.0f;
     CHECK(mark(ctx, kPhProduct));
-    CHECK(launch_csr_sketch_rhs(rowptr, colidx, vals, rows, sub ? L.slot : nullptr, Wother, k, scale,
-                                L.R, s));
+    CHECK(launch_csr_rhs_seg(rowptr, colidx, vals, L.seg[side], sub ? L.slot : nullptr, Wother, k, scale,
+                             L.R, L.seg_partials, s));
     CHECK(mark(ctx, kPhProduct));
   }
   const bool pgd = c.solver == DSANLS_SOLVER_PGD;
@@ -365,9 +431,8 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     // sketched rows a_i of A = X S as CSR: (slot, sqrt(lng/d) * value)
     CHECK(mark(ctx, kPhProduct));
     const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
-    CHECK(launch_csr_hits_count(rowptr, colidx, rows, L.slot, L.a_cnt, s));
-    CHECK(launch_exclusive_scan(L.a_cnt, L.a_rowptr, rows, L.scan_ws, s));
-    CHECK(launch_csr_hits_fill(rowptr, colidx, vals, rows, L.slot, scale, L.a_rowptr, L.a_cols, L.a_vals, s));
+    CHECK(launch_sketched_rows(rowptr, colidx, vals, rows, L.seg[side], L.slot, scale, L.a_cnt, L.a_pos,
+                               L.scan_ws, L.a_rowptr, L.a_cols, L.a_vals, s));
     CHECK(mark(ctx, kPhProduct));
     ctx->rows_kept = rows;
   }
@@ -475,6 +540,12 @@ dsanls_status dsanls_init(const dsanls_config* cfg, const dsanls_matrix* M, floa
     if ((st = launch_combine_partials(L.partials, sumsq_partials(c.m, c.n), 2, L.red, L.err, s)) != DSANLS_OK)
       return bail(st);
   } else {
+    if (M->nnz > INT32_MAX) return bail(fail(DSANLS_E_SHAPE, "CSR input supports nnz < 2^31"));
+    for (int sd = 0; sd < 2; ++sd) {
+      if ((st = build_segments(sd == 0 ? M->rowptr : M->t_rowptr, sd == 0 ? c.m : c.n, L.seg_cap[sd],
+                               L.multi_cap[sd], ctx->L.seg[sd], s)) != DSANLS_OK)
+        return bail(st);
+    }
     const int64_t nnz = std::max<int64_t>(M->nnz, 1);
     if (M->nnz > 0) {
       if ((st = launch_sumsq(M->vals, nnz, 1, nnz, L.partials, s)) != DSANLS_OK) return bail(st);

@@ -121,6 +121,33 @@ dsanls_status launch_nnls(bool pgd, const float* G, const float* R, const float*
                           void* ws, size_t ws_bytes, hipStream_t s, const float* start = nullptr);
 
 // ---------------------------------------------------------------- sparse.hip
+// Longest run of nnz one wave streams in the segmented CSR kernels.
+constexpr int64_t kCsrSegment = 4096;
+// Segment table of a CSR matrix (device arrays, built at init): segment s
+// covers nnz [seg_beg[s], min(seg_beg[s] + kCsrSegment, rowptr[row + 1]))
+// of row seg_row[s]; seg_part[s] = -1 for a single-segment row, else the
+// index of its partial vector.  Rows with several segments are listed in
+// multi_row with their partials [multi_part[i], multi_part[i + 1]).
+struct CsrSegments {
+  int32_t* seg_row = nullptr;
+  int64_t* seg_beg = nullptr;
+  int32_t* seg_part = nullptr;
+  int32_t* multi_row = nullptr;
+  int32_t* multi_part = nullptr;
+  int64_t nseg = 0, nmulti = 0, nparts = 0;
+};
+// Upper bounds used to size the table before it is built.
+inline int64_t csr_seg_bound(int64_t rows, int64_t nnz) { return rows + nnz / kCsrSegment + 1; }
+inline int64_t csr_part_bound(int64_t nnz) { return 2 * (nnz / kCsrSegment) + 2; }
+// Sketched rows a_i of A = X S (subsampling) as CSR over the segment table:
+// seg_cnt and seg_pos hold nseg and nseg + 1 ints, scan_ws scan_ws_bytes(nseg).
+dsanls_status launch_sketched_rows(const int64_t* rowptr, const int32_t* colidx, const float* vals,
+                                   int64_t rows, const CsrSegments& sg, const int32_t* slot, float scale,
+                                   int32_t* seg_cnt, int32_t* seg_pos, int32_t* scan_ws,
+                                   int32_t* a_rowptr, int32_t* a_cols, float* a_vals, hipStream_t s);
+dsanls_status launch_csr_rhs_seg(const int64_t* rowptr, const int32_t* colidx, const float* vals,
+                                 const CsrSegments& sg, const int32_t* slot, const float* W, int64_t k,
+                                 float scale, float* R, float* P, hipStream_t s);
 // R[i, :] = scale * sum_{e in row i, slot[col_e] >= 0} val_e * W[col_e, :]
 // (slot == nullptr: every column).  CSR rows x ncols, W is ncols x k.
 dsanls_status launch_csr_sketch_rhs(const int64_t* rowptr, const int32_t* colidx,

@@ -374,7 +374,7 @@ __device__ __forceinline__ void store_stage_h(unsigned short* __restrict__ s, co
 }
 
 template <int BM, int BN, bool VEC>
-__global__ __launch_bounds__(256, 2) void gemm_nt_bf16_kernel(Problem<unsigned short> p0,
+__global__ __launch_bounds__(256, (BM * BN > 128 * 128 ? 1 : 2)) void gemm_nt_bf16_kernel(Problem<unsigned short> p0,
                                                               Problem<unsigned short> p1) {
   __shared__ __attribute__((aligned(16))) unsigned short sX[2 * BM * kLdsh];
   __shared__ __attribute__((aligned(16))) unsigned short sY[2 * BN * kLdsh];

@@ -105,10 +105,21 @@ __device__ __forceinline__ void load_row(const float* __restrict__ P, int64_t ro
   for (int l = 0; l < KC; ++l) x.b[l / W][l % W] = (valid && l < k) ? p[l] : 0.f;
 }
 
-// q_j = r_j + mu c_j of this lane's row (zero in the padding).
-__device__ __forceinline__ float rhs(const float* __restrict__ R, const float* __restrict__ C,
-                                     int64_t off, int j, int k, float mu, bool valid) {
-  return (valid && j < k) ? R[off + j] + mu * C[off + j] : 0.f;
+// q_j = r_j + mu c_j for the W coordinates of block jb of this lane's row
+// (zero in the padding), loaded once per block so that the per-coordinate
+// access is a register read rather than a strided global load.
+template <int KC, int W>
+__device__ __forceinline__ typename RowBlocks<KC, W>::vec rhs_block(const float* __restrict__ R,
+                                                                     const float* __restrict__ C,
+                                                                     int64_t off, int jb, int k,
+                                                                     float mu, bool valid) {
+  typename RowBlocks<KC, W>::vec q;
+#pragma unroll
+  for (int e = 0; e < W; ++e) {
+    const int j = jb * W + e;
+    q[e] = (valid && j < k) ? R[off + j] + mu * C[off + j] : 0.f;
+  }
+  return q;
 }
 
 // One Gauss-Seidel sweep over the coordinates (Alg. 3 / eq. entry_sol):
@@ -122,13 +133,12 @@ __device__ __forceinline__ void sweep(const float* __restrict__ gp, const float*
   constexpr int NB = RowBlocks<KC, W>::NB;
 #pragma unroll
   for (int jb = 0; jb < NB; ++jb) {
-    constexpr int dummy = 0;
-    (void)dummy;
     const int jn = (jb + 1) * W <= KC ? W : KC - jb * W;
+    const auto qb = rhs_block<KC, W>(R, C, off, jb, k, mu, valid);
 #pragma nounroll
     for (int je = 0; je < jn; ++je) {
       const int j = jb * W + je;
-      const float q = rhs(R, C, off, j, k, mu, valid);
+      const float q = qb[je];
       const float t = dot_row<KC, W>(gp + j * KC, u);
       float v = fmaxf((q - t) * inv[j], 0.f);
       if (upper > 0.f) v = fminf(v, upper);
@@ -150,10 +160,11 @@ __device__ __forceinline__ float kkt(const float* __restrict__ gp, const float* 
 #pragma unroll
   for (int lb = 0; lb < NB; ++lb) {
     const int ln = (lb + 1) * W <= KC ? W : KC - lb * W;
+    const auto qb = rhs_block<KC, W>(R, C, off, lb, k, mu, valid);
 #pragma nounroll
     for (int le = 0; le < ln; ++le) {
       const int l = lb * W + le;
-      const float q = rhs(R, C, off, l, k, mu, valid);
+      const float q = qb[le];
       const float ul = u.b[lb][le];
       float g = dot_row<KC, W>(gp + l * KC, u) + den[l] * ul - q;
       if (!(ul > 0.f)) g = fminf(g, 0.f);
