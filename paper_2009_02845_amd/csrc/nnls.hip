@@ -20,13 +20,14 @@ namespace {
 
 // Prepared Gram: gp[j * KC + l] = G[l][j] for l != j (zero on the diagonal
 // and outside k x k); gdiag[j] = G_jj; den[j] = G_jj + mu; inv[j] =
-// 1 / den[j] (zero in the padding); eta = PGD step.
+// 1 / den[j] (zero in the padding); colsum[j] = sum_l |G_lj| (for the PGD
+// step size).
 struct Prep {
   float* gp;
   float* gdiag;
   float* den;
   float* inv;
-  float* eta;
+  float* colsum;
 };
 
 constexpr int kMaxKC = 128;
@@ -38,43 +39,37 @@ Prep carve_prep(void* ws, int KC) {
   return {p, p + KC * KC, p + KC * KC + KC, p + KC * KC + 2 * KC, p + KC * KC + 3 * KC};
 }
 
-__global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ G, int k, int KC,
-                                                   float mu, float* __restrict__ gp,
-                                                   float* __restrict__ gdiag,
-                                                   float* __restrict__ den,
-                                                   float* __restrict__ inv,
-                                                   float* __restrict__ eta) {
-  __shared__ float colsum[256];
-  for (int i = threadIdx.x; i < KC * KC; i += blockDim.x) {
-    const int j = i / KC, l = i % KC;
-    gp[i] = (j < k && l < k && l != j) ? G[l * k + j] : 0.f;
+// One wave per prepared row j (grid = KC).
+__global__ __launch_bounds__(64) void prep_kernel(const float* __restrict__ G, int k, int KC,
+                                                  float mu, float* __restrict__ gp,
+                                                  float* __restrict__ gdiag,
+                                                  float* __restrict__ den,
+                                                  float* __restrict__ inv,
+                                                  float* __restrict__ colsum) {
+  const int j = blockIdx.x;
+  float sabs = 0.f;
+  for (int l = threadIdx.x; l < KC; l += 64) {
+    const bool in = j < k && l < k;
+    const float g = in ? G[static_cast<int64_t>(l) * k + j] : 0.f;
+    gp[j * KC + l] = l != j ? g : 0.f;
+    sabs += fabsf(g);
   }
-  float best = 0.f;
-  for (int j = threadIdx.x; j < KC; j += blockDim.x) {
+  for (int o = 32; o > 0; o >>= 1) sabs += __shfl_xor(sabs, o, 64);
+  if (threadIdx.x == 0) {
     if (j < k) {
-      const float gj = G[j * k + j];
+      const float gj = G[static_cast<int64_t>(j) * k + j];
       const float dj = gj + mu;
       gdiag[j] = gj;
       den[j] = dj;
       // a zero denominator (G_jj = 0 and mu = 0) leaves the coordinate at 0
       inv[j] = dj != 0.f ? 1.0f / dj : 0.f;
-      float sabs = 0.f;
-      for (int l = 0; l < k; ++l) sabs += fabsf(G[l * k + j]);
-      best = fmaxf(best, sabs);
+      colsum[j] = sabs;
     } else {
       gdiag[j] = 0.f;
       den[j] = 1.f;
       inv[j] = 0.f;
+      colsum[j] = 0.f;
     }
-  }
-  colsum[threadIdx.x] = best;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float L = 0.f;
-    for (int i = 0; i < 256; ++i) L = fmaxf(L, colsum[i]);
-    // eta = 1 / (2 (L + mu)): at most the inverse Lipschitz constant of the
-    // sketched gradient 2 (U G - R), shrinking as mu_t grows.
-    eta[0] = 1.0f / (2.0f * (L + mu));
   }
 }
 
@@ -97,52 +92,160 @@ __device__ __forceinline__ float dot_row(const float* __restrict__ g, const RowB
   return t0 + t1;
 }
 
-template <int KC, int W>
-__device__ __forceinline__ void load_row(const float* __restrict__ P, int64_t row, int k, bool valid,
-                                         RowBlocks<KC, W>& x) {
-  const float* p = P + row * k;
+// The 64 rows of a wave move between HBM and registers through an LDS panel
+// of SW columns (SW divides 64): row r of the panel starts at word r * STR,
+// STR odd, so the 64 lanes reading one column of their own rows hit 64
+// distinct banks, and the global side reads and writes runs of SW
+// consecutive floats per row (64 / SW rows per instruction, coalesced)
+// instead of one strided element per lane.
+template <int SW>
+struct Panel {
+  static_assert(64 % SW == 0, "a load step covers whole panel rows");
+  static constexpr int STR = SW | 1;
+  static constexpr int WORDS = 64 * STR;
+  static constexpr int RPS = 64 / SW;  // panel rows per load step
+};
+
+// panel <- columns [c0, c0 + SW) of rows [row0, row0 + nrows) of the
+// row-major matrix P (row length k), plus mu times the same entries of C
+// when ADD; entries outside the matrix are zero.  Every load is issued
+// before the first LDS write; a load outside the matrix reads the panel's
+// corner instead (in bounds) and is then discarded.
+template <int SW, bool ADD>
+__device__ __forceinline__ void stage(float* __restrict__ panel, const float* __restrict__ P,
+                                      const float* __restrict__ C, float mu, int64_t row0,
+                                      int nrows, int k, int c0) {
+  constexpr int STR = Panel<SW>::STR, RPS = Panel<SW>::RPS;
+  // The inputs do not change during the kernel, so the compiler would hoist
+  // every panel's loads (and their addresses) out of the sweep loop and keep
+  // them all in registers; opaque copies of the corner and the lane index
+  // keep the loads where they are.
+  int64_t corner = row0 * k + c0;
+  int lane = threadIdx.x;
+  asm volatile("" : "+s"(corner));
+  asm volatile("" : "+v"(lane));
+  const int rl = lane / SW, cl = lane % SW;
+  float* dst = panel + rl * STR + cl;
+  if (c0 >= k) {
 #pragma unroll
-  for (int l = 0; l < KC; ++l) x.b[l / W][l % W] = (valid && l < k) ? p[l] : 0.f;
+    for (int s = 0; s < SW; ++s) dst[s * RPS * STR] = 0.f;
+    return;
+  }
+  const char* p = reinterpret_cast<const char*>(P + corner);
+  const char* c = ADD ? reinterpret_cast<const char*>(C + corner) : nullptr;
+  const bool col_ok = c0 + cl < k;
+  const unsigned lane_off = static_cast<unsigned>(rl * k + cl) * 4u;
+  const unsigned step = static_cast<unsigned>(RPS * k) * 4u;
+  float x[SW];
+#pragma unroll
+  for (int s = 0; s < SW; ++s) {
+    const bool ok = col_ok && s * RPS + rl < nrows;
+    const unsigned o = ok ? lane_off + s * step : 0u;
+    float v = *reinterpret_cast<const float*>(p + o);
+    if (ADD) v += mu * *reinterpret_cast<const float*>(c + o);
+    x[s] = ok ? v : 0.f;
+  }
+#pragma unroll
+  for (int s = 0; s < SW; ++s) dst[s * RPS * STR] = x[s];
 }
 
-// q_j = r_j + mu c_j for the W coordinates of block jb of this lane's row
-// (zero in the padding), loaded once per block so that the per-coordinate
-// access is a register read rather than a strided global load.
-template <int KC, int W>
-__device__ __forceinline__ typename RowBlocks<KC, W>::vec rhs_block(const float* __restrict__ R,
-                                                                     const float* __restrict__ C,
-                                                                     int64_t off, int jb, int k,
-                                                                     float mu, bool valid) {
-  typename RowBlocks<KC, W>::vec q;
+// Columns [c0, c0 + SW) of rows [row0, row0 + nrows) of P <- panel.
+template <int SW>
+__device__ __forceinline__ void unstage(const float* __restrict__ panel, float* P, int64_t row0,
+                                        int nrows, int k, int c0) {
+  constexpr int STR = Panel<SW>::STR, RPS = Panel<SW>::RPS;
+  int64_t corner = row0 * k + c0;
+  int lane = threadIdx.x;
+  asm volatile("" : "+s"(corner));
+  asm volatile("" : "+v"(lane));
+  const int rl = lane / SW, cl = lane % SW;
+  if (c0 >= k || c0 + cl >= k) return;
+  const float* src = panel + rl * STR + cl;
+  char* p = reinterpret_cast<char*>(P + corner);
+  const unsigned lane_off = static_cast<unsigned>(rl * k + cl) * 4u;
+  const unsigned step = static_cast<unsigned>(RPS * k) * 4u;
 #pragma unroll
-  for (int e = 0; e < W; ++e) {
-    const int j = jb * W + e;
-    q[e] = (valid && j < k) ? R[off + j] + mu * C[off + j] : 0.f;
+  for (int s = 0; s < SW; ++s)
+    if (s * RPS + rl < nrows) *reinterpret_cast<float*>(p + lane_off + s * step) = src[s * RPS * STR];
+}
+
+// u <- this lane's row of P on the lanes where take holds (the panel load
+// itself is cooperative: every lane of the wave takes part).
+template <int KC, int W, int SW>
+__device__ __forceinline__ void load_rows(float* __restrict__ panel, const float* __restrict__ P,
+                                          int64_t row0, int nrows, int k, bool take,
+                                          RowBlocks<KC, W>& u) {
+  constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
+  const float* mine = panel + threadIdx.x * Panel<SW>::STR;
+#pragma unroll
+  for (int pc = 0; pc < NP; ++pc) {
+    __syncthreads();
+    stage<SW, false>(panel, P, nullptr, 0.f, row0, nrows, k, pc * SW);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPP; ++b) {
+      const int jb = pc * BPP + b;
+      if (jb < NB) {
+#pragma unroll
+        for (int e = 0; e < W; ++e)
+          if (take) u.b[jb][e] = mine[b * W + e];
+      }
+    }
   }
-  return q;
+}
+
+template <int KC, int W, int SW>
+__device__ __forceinline__ void store_rows(float* __restrict__ panel, float* P, int64_t row0,
+                                           int nrows, int k, const RowBlocks<KC, W>& u) {
+  constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
+  float* mine = panel + threadIdx.x * Panel<SW>::STR;
+#pragma unroll
+  for (int pc = 0; pc < NP; ++pc) {
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPP; ++b) {
+      const int jb = pc * BPP + b;
+      if (jb < NB) {
+#pragma unroll
+        for (int e = 0; e < W; ++e) mine[b * W + e] = u.b[jb][e];
+      }
+    }
+    __syncthreads();
+    unstage<SW>(panel, P, row0, nrows, k, pc * SW);
+  }
 }
 
 // One Gauss-Seidel sweep over the coordinates (Alg. 3 / eq. entry_sol):
 // u_j <- max((q_j - sum_{l != j} G_lj u_l) / (G_jj + mu), 0), j ascending,
-// with u_l already updated for l < j.
-template <int KC, int W>
-__device__ __forceinline__ void sweep(const float* __restrict__ gp, const float* __restrict__ inv,
-                                      const float* __restrict__ R, const float* __restrict__ C,
-                                      int64_t off, int k, float mu, bool valid, float upper,
-                                      RowBlocks<KC, W>& u) {
-  constexpr int NB = RowBlocks<KC, W>::NB;
+// with u_l already updated for l < j, q = r + mu c staged one panel at a
+// time.  Only lanes with act set change their row.
+template <int KC, int W, int SW>
+__device__ __forceinline__ void sweep(float* __restrict__ panel, const float* __restrict__ gp,
+                                      const float* __restrict__ inv, const float* __restrict__ R,
+                                      const float* __restrict__ C, int64_t row0, int nrows, int k,
+                                      float mu, float upper, bool act, RowBlocks<KC, W>& u) {
+  constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
+  const float* mine = panel + threadIdx.x * Panel<SW>::STR;
 #pragma unroll
-  for (int jb = 0; jb < NB; ++jb) {
-    const int jn = (jb + 1) * W <= KC ? W : KC - jb * W;
-    const auto qb = rhs_block<KC, W>(R, C, off, jb, k, mu, valid);
+  for (int pc = 0; pc < NP; ++pc) {
+    __syncthreads();
+    stage<SW, true>(panel, R, C, mu, row0, nrows, k, pc * SW);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPP; ++b) {
+      const int jb = pc * BPP + b;
+      if (jb < NB) {
+        const int jn = (jb + 1) * W <= KC ? W : KC - jb * W;
 #pragma nounroll
-    for (int je = 0; je < jn; ++je) {
-      const int j = jb * W + je;
-      const float q = qb[je];
-      const float t = dot_row<KC, W>(gp + j * KC, u);
-      float v = fmaxf((q - t) * inv[j], 0.f);
-      if (upper > 0.f) v = fminf(v, upper);
-      u.b[jb][je] = v;
+        for (int je = 0; je < jn; ++je) {
+          const int j = jb * W + je;
+          const float q = mine[b * W + je];
+          const float t = dot_row<KC, W>(gp + j * KC, u);
+          float v = fmaxf((q - t) * inv[j], 0.f);
+          if (upper > 0.f) v = fminf(v, upper);
+          if (act) u.b[jb][je] = v;
+        }
+      }
     }
   }
 }
@@ -150,34 +253,69 @@ __device__ __forceinline__ void sweep(const float* __restrict__ gp, const float*
 // Relative projected-gradient norm of the row problem
 // min_{u >= 0} 1/2 u Q u^T - q u^T, Q = G + mu I: zero exactly at its
 // minimiser.
-template <int KC, int W>
-__device__ __forceinline__ float kkt(const float* __restrict__ gp, const float* __restrict__ den,
-                                     const float* __restrict__ R, const float* __restrict__ C,
-                                     int64_t off, int k, float mu, bool valid,
-                                     const RowBlocks<KC, W>& u) {
-  constexpr int NB = RowBlocks<KC, W>::NB;
+template <int KC, int W, int SW>
+__device__ __forceinline__ float kkt(float* __restrict__ panel, const float* __restrict__ gp,
+                                     const float* __restrict__ den, const float* __restrict__ R,
+                                     const float* __restrict__ C, int64_t row0, int nrows, int k,
+                                     float mu, const RowBlocks<KC, W>& u) {
+  constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
+  const float* mine = panel + threadIdx.x * Panel<SW>::STR;
   float pg2 = 0.f, q2 = 0.f;
 #pragma unroll
-  for (int lb = 0; lb < NB; ++lb) {
-    const int ln = (lb + 1) * W <= KC ? W : KC - lb * W;
-    const auto qb = rhs_block<KC, W>(R, C, off, lb, k, mu, valid);
+  for (int pc = 0; pc < NP; ++pc) {
+    __syncthreads();
+    stage<SW, true>(panel, R, C, mu, row0, nrows, k, pc * SW);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPP; ++b) {
+      const int lb = pc * BPP + b;
+      if (lb < NB) {
+        const int ln = (lb + 1) * W <= KC ? W : KC - lb * W;
 #pragma nounroll
-    for (int le = 0; le < ln; ++le) {
-      const int l = lb * W + le;
-      const float q = qb[le];
-      const float ul = u.b[lb][le];
-      float g = dot_row<KC, W>(gp + l * KC, u) + den[l] * ul - q;
-      if (!(ul > 0.f)) g = fminf(g, 0.f);
-      if (l < k) {
-        pg2 += g * g;
-        q2 += q * q;
+        for (int le = 0; le < ln; ++le) {
+          const int l = lb * W + le;
+          const float q = mine[b * W + le];
+          const float ul = u.b[lb][le];
+          float g = dot_row<KC, W>(gp + l * KC, u) + den[l] * ul - q;
+          if (!(ul > 0.f)) g = fminf(g, 0.f);
+          if (l < k) {
+            pg2 += g * g;
+            q2 += q * q;
+          }
+        }
       }
     }
   }
   return sqrtf(pg2) / fmaxf(sqrtf(q2), 1e-30f);
 }
 
-template <int KC, int W, bool TO_TOL>
+// Runs sweeps on the lanes whose row is pending (projected-gradient norm
+// above tol) until every row has converged or spent max_sweeps.  The loop
+// is wave-uniform (the panels are loaded by the whole wave); a lane that is
+// done keeps its row.
+template <int KC, int W, int SW>
+__device__ __forceinline__ bool solve_to_tol(float* __restrict__ panel, const float* __restrict__ gp,
+                                             const float* __restrict__ den,
+                                             const float* __restrict__ inv,
+                                             const float* __restrict__ R,
+                                             const float* __restrict__ C, int64_t row0, int nrows,
+                                             int k, float mu, float upper, float tol,
+                                             int max_sweeps, bool live, int& used,
+                                             RowBlocks<KC, W>& u) {
+  const float res0 = kkt<KC, W, SW>(panel, gp, den, R, C, row0, nrows, k, mu, u);
+  bool pending = live && res0 > tol;
+  bool run = pending && used < max_sweeps;
+  while (__any(run)) {
+    sweep<KC, W, SW>(panel, gp, inv, R, C, row0, nrows, k, mu, upper, run, u);
+    if (run) ++used;
+    const float res = kkt<KC, W, SW>(panel, gp, den, R, C, row0, nrows, k, mu, u);
+    if (run) pending = res > tol;
+    run = pending && used < max_sweeps;
+  }
+  return pending;
+}
+
+template <int KC, int W, int SW, bool TO_TOL>
 __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ gp,
                                                      const float* __restrict__ den,
                                                      const float* __restrict__ inv,
@@ -187,55 +325,47 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
                                                      float tol, int max_sweeps, float upper,
                                                      int32_t* __restrict__ sweeps_used,
                                                      unsigned long long* __restrict__ counters) {
-  // C (the proximal centre) may alias U: every lane reads its own row of C
-  // before it writes that row of U, at the end.  start (to-tolerance mode
-  // only) is a warm start; without it the solve starts from U.
-  const int64_t row = blockIdx.x * 64ll + threadIdx.x;
-  const bool valid = row < rows;
-  const int64_t off = row * k;
+  // C (the proximal centre) may alias U: the rows of C are read only before
+  // U is written, at the end.  start (to-tolerance mode only) is a warm
+  // start; without it the solve starts from U.
+  __shared__ float panel[Panel<SW>::WORDS];
+  const int64_t row0 = blockIdx.x * 64ll;
+  const int nrows = static_cast<int>(rows - row0 < 64 ? rows - row0 : 64);
+  const bool valid = static_cast<int>(threadIdx.x) < nrows;
   RowBlocks<KC, W> u;
-  load_row<KC, W>(TO_TOL && start != nullptr ? start : U, row, k, valid, u);
+  load_rows<KC, W, SW>(panel, TO_TOL && start != nullptr ? start : U, row0, nrows, k, true, u);
   int used = 0;
   bool unconverged = false, fell_back = false;
   if (!TO_TOL) {
-    for (int s = 0; s < sweeps; ++s) sweep<KC, W>(gp, inv, R, C, off, k, mu, valid, upper, u);
-    used = sweeps;
-  } else if (valid) {
-    bool ok = true;
+    for (int s = 0; s < sweeps; ++s)
+      sweep<KC, W, SW>(panel, gp, inv, R, C, row0, nrows, k, mu, upper, true, u);
+    used = valid ? sweeps : 0;
+  } else {
+    bool ok = valid;
     if (start != nullptr) {
 #pragma unroll
       for (int l = 0; l < KC; ++l) ok = ok && isfinite(u.b[l / W][l % W]);
     }
-    bool active = ok && kkt<KC, W>(gp, den, R, C, off, k, mu, valid, u) > tol;
-    while (active && used < max_sweeps) {
-      sweep<KC, W>(gp, inv, R, C, off, k, mu, valid, upper, u);
-      ++used;
-      active = kkt<KC, W>(gp, den, R, C, off, k, mu, valid, u) > tol;
-    }
-    if (start != nullptr && (!ok || active)) {
-      // the warm start failed: restart from the cold start, the centre U^t
-      fell_back = true;
-      load_row<KC, W>(C, row, k, valid, u);
+    bool pending = solve_to_tol<KC, W, SW>(panel, gp, den, inv, R, C, row0, nrows, k, mu, upper, tol,
+                                           max_sweeps, ok, used, u);
+    // the warm start failed: restart such rows from the cold start, the
+    // centre U^t
+    const bool fb = start != nullptr && valid && (!ok || pending);
+    if (__any(fb)) {
+      load_rows<KC, W, SW>(panel, C, row0, nrows, k, fb, u);
       int cold = 0;
-      active = kkt<KC, W>(gp, den, R, C, off, k, mu, valid, u) > tol;
-      while (active && cold < max_sweeps) {
-        sweep<KC, W>(gp, inv, R, C, off, k, mu, valid, upper, u);
-        ++cold;
-        active = kkt<KC, W>(gp, den, R, C, off, k, mu, valid, u) > tol;
+      const bool p2 = solve_to_tol<KC, W, SW>(panel, gp, den, inv, R, C, row0, nrows, k, mu, upper,
+                                              tol, max_sweeps, fb, cold, u);
+      if (fb) {
+        used += cold;
+        pending = p2;
       }
-      used += cold;
     }
-    unconverged = active;
+    fell_back = fb;
+    unconverged = pending;
   }
-  if (valid) {
-    float* p = U + off;
-#pragma unroll
-    for (int l = 0; l < KC; ++l)
-      if (l < k) p[l] = u.b[l / W][l % W];
-    if (sweeps_used != nullptr) sweeps_used[row] = used;
-  } else {
-    used = 0;
-  }
+  store_rows<KC, W, SW>(panel, U, row0, nrows, k, u);
+  if (valid && sweeps_used != nullptr) sweeps_used[row0 + threadIdx.x] = used;
   if (counters != nullptr) {
     // wave totals, one integer atomic per wave (exact, order-free)
     unsigned long long a = static_cast<unsigned long long>(used);
@@ -255,58 +385,76 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
 }
 
 // One projected-gradient step (eq. gradient_descent), every coordinate from
-// the old iterate: u_j <- max(u_j - 2 eta ((u G)_j - r_j), 0), written out
-// as it is formed.
-template <int KC, int W>
+// the old iterate: u_j <- max(u_j - 2 eta ((u G)_j - r_j), 0), with
+// eta = 1 / (2 (L + mu)), L = max_j sum_l |G_lj| (at most the inverse
+// Lipschitz constant of the sketched gradient 2 (U G - R)).  The new values
+// replace r in the panel and leave through it.
+template <int KC, int W, int SW>
 __global__ __launch_bounds__(64) void pgd_kernel(const float* __restrict__ gp,
                                                  const float* __restrict__ gdiag,
-                                                 const float* __restrict__ eta_p,
+                                                 const float* __restrict__ colsum,
                                                  const float* __restrict__ R, float* U,
-                                                 int64_t rows, int k, float upper) {
-  const int64_t row = blockIdx.x * 64ll + threadIdx.x;
-  const bool valid = row < rows;
-  const int64_t off = row * k;
+                                                 int64_t rows, int k, float mu, float upper) {
+  constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
+  __shared__ float panel[Panel<SW>::WORDS];
+  const int64_t row0 = blockIdx.x * 64ll;
+  const int nrows = static_cast<int>(rows - row0 < 64 ? rows - row0 : 64);
+  float* mine = panel + threadIdx.x * Panel<SW>::STR;
   RowBlocks<KC, W> u;
-  load_row<KC, W>(U, row, k, valid, u);
-  const float two_eta = 2.0f * eta_p[0];
-  constexpr int NB = RowBlocks<KC, W>::NB;
+  load_rows<KC, W, SW>(panel, U, row0, nrows, k, true, u);
+  float L = 0.f;
 #pragma unroll
-  for (int jb = 0; jb < NB; ++jb) {
-    const int jn = (jb + 1) * W <= KC ? W : KC - jb * W;
+  for (int j = 0; j < KC; ++j) L = fmaxf(L, colsum[j]);
+  const float two_eta = 1.0f / (L + mu);
+#pragma unroll
+  for (int pc = 0; pc < NP; ++pc) {
+    __syncthreads();
+    stage<SW, false>(panel, R, nullptr, 0.f, row0, nrows, k, pc * SW);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPP; ++b) {
+      const int jb = pc * BPP + b;
+      if (jb < NB) {
+        const int jn = (jb + 1) * W <= KC ? W : KC - jb * W;
 #pragma nounroll
-    for (int je = 0; je < jn; ++je) {
-      const int j = jb * W + je;
-      if (j >= k) break;
-      const float uj = u.b[jb][je];
-      const float r = valid ? R[off + j] : 0.f;
-      const float g = dot_row<KC, W>(gp + j * KC, u) + gdiag[j] * uj - r;
-      float v = fmaxf(uj - two_eta * g, 0.f);
-      if (upper > 0.f) v = fminf(v, upper);
-      if (valid) U[off + j] = v;
+        for (int je = 0; je < jn; ++je) {
+          const int j = jb * W + je;
+          const float uj = u.b[jb][je];
+          const float g = dot_row<KC, W>(gp + j * KC, u) + gdiag[j] * uj - mine[b * W + je];
+          float v = fmaxf(uj - two_eta * g, 0.f);
+          if (upper > 0.f) v = fminf(v, upper);
+          mine[b * W + je] = v;
+        }
+      }
     }
+    __syncthreads();
+    unstage<SW>(panel, U, row0, nrows, k, pc * SW);
   }
 }
 
-template <int KC, int W>
+template <int KC, int W, int SW>
 dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, float* U,
                      int64_t rows, int k, float mu, int sweeps, float tol, int max_sweeps,
                      float upper, int32_t* sweeps_used, unsigned long long* counters, void* ws,
                      hipStream_t s, const float* start) {
+  static_assert(SW % W == 0, "a panel holds whole register blocks");
   Prep p = carve_prep(ws, KC);
-  prep_kernel<<<1, 256, 0, s>>>(G, k, KC, mu, p.gp, p.gdiag, p.den, p.inv, p.eta);
+  prep_kernel<<<KC, 64, 0, s>>>(G, k, KC, mu, p.gp, p.gdiag, p.den, p.inv, p.colsum);
   DSANLS_LAUNCHED("prep_kernel");
   if (rows == 0) return DSANLS_OK;
   const unsigned grid = static_cast<unsigned>(ceil_div(rows, 64));
   if (pgd) {
-    pgd_kernel<KC, W><<<grid, 64, 0, s>>>(p.gp, p.gdiag, p.eta, R, U, rows, k, upper);
+    pgd_kernel<KC, W, SW><<<grid, 64, 0, s>>>(p.gp, p.gdiag, p.colsum, R, U, rows, k, mu, upper);
     DSANLS_LAUNCHED("pgd_kernel");
   } else if (sweeps > 0) {
-    prox_cd_kernel<KC, W, false><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, nullptr, U, rows, k, mu,
-                                                     sweeps, tol, max_sweeps, upper, sweeps_used, counters);
+    prox_cd_kernel<KC, W, SW, false><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, nullptr, U, rows, k,
+                                                         mu, sweeps, tol, max_sweeps, upper,
+                                                         sweeps_used, counters);
     DSANLS_LAUNCHED("prox_cd_kernel");
   } else {
-    prox_cd_kernel<KC, W, true><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, start, U, rows, k, mu,
-                                                    sweeps, tol, max_sweeps, upper, sweeps_used, counters);
+    prox_cd_kernel<KC, W, SW, true><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, start, U, rows, k,
+                                                        mu, sweeps, tol, max_sweeps, upper,
+                                                        sweeps_used, counters);
     DSANLS_LAUNCHED("prox_cd_kernel");
   }
   return DSANLS_OK;
@@ -337,20 +485,20 @@ dsanls_status launch_nnls(bool pgd, const float* G, const float* R, const float*
   if (k < 1 || k > kMaxK) return fail(DSANLS_E_UNSUPPORTED, "NNLS supports 1 <= k <= 128");
   if (ws_bytes < nnls_ws_bytes(k)) return fail(DSANLS_E_WORKSPACE, "NNLS workspace too small");
   switch (nnls_kc(k)) {
-#define DSANLS_KC(KC, W)                                                                             \
+#define DSANLS_KC(KC, W, SW)                                                                         \
   case KC:                                                                                           \
-    return run_kc<KC, W>(pgd, G, R, C, U, rows, k, mu, sweeps, tol, max_sweeps, upper, sweeps_used, \
-                         counters, ws, s, start);
-    DSANLS_KC(4, 4)
-    DSANLS_KC(8, 8)
-    DSANLS_KC(10, 16)
-    DSANLS_KC(16, 16)
-    DSANLS_KC(32, 32)
-    DSANLS_KC(48, 16)
-    DSANLS_KC(64, 32)
-    DSANLS_KC(96, 32)
-    DSANLS_KC(100, 32)
-    DSANLS_KC(128, 32)
+    return run_kc<KC, W, SW>(pgd, G, R, C, U, rows, k, mu, sweeps, tol, max_sweeps, upper,          \
+                             sweeps_used, counters, ws, s, start);
+    DSANLS_KC(4, 4, 4)
+    DSANLS_KC(8, 8, 8)
+    DSANLS_KC(10, 16, 16)
+    DSANLS_KC(16, 16, 16)
+    DSANLS_KC(32, 16, 16)
+    DSANLS_KC(48, 16, 16)
+    DSANLS_KC(64, 16, 16)
+    DSANLS_KC(96, 16, 16)
+    DSANLS_KC(100, 8, 16)
+    DSANLS_KC(128, 16, 16)
 #undef DSANLS_KC
   }
   return fail(DSANLS_E_UNSUPPORTED, "NNLS: no kernel for this k");
