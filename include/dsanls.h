@@ -131,7 +131,7 @@ typedef struct {
   int64_t rows_updated;     /* NNLS rows solved                              */
   int64_t sweeps_total;     /* prox-CD row-sweeps run (to-tol mode: counted) */
   int64_t rows_unconverged; /* to-tol rows that hit max_sweeps               */
-  int64_t warm_fallbacks;   /* warm-started rows restarted from U^t          */
+  int64_t warm_fallbacks;   /* warm-start rows that started from U^t instead */
 } dsanls_stats;
 
 /* Size in bytes of the device workspace init needs for (cfg, M). */
@@ -172,10 +172,11 @@ dsanls_status dsanls_get_stats(dsanls_ctx* ctx, dsanls_stats* out);
  * caller-owned, read at each update), with d = cfg.d = cfg.d_prime, k = cfg.k
  * and hidden = cfg.warm_hidden.  With a warm start, each to-tolerance update
  * first forms the sketched rows a_i of A = X S (CSR), runs the network on
- * [a_i; u_i^t] for every row, starts prox-CD from its output with the
- * proximal centre kept at u_i^t, and restarts a row from u_i^t when the
- * warm start is not finite or does not reach tol within max_sweeps
- * (counted in dsanls_stats.warm_fallbacks).
+ * [a_i; u_i^t] for every row and starts prox-CD from its output, with the
+ * proximal centre kept at u_i^t.  A row starts from u_i^t instead when the
+ * network's output is not finite or has the larger relative
+ * projected-gradient norm of the two (counted in
+ * dsanls_stats.warm_fallbacks).
  * Errors: STATE (the context cannot take a warm start), SHAPE. */
 dsanls_status dsanls_set_warm_start(dsanls_ctx* ctx, const float* params, int32_t hidden);
 

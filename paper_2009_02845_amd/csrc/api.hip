@@ -72,6 +72,7 @@ struct Layout {
   float* red = nullptr;             // 64 floats of small results
   int* err = nullptr;               // 16 ints of device flags
   unsigned long long* counters = nullptr;
+  unsigned long long* wave_counts = nullptr;   // 3 per NNLS wave
   size_t total = 0;
 };
 
@@ -171,6 +172,8 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
   L.red = reinterpret_cast<float*>(take(sizeof(float) * 64));
   L.err = reinterpret_cast<int*>(take(sizeof(int) * 16));
   L.counters = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * 8));
+  L.wave_counts = reinterpret_cast<unsigned long long*>(
+      take(sizeof(unsigned long long) * 3 * ((rowsmax + 63) / 64)));
   L.total = off;
   return L;
 }
@@ -447,7 +450,8 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
   CHECK(mark(ctx, kPhNnls));
   CHECK(launch_nnls(pgd, L.G, L.R, Wself, Wself, rows, static_cast<int>(k), static_cast<float>(mu),
                     c.sweeps, static_cast<float>(c.tol), c.max_sweeps, ctx->upper, nullptr,
-                    L.counters, L.nnls_ws, L.nnls_ws_bytes, s, start));
+                    L.counters, L.wave_counts, L.nnls_ws, L.nnls_ws_bytes, s, start));
+  if (!pgd && c.sweeps > 0) ctx->stats.sweeps_total += rows * c.sweeps;
   CHECK(mark(ctx, kPhNnls));
   if (ctx->timing) ctx->timed_updates += 1;
 #undef CHECK
@@ -634,7 +638,7 @@ dsanls_status dsanls_get_stats(dsanls_ctx* ctx, dsanls_stats* out) {
   DSANLS_HIP(hipMemcpyAsync(cnt, ctx->L.counters, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
   DSANLS_HIP(hipStreamSynchronize(ctx->stream));
   *out = ctx->stats;
-  out->sweeps_total = static_cast<int64_t>(cnt[0]);
+  out->sweeps_total = ctx->stats.sweeps_total + static_cast<int64_t>(cnt[0]);
   out->rows_unconverged = static_cast<int64_t>(cnt[1]);
   out->warm_fallbacks = static_cast<int64_t>(cnt[2]);
   return DSANLS_OK;

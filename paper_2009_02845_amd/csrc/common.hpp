@@ -111,14 +111,18 @@ dsanls_status launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, 
 // ---------------------------------------------------------------- nnls.hip
 size_t nnls_ws_bytes(int k);
 // pgd = false: prox-CD (sweeps >= 1, or 0 = to tol); pgd = true: one PGD step.
-// counters (may be null): [0] += row-sweeps run, [1] += rows left unconverged.
+// counters (may be null; to-tolerance mode only): [0] += row-sweeps run,
+// [1] += rows left unconverged, [2] += rows that started from the centre C
+// although a warm start was given; wave_counts (3 * ceil(rows / 64)
+// entries) holds the per-wave counts that are summed into counters.
 // start (may be null: start from U) is a warm start for the to-tolerance
-// mode; rows whose warm start does not converge within max_sweeps, or is
-// not finite, restart from the centre C (counters[2] += 1 per such row).
+// mode; a row starts from C instead when its warm start is not finite or
+// has the larger projected-gradient norm.
 dsanls_status launch_nnls(bool pgd, const float* G, const float* R, const float* C, float* U,
                           int64_t rows, int k, float mu, int sweeps, float tol, int max_sweeps,
                           float upper, int32_t* sweeps_used, unsigned long long* counters,
-                          void* ws, size_t ws_bytes, hipStream_t s, const float* start = nullptr);
+                          unsigned long long* wave_counts, void* ws, size_t ws_bytes,
+                          hipStream_t s, const float* start = nullptr);
 
 // ---------------------------------------------------------------- sparse.hip
 // Longest run of nnz one wave streams in the segmented CSR kernels.

@@ -9,9 +9,10 @@
 // its dot product take G as a scalar operand: 64 rows share every G value
 // and no lane reads G through LDS.  The coordinate loop runs at run time
 // inside each (statically unrolled) block, so the one dynamic register
-// access per coordinate, u_j <- new value, is an indexed register move.
-// The per-row right-hand side q_j = r_j + mu c_j is loaded per coordinate
-// (the load is issued ahead of the dot product that hides it).
+// access per coordinate, u_j <- new value, is an indexed register write.
+// Rows of U and of the right-hand side q = r + mu c move between HBM and
+// the lanes through LDS panels of SW columns, loaded and stored by the
+// whole wave with coalesced row runs.
 #include "common.hpp"
 
 namespace dsanls {
@@ -131,19 +132,31 @@ __device__ __forceinline__ void stage(float* __restrict__ panel, const float* __
     for (int s = 0; s < SW; ++s) dst[s * RPS * STR] = 0.f;
     return;
   }
-  const char* p = reinterpret_cast<const char*>(P + corner);
-  const char* c = ADD ? reinterpret_cast<const char*>(C + corner) : nullptr;
-  const bool col_ok = c0 + cl < k;
+  const float* p = P + corner;
+  const float* c = ADD ? C + corner : nullptr;
   const unsigned lane_off = static_cast<unsigned>(rl * k + cl) * 4u;
-  const unsigned step = static_cast<unsigned>(RPS * k) * 4u;
+  const int64_t step = static_cast<int64_t>(RPS) * k;
   float x[SW];
+  if (nrows == 64 && c0 + SW <= k) {
+    // whole panel inside the matrix: a wave-uniform row base per step plus
+    // the lane's 32-bit byte offset
 #pragma unroll
-  for (int s = 0; s < SW; ++s) {
-    const bool ok = col_ok && s * RPS + rl < nrows;
-    const unsigned o = ok ? lane_off + s * step : 0u;
-    float v = *reinterpret_cast<const float*>(p + o);
-    if (ADD) v += mu * *reinterpret_cast<const float*>(c + o);
-    x[s] = ok ? v : 0.f;
+    for (int s = 0; s < SW; ++s) {
+      float v = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(p + s * step) + lane_off);
+      if (ADD) v += mu * *reinterpret_cast<const float*>(reinterpret_cast<const char*>(c + s * step) + lane_off);
+      x[s] = v;
+    }
+  } else {
+    const bool col_ok = c0 + cl < k;
+    const unsigned bstep = static_cast<unsigned>(step) * 4u;
+#pragma unroll
+    for (int s = 0; s < SW; ++s) {
+      const bool ok = col_ok && s * RPS + rl < nrows;
+      const unsigned o = ok ? lane_off + s * bstep : 0u;
+      float v = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(p) + o);
+      if (ADD) v += mu * *reinterpret_cast<const float*>(reinterpret_cast<const char*>(c) + o);
+      x[s] = ok ? v : 0.f;
+    }
   }
 #pragma unroll
   for (int s = 0; s < SW; ++s) dst[s * RPS * STR] = x[s];
@@ -218,12 +231,13 @@ __device__ __forceinline__ void store_rows(float* __restrict__ panel, float* P, 
 // One Gauss-Seidel sweep over the coordinates (Alg. 3 / eq. entry_sol):
 // u_j <- max((q_j - sum_{l != j} G_lj u_l) / (G_jj + mu), 0), j ascending,
 // with u_l already updated for l < j, q = r + mu c staged one panel at a
-// time.  Only lanes with act set change their row.
+// time, clipped at ub (+inf without a bound).  Only lanes with act set
+// change their row.
 template <int KC, int W, int SW>
 __device__ __forceinline__ void sweep(float* __restrict__ panel, const float* __restrict__ gp,
                                       const float* __restrict__ inv, const float* __restrict__ R,
                                       const float* __restrict__ C, int64_t row0, int nrows, int k,
-                                      float mu, float upper, bool act, RowBlocks<KC, W>& u) {
+                                      float mu, float ub, bool act, RowBlocks<KC, W>& u) {
   constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
   const float* mine = panel + threadIdx.x * Panel<SW>::STR;
 #pragma unroll
@@ -241,8 +255,7 @@ __device__ __forceinline__ void sweep(float* __restrict__ panel, const float* __
           const int j = jb * W + je;
           const float q = mine[b * W + je];
           const float t = dot_row<KC, W>(gp + j * KC, u);
-          float v = fmaxf((q - t) * inv[j], 0.f);
-          if (upper > 0.f) v = fminf(v, upper);
+          const float v = fminf(fmaxf((q - t) * inv[j], 0.f), ub);
           if (act) u.b[jb][je] = v;
         }
       }
@@ -289,32 +302,6 @@ __device__ __forceinline__ float kkt(float* __restrict__ panel, const float* __r
   return sqrtf(pg2) / fmaxf(sqrtf(q2), 1e-30f);
 }
 
-// Runs sweeps on the lanes whose row is pending (projected-gradient norm
-// above tol) until every row has converged or spent max_sweeps.  The loop
-// is wave-uniform (the panels are loaded by the whole wave); a lane that is
-// done keeps its row.
-template <int KC, int W, int SW>
-__device__ __forceinline__ bool solve_to_tol(float* __restrict__ panel, const float* __restrict__ gp,
-                                             const float* __restrict__ den,
-                                             const float* __restrict__ inv,
-                                             const float* __restrict__ R,
-                                             const float* __restrict__ C, int64_t row0, int nrows,
-                                             int k, float mu, float upper, float tol,
-                                             int max_sweeps, bool live, int& used,
-                                             RowBlocks<KC, W>& u) {
-  const float res0 = kkt<KC, W, SW>(panel, gp, den, R, C, row0, nrows, k, mu, u);
-  bool pending = live && res0 > tol;
-  bool run = pending && used < max_sweeps;
-  while (__any(run)) {
-    sweep<KC, W, SW>(panel, gp, inv, R, C, row0, nrows, k, mu, upper, run, u);
-    if (run) ++used;
-    const float res = kkt<KC, W, SW>(panel, gp, den, R, C, row0, nrows, k, mu, u);
-    if (run) pending = res > tol;
-    run = pending && used < max_sweeps;
-  }
-  return pending;
-}
-
 template <int KC, int W, int SW, bool TO_TOL>
 __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ gp,
                                                      const float* __restrict__ den,
@@ -324,7 +311,7 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
                                                      int64_t rows, int k, float mu, int sweeps,
                                                      float tol, int max_sweeps, float upper,
                                                      int32_t* __restrict__ sweeps_used,
-                                                     unsigned long long* __restrict__ counters) {
+                                                     unsigned long long* __restrict__ wave_counts) {
   // C (the proximal centre) may alias U: the rows of C are read only before
   // U is written, at the end.  start (to-tolerance mode only) is a warm
   // start; without it the solve starts from U.
@@ -332,42 +319,61 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
   const int64_t row0 = blockIdx.x * 64ll;
   const int nrows = static_cast<int>(rows - row0 < 64 ? rows - row0 : 64);
   const bool valid = static_cast<int>(threadIdx.x) < nrows;
+  const float ub = upper > 0.f ? upper : INFINITY;
   RowBlocks<KC, W> u;
   load_rows<KC, W, SW>(panel, TO_TOL && start != nullptr ? start : U, row0, nrows, k, true, u);
   int used = 0;
   bool unconverged = false, fell_back = false;
   if (!TO_TOL) {
     for (int s = 0; s < sweeps; ++s)
-      sweep<KC, W, SW>(panel, gp, inv, R, C, row0, nrows, k, mu, upper, true, u);
+      sweep<KC, W, SW>(panel, gp, inv, R, C, row0, nrows, k, mu, ub, true, u);
     used = valid ? sweeps : 0;
   } else {
+    // Sweeps run on the lanes whose row is pending (projected-gradient norm
+    // above tol) until every row has converged or spent max_sweeps; the
+    // loop is wave-uniform (the panels are loaded by the whole wave) and a
+    // lane that is done keeps its row.  With a warm start, each row starts
+    // from whichever of the warm start and the cold start (the centre U^t)
+    // has the smaller projected-gradient norm; a start that is not finite
+    // is never taken.
     bool ok = valid;
     if (start != nullptr) {
 #pragma unroll
       for (int l = 0; l < KC; ++l) ok = ok && isfinite(u.b[l / W][l % W]);
     }
-    bool pending = solve_to_tol<KC, W, SW>(panel, gp, den, inv, R, C, row0, nrows, k, mu, upper, tol,
-                                           max_sweeps, ok, used, u);
-    // the warm start failed: restart such rows from the cold start, the
-    // centre U^t
-    const bool fb = start != nullptr && valid && (!ok || pending);
-    if (__any(fb)) {
-      load_rows<KC, W, SW>(panel, C, row0, nrows, k, fb, u);
-      int cold = 0;
-      const bool p2 = solve_to_tol<KC, W, SW>(panel, gp, den, inv, R, C, row0, nrows, k, mu, upper,
-                                              tol, max_sweeps, fb, cold, u);
-      if (fb) {
-        used += cold;
-        pending = p2;
-      }
+    float res_w = 0.f, res_c = 0.f;
+    const int ncand = start != nullptr ? 2 : 1;
+#pragma nounroll
+    for (int c = 0; c < ncand; ++c) {
+      if (c == 1) load_rows<KC, W, SW>(panel, C, row0, nrows, k, true, u);
+      const float r = kkt<KC, W, SW>(panel, gp, den, R, C, row0, nrows, k, mu, u);
+      if (c == 0) res_w = r;
+      else res_c = r;
     }
-    fell_back = fb;
-    unconverged = pending;
+    float res = res_w;
+    if (start != nullptr) {
+      const bool warm = ok && res_w < res_c;
+      fell_back = valid && !warm;
+      if (__any(warm)) load_rows<KC, W, SW>(panel, start, row0, nrows, k, warm, u);
+      res = warm ? res_w : res_c;
+    }
+    bool pend = false;
+    for (;;) {
+      if (valid) pend = res > tol;
+      const bool run = valid && pend && used < max_sweeps;
+      if (!__any(run)) break;
+      sweep<KC, W, SW>(panel, gp, inv, R, C, row0, nrows, k, mu, ub, run, u);
+      if (run) ++used;
+      res = kkt<KC, W, SW>(panel, gp, den, R, C, row0, nrows, k, mu, u);
+    }
+    unconverged = pend;
   }
   store_rows<KC, W, SW>(panel, U, row0, nrows, k, u);
   if (valid && sweeps_used != nullptr) sweeps_used[row0 + threadIdx.x] = used;
-  if (counters != nullptr) {
-    // wave totals, one integer atomic per wave (exact, order-free)
+  if (TO_TOL && wave_counts != nullptr) {
+    // wave totals, stored per wave and summed by count_reduce_kernel (one
+    // atomic per wave on three shared addresses serialises in L2 and stalls
+    // the loads of every other wave behind it)
     unsigned long long a = static_cast<unsigned long long>(used);
     unsigned long long b = unconverged ? 1ull : 0ull;
     unsigned long long f = fell_back ? 1ull : 0ull;
@@ -377,10 +383,33 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
       f += __shfl_down(f, o, 64);
     }
     if (threadIdx.x == 0) {
-      atomicAdd(&counters[0], a);
-      atomicAdd(&counters[1], b);
-      atomicAdd(&counters[2], f);
+      unsigned long long* w = wave_counts + 3 * static_cast<int64_t>(blockIdx.x);
+      w[0] = a;
+      w[1] = b;
+      w[2] = f;
     }
+  }
+}
+
+// counters[c] += sum over waves of wave_counts[3 w + c] (one block).
+__global__ __launch_bounds__(256) void count_reduce_kernel(const unsigned long long* __restrict__ wave_counts,
+                                                           int64_t nwaves,
+                                                           unsigned long long* __restrict__ counters) {
+  __shared__ unsigned long long part[3][256];
+  unsigned long long a = 0, b = 0, f = 0;
+  for (int64_t w = threadIdx.x; w < nwaves; w += 256) {
+    a += wave_counts[3 * w];
+    b += wave_counts[3 * w + 1];
+    f += wave_counts[3 * w + 2];
+  }
+  part[0][threadIdx.x] = a;
+  part[1][threadIdx.x] = b;
+  part[2][threadIdx.x] = f;
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    unsigned long long t = 0;
+    for (int i = 0; i < 256; ++i) t += part[threadIdx.x][i];
+    counters[threadIdx.x] += t;
   }
 }
 
@@ -406,6 +435,7 @@ __global__ __launch_bounds__(64) void pgd_kernel(const float* __restrict__ gp,
 #pragma unroll
   for (int j = 0; j < KC; ++j) L = fmaxf(L, colsum[j]);
   const float two_eta = 1.0f / (L + mu);
+  const float ub = upper > 0.f ? upper : INFINITY;
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
     __syncthreads();
@@ -421,9 +451,7 @@ __global__ __launch_bounds__(64) void pgd_kernel(const float* __restrict__ gp,
           const int j = jb * W + je;
           const float uj = u.b[jb][je];
           const float g = dot_row<KC, W>(gp + j * KC, u) + gdiag[j] * uj - mine[b * W + je];
-          float v = fmaxf(uj - two_eta * g, 0.f);
-          if (upper > 0.f) v = fminf(v, upper);
-          mine[b * W + je] = v;
+          mine[b * W + je] = fminf(fmaxf(uj - two_eta * g, 0.f), ub);
         }
       }
     }
@@ -435,8 +463,8 @@ __global__ __launch_bounds__(64) void pgd_kernel(const float* __restrict__ gp,
 template <int KC, int W, int SW>
 dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, float* U,
                      int64_t rows, int k, float mu, int sweeps, float tol, int max_sweeps,
-                     float upper, int32_t* sweeps_used, unsigned long long* counters, void* ws,
-                     hipStream_t s, const float* start) {
+                     float upper, int32_t* sweeps_used, unsigned long long* counters,
+                     unsigned long long* wave_counts, void* ws, hipStream_t s, const float* start) {
   static_assert(SW % W == 0, "a panel holds whole register blocks");
   Prep p = carve_prep(ws, KC);
   prep_kernel<<<KC, 64, 0, s>>>(G, k, KC, mu, p.gp, p.gdiag, p.den, p.inv, p.colsum);
@@ -449,13 +477,18 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
   } else if (sweeps > 0) {
     prox_cd_kernel<KC, W, SW, false><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, nullptr, U, rows, k,
                                                          mu, sweeps, tol, max_sweeps, upper,
-                                                         sweeps_used, counters);
+                                                         sweeps_used, nullptr);
     DSANLS_LAUNCHED("prox_cd_kernel");
   } else {
+    const bool count = counters != nullptr && wave_counts != nullptr;
     prox_cd_kernel<KC, W, SW, true><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, start, U, rows, k,
                                                         mu, sweeps, tol, max_sweeps, upper,
-                                                        sweeps_used, counters);
+                                                        sweeps_used, count ? wave_counts : nullptr);
     DSANLS_LAUNCHED("prox_cd_kernel");
+    if (count) {
+      count_reduce_kernel<<<1, 256, 0, s>>>(wave_counts, static_cast<int64_t>(grid), counters);
+      DSANLS_LAUNCHED("count_reduce_kernel");
+    }
   }
   return DSANLS_OK;
 }
@@ -481,14 +514,15 @@ size_t nnls_ws_bytes(int k) {
 dsanls_status launch_nnls(bool pgd, const float* G, const float* R, const float* C, float* U,
                           int64_t rows, int k, float mu, int sweeps, float tol, int max_sweeps,
                           float upper, int32_t* sweeps_used, unsigned long long* counters,
-                          void* ws, size_t ws_bytes, hipStream_t s, const float* start) {
+                          unsigned long long* wave_counts, void* ws, size_t ws_bytes,
+                          hipStream_t s, const float* start) {
   if (k < 1 || k > kMaxK) return fail(DSANLS_E_UNSUPPORTED, "NNLS supports 1 <= k <= 128");
   if (ws_bytes < nnls_ws_bytes(k)) return fail(DSANLS_E_WORKSPACE, "NNLS workspace too small");
   switch (nnls_kc(k)) {
 #define DSANLS_KC(KC, W, SW)                                                                         \
   case KC:                                                                                           \
     return run_kc<KC, W, SW>(pgd, G, R, C, U, rows, k, mu, sweeps, tol, max_sweeps, upper,          \
-                             sweeps_used, counters, ws, s, start);
+                             sweeps_used, counters, wave_counts, ws, s, start);
     DSANLS_KC(4, 4, 4)
     DSANLS_KC(8, 8, 8)
     DSANLS_KC(10, 16, 16)
@@ -497,7 +531,7 @@ dsanls_status launch_nnls(bool pgd, const float* G, const float* R, const float*
     DSANLS_KC(48, 16, 16)
     DSANLS_KC(64, 16, 16)
     DSANLS_KC(96, 16, 16)
-    DSANLS_KC(100, 8, 16)
+    DSANLS_KC(100, 16, 16)
     DSANLS_KC(128, 16, 16)
 #undef DSANLS_KC
   }
@@ -522,7 +556,7 @@ extern "C" dsanls_status dsanls_nnls_prox_cd(const float* G, const float* R, con
   if (sweeps < 0 || (sweeps == 0 && (max_sweeps < 1 || !(tol >= 0.f))) || !(mu >= 0.f))
     return fail(DSANLS_E_INVALID_ARG, "nnls_prox_cd: bad sweeps/tol/mu");
   return launch_nnls(false, G, R, C, U, rows, k, mu, sweeps, tol, max_sweeps, upper, sweeps_used,
-                     nullptr, workspace, workspace_bytes, static_cast<hipStream_t>(hip_stream));
+                     nullptr, nullptr, workspace, workspace_bytes, static_cast<hipStream_t>(hip_stream));
 }
 
 extern "C" dsanls_status dsanls_pgd_step(const float* G, const float* R, float* U, int64_t rows,
@@ -530,6 +564,6 @@ extern "C" dsanls_status dsanls_pgd_step(const float* G, const float* R, float* 
                                          size_t workspace_bytes, void* hip_stream) {
   if (rows < 0 || !G || (rows > 0 && (!R || !U)) || !workspace || !(mu >= 0.f))
     return fail(DSANLS_E_INVALID_ARG, "pgd_step: bad arguments");
-  return launch_nnls(true, G, R, nullptr, U, rows, k, mu, 1, 0.f, 1, upper, nullptr, nullptr,
+  return launch_nnls(true, G, R, nullptr, U, rows, k, mu, 1, 0.f, 1, upper, nullptr, nullptr, nullptr,
                      workspace, workspace_bytes, static_cast<hipStream_t>(hip_stream));
 }

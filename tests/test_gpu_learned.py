@@ -121,8 +121,7 @@ def test_sketched_rows_match_oracle(env):
 
 def test_warm_start_reaches_the_cold_solution(env):
     # the regularised row problem has a unique minimiser (mu > 0): warm and
-    # cold to-tolerance solves agree to the tolerance; a network that outputs
-    # NaN falls back to the cold start on every row
+    # cold to-tolerance solves agree to the tolerance
     torch, Bd = env
     m, n, k, d, h = 700, 500, 10, 80, 32
     cold, M64, Uc, Vc, U0, V0 = _sparse_ctx(env, m, n, k, d, 9)
@@ -136,13 +135,15 @@ def test_warm_start_reaches_the_cold_solution(env):
         assert _rel(Vw.cpu().numpy(), Vc.cpu().numpy()) < 1e-3
     st = warm.stats()
     assert st["warm_fallbacks"] < st["rows_updated"]
-    for poison in ("nan", "inf"):
+    # a start that is not finite, or finite but farther from optimal than
+    # U^t (every prediction 1e3), is never taken: every row starts from U^t
+    for poison in ("nan", "inf", "far"):
         bad = p.clone()
         if poison == "nan":
             bad[:] = float("nan")
         else:
             bad[:] = 0.0
-            bad[-k:] = float("inf")          # output bias: every prediction is +inf
+            bad[-k:] = float("inf") if poison == "inf" else 1e3   # output bias
         Uw.copy_(Uc)
         Vw.copy_(Vc)
         warm.set_warm_start(bad, h)
