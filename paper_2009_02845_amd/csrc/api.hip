@@ -54,7 +54,9 @@ struct Layout {
   int32_t* slot = nullptr;
   // sketched rows of A (CSR input, subsampling): counts, offsets, entries
   int32_t* a_cnt = nullptr;         // per-row or per-segment counts
-  int32_t* a_pos = nullptr;         // per-segment start positions
+  int32_t* a_pos = nullptr;         // per-segment start positions / column offsets
+  int32_t* long_rows = nullptr;     // rows of A longer than a lane sorts
+  int32_t* nlong = nullptr;
   int32_t* a_rowptr = nullptr;
   int32_t* a_cols = nullptr;
   float* a_vals = nullptr;
@@ -159,6 +161,8 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
     L.a_cols = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * std::max<int64_t>(M.nnz, 1)));
     L.a_vals = reinterpret_cast<float*>(take(sizeof(float) * std::max<int64_t>(M.nnz, 1)));
     L.scan_ws = reinterpret_cast<int32_t*>(take(scan_ws_bytes(cnt_len)));
+    L.long_rows = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * rowsmax));
+    L.nlong = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 4));
     if (c.warm_hidden > 0) {
       L.ustart = reinterpret_cast<float*>(take(sizeof(float) * rowsmax * k));
       L.mlp_ws_bytes = mlp_ws_bytes(static_cast<int>(c.d), static_cast<int>(k), c.warm_hidden, rowsmax, true);
@@ -420,18 +424,36 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
   } else {
     CHECK(mark(ctx, kPhSmall));
     const bool sub = c.sketch == DSANLS_SKETCH_SUBSAMPLE;
-    const float scale = sub ? static_cast<float>(static_cast<double>(lng) / static_cast<double>(d)) : 1.0f;
+    ctx->rows_kept = -1;
     CHECK(mark(ctx, kPhProduct));
-    CHECK(launch_csr_rhs_seg(rowptr, colidx, vals, L.seg[side], sub ? L.slot : nullptr, Wother, k, scale,
-                             L.R, L.seg_partials, s));
+    if (sub && d <= kGatherMaxD && ctx->mat.nnz < (int64_t{1} << 31)) {
+      // sketched rows a_i of A = X S (slot, sqrt(lng/d) * value) from the
+      // sampled columns of X, i.e. rows idx of X^T, then R = A B^T with
+      // B = sqrt(lng/d) W[idx]^T
+      const int64_t* xt_rowptr = side == 0 ? ctx->mat.t_rowptr : ctx->mat.rowptr;
+      const int32_t* xt_colidx = side == 0 ? ctx->mat.t_colidx : ctx->mat.colidx;
+      const float* xt_vals = side == 0 ? ctx->mat.t_vals : ctx->mat.vals;
+      const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
+      CHECK(launch_sampled_rows(xt_rowptr, xt_colidx, xt_vals, rows, L.idx, d, scale, L.a_cnt, L.a_pos,
+                                L.scan_ws, L.a_rowptr, L.a_cols, L.a_vals, L.long_rows, L.nlong, s));
+      CHECK(launch_a_rhs(L.a_rowptr, L.a_cols, L.a_vals, rows, L.idx, Wother, k, scale, L.long_rows, L.nlong, L.R,
+                         s));
+      ctx->rows_kept = rows;
+    } else {
+      // the CSR stream: every nnz of X, the sampled ones (or all, identity)
+      // folded into R
+      const float scale = sub ? static_cast<float>(static_cast<double>(lng) / static_cast<double>(d)) : 1.0f;
+      CHECK(launch_csr_rhs_seg(rowptr, colidx, vals, L.seg[side], sub ? L.slot : nullptr, Wother, k, scale,
+                               L.R, L.seg_partials, s));
+    }
     CHECK(mark(ctx, kPhProduct));
   }
   const bool pgd = c.solver == DSANLS_SOLVER_PGD;
   const bool warm = ctx->warm != nullptr && !is_dense && c.sketch == DSANLS_SKETCH_SUBSAMPLE &&
                     !pgd && c.sweeps == 0;
-  ctx->rows_kept = -1;
-  if (!is_dense && c.sketch == DSANLS_SKETCH_SUBSAMPLE && (warm || ctx->keep_rows)) {
-    // sketched rows a_i of A = X S as CSR: (slot, sqrt(lng/d) * value)
+  if (is_dense) ctx->rows_kept = -1;
+  if (!is_dense && c.sketch == DSANLS_SKETCH_SUBSAMPLE && (warm || ctx->keep_rows) && ctx->rows_kept < 0) {
+    // sketched rows from the CSR stream (d too large for the gather)
     CHECK(mark(ctx, kPhProduct));
     const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
     CHECK(launch_sketched_rows(rowptr, colidx, vals, rows, L.seg[side], L.slot, scale, L.a_cnt, L.a_pos,

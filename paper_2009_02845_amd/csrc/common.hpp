@@ -145,6 +145,25 @@ inline int64_t csr_seg_bound(int64_t rows, int64_t nnz) { return rows + nnz / kC
 inline int64_t csr_part_bound(int64_t nnz) { return 2 * (nnz / kCsrSegment) + 2; }
 // Sketched rows a_i of A = X S (subsampling) as CSR over the segment table:
 // seg_cnt and seg_pos hold nseg and nseg + 1 ints, scan_ws scan_ws_bytes(nseg).
+// Largest sketch size d of the sampled-column gather (a row of A then
+// holds at most d entries, which one workgroup sorts in LDS).
+constexpr int64_t kGatherMaxD = 4096;
+// Sketched rows A = X S (CSR, int32 offsets, values scaled) of a
+// subsampling sketch, gathered from the rows idx[0..d) of X^T
+// (t_rowptr/t_colidx/t_vals).  Rows longer than 8 entries leave sorted by
+// slot; launch_a_rhs sorts the others.  Needs nnz(X) < 2^31 and
+// d <= kGatherMaxD.
+// cnt: rows + 1 ints; offs: d + 1 ints; long_rows: rows ints; nlong: 1 int.
+dsanls_status launch_sampled_rows(const int64_t* t_rowptr, const int32_t* t_colidx, const float* t_vals,
+                                  int64_t rows, const int32_t* idx, int64_t d, float scale, int32_t* cnt,
+                                  int32_t* offs, int32_t* scan_ws, int32_t* a_rowptr, int32_t* a_cols,
+                                  float* a_vals, int32_t* long_rows, int32_t* nlong, hipStream_t s);
+// R[i, :] = scale * sum_e a_vals[e] W[idx[a_cols[e]], :] over row i of A, in
+// slot order; sorts (in place) the rows launch_sampled_rows left unsorted;
+// long_rows/nlong are launch_sampled_rows' list of the rows it sorted.
+dsanls_status launch_a_rhs(const int32_t* a_rowptr, int32_t* a_cols, float* a_vals, int64_t rows,
+                           const int32_t* idx, const float* W, int64_t k, float scale, const int32_t* long_rows,
+                           const int32_t* nlong, float* R, hipStream_t s);
 dsanls_status launch_sketched_rows(const int64_t* rowptr, const int32_t* colidx, const float* vals,
                                    int64_t rows, const CsrSegments& sg, const int32_t* slot, float scale,
                                    int32_t* seg_cnt, int32_t* seg_pos, int32_t* scan_ws,

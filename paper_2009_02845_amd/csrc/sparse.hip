@@ -353,6 +353,311 @@ __global__ __launch_bounds__(256) void csr_cross_kernel(const int64_t* __restric
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Sampled-column gather.  The sketched rows A = X S of a subsampling sketch
+// hold only the sampled columns X[:, idx[c]] (scaled), and column idx[c] of X
+// is row idx[c] of the transposed CSR: reading those rows touches about d/n
+// of the nnz instead of streaming all of them.  The entries are bucketed by
+// row (count, scan, fill), then every row is sorted by slot c (= ascending
+// column of X, the subsample being in index order), which makes the result
+// independent of the order the atomics ran in.
+
+// Rows of A with up to kShortRow entries are sorted by a_rhs_kernel itself
+// (one lane each, in registers); longer ones (at most d <= kLongCap) by
+// row_sort_long_kernel first.
+constexpr int kShortRow = 8;
+constexpr int kLongCap = 4096;
+
+// len[c] = nnz of column idx[c] of X (row idx[c] of X^T).
+__global__ __launch_bounds__(256) void gather_len_kernel(const int64_t* __restrict__ t_rowptr,
+                                                         const int32_t* __restrict__ idx, int d,
+                                                         int32_t* __restrict__ len) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c < d) len[c] = static_cast<int32_t>(t_rowptr[idx[c] + 1] - t_rowptr[idx[c]]);
+}
+
+__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += gridDim.x * 256ll) p[i] = v;
+}
+
+// Walks the E = offs[d] sampled entries as one flat range, 64 per wave step
+// (offs = exclusive scan of len): COUNT adds one to cnt[row] per entry; the
+// fill pass takes a slot of its row from the back (cnt counts down), writes
+// (c, scale * value) there and lists the rows longer than kShortRow.
+template <bool COUNT>
+__global__ __launch_bounds__(256) void gather_entries_kernel(const int64_t* __restrict__ t_rowptr,
+                                                             const int32_t* __restrict__ t_colidx,
+                                                             const float* __restrict__ t_vals,
+                                                             const int32_t* __restrict__ idx,
+                                                             const int32_t* __restrict__ offs, int d,
+                                                             int32_t* __restrict__ cnt,
+                                                             const int32_t* __restrict__ a_rowptr,
+                                                             int32_t* __restrict__ a_cols,
+                                                             float* __restrict__ a_vals, float scale,
+                                                             int32_t* __restrict__ long_rows,
+                                                             int32_t* __restrict__ nlong) {
+  const int lane = threadIdx.x & 63;
+  const int32_t E = offs[d];
+  const int64_t step = static_cast<int64_t>(gridDim.x) * 4;
+  for (int64_t tile = blockIdx.x * 4ll + (threadIdx.x >> 6); tile * 64 < E; tile += step) {
+    const int32_t fb = static_cast<int32_t>(tile * 64);
+    // column of the tile's first entry: the last c with offs[c] <= fb
+    int lo = 0, hi = d - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (offs[mid] <= fb) lo = mid;
+      else hi = mid - 1;
+    }
+    const int32_t f = fb + lane;
+    if (f >= E) continue;
+    int c = lo;
+    while (offs[c + 1] <= f) ++c;
+    const int64_t e = t_rowptr[idx[c]] + (f - offs[c]);
+    const int32_t row = t_colidx[e];
+    if (COUNT) {
+      atomicAdd(&cnt[row], 1);
+    } else {
+      const int32_t left = atomicSub(&cnt[row], 1) - 1;
+      const int32_t pos = a_rowptr[row] + left;
+      a_cols[pos] = c;
+      a_vals[pos] = scale * t_vals[e];
+      // the entry that takes a row's last free slot lists the row if it is
+      // longer than a_rhs_kernel sorts itself
+      if (left == 0 && a_rowptr[row + 1] - a_rowptr[row] > kShortRow) long_rows[atomicAdd(nlong, 1)] = row;
+    }
+  }
+}
+
+// Listed rows (kShortRow < length <= kLongCap): one workgroup per row, a
+// bitonic sort of (slot, value) by slot in LDS; the workgroups walk the list.
+__global__ __launch_bounds__(256) void row_sort_long_kernel(const int32_t* __restrict__ a_rowptr,
+                                                            int32_t* __restrict__ a_cols,
+                                                            float* __restrict__ a_vals,
+                                                            const int32_t* __restrict__ long_rows,
+                                                            const int32_t* __restrict__ nlong) {
+  __shared__ int32_t key[kLongCap];
+  __shared__ float val[kLongCap];
+  const int n_long = *nlong;
+  for (int r = blockIdx.x; r < n_long; r += gridDim.x) {
+    const int32_t i = long_rows[r];
+    const int32_t b = a_rowptr[i], n = a_rowptr[i + 1] - b;
+    if (n > kLongCap) continue;   // only with duplicate entries in a CSR row
+    int P = 1;
+    while (P < n) P <<= 1;
+    __syncthreads();
+    for (int t = threadIdx.x; t < P; t += 256) {
+      key[t] = t < n ? a_cols[b + t] : 0x7fffffff;
+      val[t] = t < n ? a_vals[b + t] : 0.f;
+    }
+    for (int size = 2; size <= P; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < (P >> 1); t += 256) {
+          const int lo = 2 * stride * (t / stride) + (t % stride), hi = lo + stride;
+          const bool up = (lo & size) == 0;
+          if ((key[lo] > key[hi]) == up) {
+            const int32_t kt = key[lo];
+            key[lo] = key[hi];
+            key[hi] = kt;
+            const float vt = val[lo];
+            val[lo] = val[hi];
+            val[hi] = vt;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n; t += 256) {
+      a_cols[b + t] = key[t];
+      a_vals[b + t] = val[t];
+    }
+  }
+}
+
+// R[i, :] = scale * sum over row i of A, in slot order, of a_vals[e] *
+// W[idx[a_cols[e]], :] (W row-major, row length k <= 128), 64 rows per wave
+// and the lanes over the columns of R (lane, lane + 64).
+//  * A row of at most kShortRow entries arrives in fill order: its lane
+//    sorts it in registers (odd-even transposition), writes it back (so A
+//    leaves sorted) and puts (W row, value, row) into the wave's flat entry
+//    list in LDS, rows in order.  The wave walks the list four entries at a
+//    time, the four W rows loaded before their FMAs, and writes each R row
+//    (zero for a row without short entries) when the list moves past it.
+//  * A longer row (listed and sorted by row_sort_long_kernel) gets a zero
+//    row here and its value from a_rhs_long_kernel afterwards.
+__global__ __launch_bounds__(256) void a_rhs_kernel(const int32_t* __restrict__ a_rowptr,
+                                                    int32_t* __restrict__ a_cols,
+                                                    float* __restrict__ a_vals, int64_t rows,
+                                                    const int32_t* __restrict__ idx,
+                                                    const float* __restrict__ W, int k, float scale,
+                                                    float* __restrict__ R) {
+  __shared__ int32_t s_j[4][64 * kShortRow];
+  __shared__ float s_v[4][64 * kShortRow];
+  __shared__ int32_t s_r[4][64 * kShortRow];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t row0 = (blockIdx.x * 4ll + w) * 64;
+  if (row0 >= rows) return;   // whole waves only; no block barrier below
+  const int nrows = static_cast<int>(rows - row0 < 64 ? rows - row0 : 64);
+  int32_t b = 0, n = 0;
+  if (lane < nrows) {
+    b = a_rowptr[row0 + lane];
+    n = a_rowptr[row0 + lane + 1] - b;
+  }
+  const bool is_short = n <= kShortRow;
+  const int ns = is_short ? n : 0;
+  int32_t c[kShortRow];
+  float v[kShortRow];
+  // unconditional loads (entry q clamped into the row, or the lane's row
+  // start, always inside A) so that they are all in flight at once
+#pragma unroll
+  for (int q = 0; q < kShortRow; ++q) {
+    const int32_t e = b + (q < ns ? q : 0);
+    const int32_t cq = a_cols[e];
+    const float vq = a_vals[e];
+    c[q] = q < ns ? cq : 0x7fffffff;
+    v[q] = q < ns ? vq : 0.f;
+  }
+#pragma unroll
+  for (int round = 0; round < kShortRow; ++round) {
+#pragma unroll
+    for (int q = round & 1; q + 1 < kShortRow; q += 2) {
+      if (c[q] > c[q + 1]) {
+        const int32_t ct = c[q];
+        c[q] = c[q + 1];
+        c[q + 1] = ct;
+        const float vt = v[q];
+        v[q] = v[q + 1];
+        v[q + 1] = vt;
+      }
+    }
+  }
+  // flat offset of this lane's entries: exclusive scan of ns over the lanes
+  int incl = ns;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const int off = incl - ns;
+  const int total = __shfl(incl, 63, 64);
+#pragma unroll
+  for (int q = 0; q < kShortRow; ++q) {
+    if (q < ns) {
+      if (ns > 1) {
+        a_cols[b + q] = c[q];
+        a_vals[b + q] = v[q];
+      }
+      s_j[w][off + q] = idx[c[q]];
+      s_v[w][off + q] = v[q];
+      s_r[w][off + q] = lane;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const bool in0 = lane < k, in1 = lane + 64 < k;
+  const int col0 = in0 ? lane : k - 1, col1 = in1 ? lane + 64 : k - 1;   // in-row load columns
+  float* Rw = R + row0 * k;
+  float a0 = 0.f, a1 = 0.f;
+  int cur = 0;   // next R row of the wave to write
+  for (int t0 = 0; t0 < total; t0 += 4) {
+    float x0[4], x1[4], vv[4];
+    int rr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = t0 + q < total ? t0 + q : t0;
+      const float* wr = W + static_cast<int64_t>(s_j[w][t]) * k;
+      const float y0 = wr[col0], y1 = wr[col1];
+      x0[q] = in0 ? y0 : 0.f;
+      x1[q] = in1 ? y1 : 0.f;
+      vv[q] = s_v[w][t];
+      rr[q] = __builtin_amdgcn_readfirstlane(s_r[w][t]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (t0 + q < total) {
+        while (cur < rr[q]) {
+          if (in0) Rw[static_cast<int64_t>(cur) * k + lane] = scale * a0;
+          if (in1) Rw[static_cast<int64_t>(cur) * k + lane + 64] = scale * a1;
+          a0 = a1 = 0.f;
+          ++cur;
+        }
+        a0 += vv[q] * x0[q];
+        a1 += vv[q] * x1[q];
+      }
+    }
+  }
+  while (cur < nrows) {
+    if (in0) Rw[static_cast<int64_t>(cur) * k + lane] = scale * a0;
+    if (in1) Rw[static_cast<int64_t>(cur) * k + lane + 64] = scale * a1;
+    a0 = a1 = 0.f;
+    ++cur;
+  }
+}
+
+// R rows of the listed (long, sorted) rows of A: one workgroup per row, the
+// row's entries split into four consecutive quarters, one per wave; a wave
+// loads 64 entries at a time (slot, value, W row), then walks them with the
+// lanes over the columns of R, eight W rows in flight.  The four partial
+// sums are added in wave order, so the result depends only on the row.
+__global__ __launch_bounds__(256) void a_rhs_long_kernel(const int32_t* __restrict__ a_rowptr,
+                                                         const int32_t* __restrict__ a_cols,
+                                                         const float* __restrict__ a_vals,
+                                                         const int32_t* __restrict__ idx,
+                                                         const float* __restrict__ W, int k, float scale,
+                                                         const int32_t* __restrict__ long_rows,
+                                                         const int32_t* __restrict__ nlong,
+                                                         float* __restrict__ R) {
+  __shared__ float part[4][128];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const bool in0 = lane < k, in1 = lane + 64 < k;
+  const int col0 = in0 ? lane : k - 1, col1 = in1 ? lane + 64 : k - 1;
+  const int n_long = *nlong;
+  for (int li = blockIdx.x; li < n_long; li += gridDim.x) {
+    const int32_t row = long_rows[li];
+    const int32_t rb = a_rowptr[row], n = a_rowptr[row + 1] - rb;
+    const int32_t q4 = (n + 3) / 4;
+    const int32_t beg = rb + (w * q4 < n ? w * q4 : n), end = rb + ((w + 1) * q4 < n ? (w + 1) * q4 : n);
+    float a0 = 0.f, a1 = 0.f;
+    for (int32_t e0 = beg; e0 < end; e0 += 64) {
+      const int cn = end - e0 < 64 ? end - e0 : 64;
+      const int32_t e = e0 + (lane < cn ? lane : 0);
+      const int32_t j = idx[a_cols[e]];
+      const float v = a_vals[e];
+      for (int r0 = 0; r0 < cn; r0 += 8) {
+        float x0[8], x1[8], vv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int r = r0 + q < cn ? r0 + q : r0;
+          const float* wr = W + static_cast<int64_t>(__shfl(j, r, 64)) * k;
+          const float y0 = wr[col0], y1 = wr[col1];
+          x0[q] = in0 ? y0 : 0.f;
+          x1[q] = in1 ? y1 : 0.f;
+          vv[q] = r0 + q < cn ? __shfl(v, r, 64) : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (r0 + q < cn) {
+            a0 += vv[q] * x0[q];
+            a1 += vv[q] * x1[q];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    part[w][lane] = a0;
+    part[w][lane + 64] = a1;
+    __syncthreads();
+    if (w == 0) {
+      const float s0 = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+      const float s1 = ((part[0][lane + 64] + part[1][lane + 64]) + part[2][lane + 64]) + part[3][lane + 64];
+      if (in0) R[static_cast<int64_t>(row) * k + lane] = scale * s0;
+      if (in1) R[static_cast<int64_t>(row) * k + lane + 64] = scale * s1;
+    }
+  }
+}
+
 }  // namespace
 
 dsanls_status launch_csr_sketch_rhs(const int64_t* rowptr, const int32_t* colidx, const float* vals,
@@ -380,6 +685,52 @@ dsanls_status launch_csr_rhs_seg(const int64_t* rowptr, const int32_t* colidx, c
         sg.multi_row, sg.multi_part, sg.nmulti, static_cast<int>(k), scale, P, R);
     DSANLS_LAUNCHED("csr_rhs_fixup_kernel");
   }
+  return DSANLS_OK;
+}
+
+
+dsanls_status launch_sampled_rows(const int64_t* t_rowptr, const int32_t* t_colidx, const float* t_vals,
+                                  int64_t rows, const int32_t* idx, int64_t d, float scale, int32_t* cnt,
+                                  int32_t* offs, int32_t* scan_ws, int32_t* a_rowptr, int32_t* a_cols,
+                                  float* a_vals, int32_t* long_rows, int32_t* nlong, hipStream_t s) {
+  if (d < 1 || d > kGatherMaxD) return fail(DSANLS_E_UNSUPPORTED, "sampled-column gather needs 1 <= d <= 4096");
+  // column lengths (into a_rowptr, free until the row scan) -> offs
+  gather_len_kernel<<<static_cast<unsigned>(ceil_div(d, 256)), 256, 0, s>>>(t_rowptr, idx, static_cast<int>(d),
+                                                                           a_rowptr);
+  DSANLS_LAUNCHED("gather_len_kernel");
+  dsanls_status st = launch_exclusive_scan(a_rowptr, offs, d, scan_ws, s);
+  if (st != DSANLS_OK) return st;
+  const unsigned zg = static_cast<unsigned>(std::min<int64_t>(ceil_div(rows + 1, 256), 4096));
+  fill_i32_kernel<<<zg, 256, 0, s>>>(cnt, rows + 1, 0);
+  DSANLS_LAUNCHED("fill_i32_kernel");
+  fill_i32_kernel<<<1, 256, 0, s>>>(nlong, 1, 0);
+  DSANLS_LAUNCHED("fill_i32_kernel");
+  const unsigned eg = 2048;
+  gather_entries_kernel<true><<<eg, 256, 0, s>>>(t_rowptr, t_colidx, t_vals, idx, offs, static_cast<int>(d), cnt,
+                                                 nullptr, nullptr, nullptr, scale, nullptr, nullptr);
+  DSANLS_LAUNCHED("gather_entries_kernel");
+  if ((st = launch_exclusive_scan(cnt, a_rowptr, rows, scan_ws, s)) != DSANLS_OK) return st;
+  gather_entries_kernel<false><<<eg, 256, 0, s>>>(t_rowptr, t_colidx, t_vals, idx, offs, static_cast<int>(d), cnt,
+                                                  a_rowptr, a_cols, a_vals, scale, long_rows, nlong);
+  DSANLS_LAUNCHED("gather_entries_kernel");
+  if (rows > 0) {
+    row_sort_long_kernel<<<1024, 256, 0, s>>>(a_rowptr, a_cols, a_vals, long_rows, nlong);
+    DSANLS_LAUNCHED("row_sort_long_kernel");
+  }
+  return DSANLS_OK;
+}
+
+dsanls_status launch_a_rhs(const int32_t* a_rowptr, int32_t* a_cols, float* a_vals, int64_t rows,
+                           const int32_t* idx, const float* W, int64_t k, float scale, const int32_t* long_rows,
+                           const int32_t* nlong, float* R, hipStream_t s) {
+  if (rows <= 0) return DSANLS_OK;
+  if (k > 128) return fail(DSANLS_E_UNSUPPORTED, "CSR path supports k <= 128");
+  a_rhs_kernel<<<static_cast<unsigned>(ceil_div(rows, 256)), 256, 0, s>>>(a_rowptr, a_cols, a_vals, rows, idx, W,
+                                                                         static_cast<int>(k), scale, R);
+  DSANLS_LAUNCHED("a_rhs_kernel");
+  a_rhs_long_kernel<<<1024, 256, 0, s>>>(a_rowptr, a_cols, a_vals, idx, W, static_cast<int>(k), scale, long_rows,
+                                         nlong, R);
+  DSANLS_LAUNCHED("a_rhs_long_kernel");
   return DSANLS_OK;
 }
 

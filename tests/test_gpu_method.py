@@ -241,6 +241,80 @@ def test_sparse_per_update_parity(env, sketch):
     assert abs(prob.solver.objective() - O.relative_error(M64, U, V)) / O.relative_error(M64, U, V) < 1e-5
 
 
+def _skewed_sparse(m, n, k, seed):
+    # Zipf-like column popularity, a few fully dense rows and columns, empty
+    # rows and many empty columns: sampled columns of every length (0 to m)
+    # and rows of the sketched matrix longer than one lane sorts
+    g = np.random.default_rng(seed)
+    nnz = 6 * m
+    pop = 1.0 / np.arange(1, n + 1) ** 1.1
+    cols = g.choice(n, size=nnz, p=pop / pop.sum())
+    rows = g.integers(0, m, size=nnz)
+    dense_rows = np.repeat(g.choice(m, 3, replace=False), n)
+    dense_cols = np.tile(np.arange(n), 3)
+    dc = np.repeat(g.choice(n, 2, replace=False), m)
+    dr = np.tile(np.arange(m), 2)
+    r = np.concatenate([rows, dense_rows, dr])
+    c = np.concatenate([cols, dense_cols, dc])
+    Ms = sp.csr_matrix((g.lognormal(0, 1, r.size), (r, c)), shape=(m, n))
+    Ms.sum_duplicates()
+    Ms.sort_indices()
+    empty = g.choice(m, m // 10, replace=False)
+    empty_c = g.choice(n, n // 10, replace=False)
+    Ms = sp.diags(np.isin(np.arange(m), empty, invert=True).astype(np.float64)) @ Ms
+    Ms = Ms @ sp.diags(np.isin(np.arange(n), empty_c, invert=True).astype(np.float64))
+    Ms = Ms.tocsr()
+    Ms.eliminate_zeros()
+    Ms.sort_indices()
+    U0, V0 = synth.init_factors(m, n, k, seed, dtype=np.float64)
+    return Ms, U0, V0
+
+
+@pytest.mark.parametrize("m,n,d,dp", [(1500, 900, 200, 300), (400, 6000, 4500, 300)])
+def test_sparse_subsample_skewed_parity(env, m, n, d, dp):
+    # d <= 4096: sampled rows gathered through CSR(X^T); d = 4500 on the U
+    # side: the CSR stream
+    k = 12
+    Ms, U0, V0 = _skewed_sparse(m, n, k, 8)
+    ocfg = _ocfg(k, d, dp, O.SKETCH_SUBSAMPLE, O.SOLVER_PROX_CD, alpha=0.5, beta=0.5, seed=3)
+    prob = Sparse(env, Ms, U0, V0, ocfg)
+    M64 = Ms.astype(np.float32).astype(np.float64).tocsr()
+    U, V = U0.astype(np.float32).astype(np.float64), V0.astype(np.float32).astype(np.float64)
+    for t in range(2):
+        prob.set(U, V)
+        prob.solver.update_U(t)
+        Ug, _ = prob.get()
+        Uo = O.update_U(M64, U, V, t, ocfg)
+        assert _rel(Ug, Uo) < 1e-4
+        prob.set(Uo, V)
+        prob.solver.update_V(t)
+        _, Vg = prob.get()
+        Vo = O.update_V(M64, Uo, V, t, ocfg)
+        assert _rel(Vg, Vo) < 1e-4
+        U, V = Uo, Vo
+
+
+def test_sparse_sketched_rows_skewed(env):
+    # the gathered rows of A = M S equal the oracle's, slots ascending, also
+    # for the near-dense rows and the empty ones
+    torch, B = env
+    m, n, k, d = 1500, 900, 12, 200
+    Ms, U0, V0 = _skewed_sparse(m, n, k, 9)
+    ocfg = _ocfg(k, d, 300, O.SKETCH_SUBSAMPLE, O.SOLVER_PROX_CD, seed=5)
+    prob = Sparse(env, Ms, U0, V0, ocfg)
+    prob.solver.keep_sketched_rows(True)
+    prob.solver.update_U(2)
+    sel = np.arange(m, dtype=np.int32)
+    rp, cols, vals = prob.solver.gather_sketched_rows(torch.from_numpy(sel).cuda(), capacity=Ms.nnz)
+    A = (Ms.astype(np.float32).astype(np.float64) @ P.subsample_sketch(5, 2, 0, n, d)).tocsr()
+    A.sort_indices()
+    got = sp.csr_matrix((vals.cpu().numpy().astype(np.float64), cols.cpu().numpy(), rp.cpu().numpy()),
+                        shape=(m, d))
+    assert np.array_equal(got.indptr, A.indptr) and np.array_equal(got.indices, A.indices)
+    assert np.allclose(got.data, A.data, rtol=1e-6, atol=0)
+    assert np.diff(A.indptr).max() > 16   # rows sorted by the workgroup path
+
+
 def test_sparse_subsample_fetch_indices(env):
     Ms, U0, V0 = _sparse_problem(500, 400, 0.02, 8, 6)
     ocfg = _ocfg(8, 50, 60, O.SKETCH_SUBSAMPLE, O.SOLVER_PROX_CD, seed=17)
