@@ -339,6 +339,10 @@ typedef unsigned short ushortx8 __attribute__((ext_vector_type(8)));
 
 constexpr int kBKh = 64;
 constexpr int kLdsh = kBKh + 8;
+// BF16 block tile: four waves of 128 x 128 (4 x 4 MFMA tiles each), so that
+// every fragment read from LDS feeds four MFMAs: LDS reads 64 B/clk per CU
+// at the MFMA rate (a 64 x 64 wave tile needs 128 B/clk, the whole LDS port).
+constexpr int kBMh = 256, kBNh = 256;
 
 template <int NV, bool VEC>
 __device__ __forceinline__ void load_stage_h(const unsigned short* __restrict__ P, int64_t ld, int r0,
@@ -543,13 +547,13 @@ dsanls_status launch_residual_sq(const float* M, int64_t ldm, const float* U, co
 namespace {
 
 template <typename T>
-bool make_problem(const GemmDesc& g, int elems_per_vec, Problem<T>& p, bool& vec) {
+bool make_problem(const GemmDesc& g, int elems_per_vec, Problem<T>& p, bool& vec, int bm = 128, int bn = 128) {
   if (g.rows <= 0 || g.cols <= 0) {
     p = Problem<T>{nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 1, 0};
     return true;
   }
   if (g.rows > INT32_MAX || g.cols > INT32_MAX || g.K > INT32_MAX) return false;
-  const int tm = static_cast<int>(ceil_div(g.rows, 128)), tn = static_cast<int>(ceil_div(g.cols, 128));
+  const int tm = static_cast<int>(ceil_div(g.rows, bm)), tn = static_cast<int>(ceil_div(g.cols, bn));
   p = Problem<T>{static_cast<const T*>(g.X), g.ldx, static_cast<const T*>(g.Y), g.ldy, g.C, g.ldc,
                  static_cast<int>(g.rows), static_cast<int>(g.cols), static_cast<int>(g.K), tn, tm * tn};
   vec = vec && (g.ldx % elems_per_vec == 0) && (g.ldy % elems_per_vec == 0) &&
@@ -568,14 +572,14 @@ dsanls_status launch_gemm_grouped(const GemmDesc& a_in, const GemmDesc& b_in, bo
   bool vec = true;
   if (bf16) {
     Problem<unsigned short> p0, p1;
-    if (!make_problem(a, 8, p0, vec) || !make_problem(b, 8, p1, vec))
+    if (!make_problem(a, 8, p0, vec, kBMh, kBNh) || !make_problem(b, 8, p1, vec, kBMh, kBNh))
       return fail(DSANLS_E_SHAPE, "gemm: dimension exceeds int32");
     if (p0.ntiles + p1.ntiles == 0) return DSANLS_OK;
     const int grid = grouped_grid(p0.ntiles, p1.ntiles);
     if (vec)
-      gemm_nt_bf16_kernel<128, 128, true><<<grid, 256, 0, s>>>(p0, p1);
+      gemm_nt_bf16_kernel<kBMh, kBNh, true><<<grid, 256, 0, s>>>(p0, p1);
     else
-      gemm_nt_bf16_kernel<128, 128, false><<<grid, 256, 0, s>>>(p0, p1);
+      gemm_nt_bf16_kernel<kBMh, kBNh, false><<<grid, 256, 0, s>>>(p0, p1);
     DSANLS_LAUNCHED("gemm_nt_bf16_kernel");
     return DSANLS_OK;
   }

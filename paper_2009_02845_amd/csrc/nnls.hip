@@ -10,9 +10,10 @@
 // and no lane reads G through LDS.  The coordinate loop runs at run time
 // inside each (statically unrolled) block, so the one dynamic register
 // access per coordinate, u_j <- new value, is an indexed register write.
-// Rows of U and of the right-hand side q = r + mu c move between HBM and
-// the lanes through LDS panels of SW columns, loaded and stored by the
-// whole wave with coalesced row runs.
+// Rows of U move between HBM and the lanes through LDS panels of SW
+// columns, loaded and stored by the whole wave with coalesced row runs; the
+// right-hand side q = r + mu c streams into LDS one panel ahead of the
+// coordinates that use it.
 #include "common.hpp"
 
 namespace dsanls {
@@ -182,6 +183,88 @@ __device__ __forceinline__ void unstage(const float* __restrict__ panel, float* 
     if (s * RPS + rl < nrows) *reinterpret_cast<float*>(p + lane_off + s * step) = src[s * RPS * STR];
 }
 
+// The right-hand side q = r + mu c of the sweeps and the KKT test moves in
+// panels of SW columns straight from HBM into LDS (global_load_lds_dword:
+// no registers in between), one panel ahead of the coordinates that use
+// it: the lanes read panel pc into registers, then issue panel pc + 1 into
+// the same LDS and work through the coordinates of pc while it arrives.
+// Lane l of load step s writes LDS word 64 s + l, i.e. row r = RPS s + l / SW
+// of the panel at slot l % SW, which holds column (l % SW) ^ f(r): the
+// swizzle f makes the 64 lanes reading one column of their own rows hit 64
+// distinct banks (and 32 distinct within each half-wave).
+template <int SW>
+__device__ __forceinline__ int swz(int r) {
+  constexpr int RPS = Panel<SW>::RPS;
+  return (r / RPS) ^ ((SW / 2) * ((2 * r / RPS) & 1));
+}
+
+template <int SW>
+struct QPanel {
+  float r[64 * SW];
+  float c[64 * SW];
+};
+
+// The compiler does not order the LDS reads of a panel after its
+// global_load_lds writes (nor the next panel's writes after the reads), so
+// the two waits are explicit, and compiler barriers too.
+__device__ __forceinline__ void wait_lds_reads() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void wait_panel_loads() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Between the LDS writes and reads of one wave (the workgroup is one wave)
+// a wait for the wave's own LDS traffic is enough: no barrier, and no wait
+// for its global stores still in flight.
+__device__ __forceinline__ void lds_order() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Issue the loads of columns [c0, c0 + SW) of rows [row0, row0 + nrows) of R
+// and C into qp.  An entry outside the matrix loads the panel's corner
+// instead (in bounds; its q is never used: padding coordinates have
+// 1 / (G_jj + mu) = 0 and rows past nrows are not stored).
+template <int SW>
+__device__ __forceinline__ void q_issue(QPanel<SW>& qp, const float* __restrict__ R,
+                                        const float* __restrict__ C, int64_t row0, int nrows, int k,
+                                        int c0) {
+  constexpr int RPS = Panel<SW>::RPS;
+  if (c0 >= k) return;
+  // opaque copies, or the compiler hoists every panel's addresses out of the
+  // sweep loop and keeps them all in registers
+  int64_t corner = row0 * k + c0;
+  int lane = threadIdx.x;
+  asm volatile("" : "+s"(corner));
+  asm volatile("" : "+v"(lane));
+  const float* rb = R + corner;
+  const float* cb = C + corner;
+#pragma unroll
+  for (int s = 0; s < SW; ++s) {
+    const int r = RPS * s + lane / SW;
+    const int c = (lane % SW) ^ swz<SW>(r);
+    const int off = r < nrows && c0 + c < k ? r * k + c : 0;
+    __builtin_amdgcn_global_load_lds(rb + off, qp.r + 64 * s, 4, 0, 0);
+    __builtin_amdgcn_global_load_lds(cb + off, qp.c + 64 * s, 4, 0, 0);
+  }
+}
+
+// q[e] = r + mu c of this lane's row at panel column e.
+template <int SW>
+__device__ __forceinline__ void q_read(const QPanel<SW>& qp, float mu, int c0, int k,
+                                       typename RowBlocks<SW, SW>::vec& q) {
+  int lane = threadIdx.x;
+  asm volatile("" : "+v"(lane));
+  const int f = swz<SW>(lane);
+  wait_panel_loads();
+  if (c0 >= k) {
+#pragma unroll
+    for (int e = 0; e < SW; ++e) q[e] = 0.f;
+    return;
+  }
+  float x[SW], y[SW];
+#pragma unroll
+  for (int e = 0; e < SW; ++e) {
+    x[e] = qp.r[SW * lane + (e ^ f)];
+    y[e] = qp.c[SW * lane + (e ^ f)];
+  }
+#pragma unroll
+  for (int e = 0; e < SW; ++e) q[e] = x[e] + mu * y[e];
+}
+
 // u <- this lane's row of P on the lanes where take holds (the panel load
 // itself is cooperative: every lane of the wave takes part).
 template <int KC, int W, int SW>
@@ -192,9 +275,9 @@ __device__ __forceinline__ void load_rows(float* __restrict__ panel, const float
   const float* mine = panel + threadIdx.x * Panel<SW>::STR;
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
-    __syncthreads();
+    lds_order();
     stage<SW, false>(panel, P, nullptr, 0.f, row0, nrows, k, pc * SW);
-    __syncthreads();
+    lds_order();
 #pragma unroll
     for (int b = 0; b < BPP; ++b) {
       const int jb = pc * BPP + b;
@@ -214,7 +297,7 @@ __device__ __forceinline__ void store_rows(float* __restrict__ panel, float* P, 
   float* mine = panel + threadIdx.x * Panel<SW>::STR;
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
-    __syncthreads();
+    lds_order();
 #pragma unroll
     for (int b = 0; b < BPP; ++b) {
       const int jb = pc * BPP + b;
@@ -223,28 +306,30 @@ __device__ __forceinline__ void store_rows(float* __restrict__ panel, float* P, 
         for (int e = 0; e < W; ++e) mine[b * W + e] = u.b[jb][e];
       }
     }
-    __syncthreads();
+    lds_order();
     unstage<SW>(panel, P, row0, nrows, k, pc * SW);
   }
 }
 
 // One Gauss-Seidel sweep over the coordinates (Alg. 3 / eq. entry_sol):
 // u_j <- max((q_j - sum_{l != j} G_lj u_l) / (G_jj + mu), 0), j ascending,
-// with u_l already updated for l < j, q = r + mu c staged one panel at a
-// time, clipped at ub (+inf without a bound).  Only lanes with act set
-// change their row.
+// with u_l already updated for l < j, q = r + mu c one panel at a time,
+// clipped at ub (+inf without a bound).  Only lanes with act set change
+// their row.
 template <int KC, int W, int SW>
-__device__ __forceinline__ void sweep(float* __restrict__ panel, const float* __restrict__ gp,
+__device__ __forceinline__ void sweep(QPanel<SW>& qp, const float* __restrict__ gp,
                                       const float* __restrict__ inv, const float* __restrict__ R,
                                       const float* __restrict__ C, int64_t row0, int nrows, int k,
                                       float mu, float ub, bool act, RowBlocks<KC, W>& u) {
   constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
-  const float* mine = panel + threadIdx.x * Panel<SW>::STR;
+  wait_lds_reads();
+  q_issue<SW>(qp, R, C, row0, nrows, k, 0);
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
-    __syncthreads();
-    stage<SW, true>(panel, R, C, mu, row0, nrows, k, pc * SW);
-    __syncthreads();
+    typename RowBlocks<SW, SW>::vec qb;
+    q_read<SW>(qp, mu, pc * SW, k, qb);
+    wait_lds_reads();
+    if (pc + 1 < NP) q_issue<SW>(qp, R, C, row0, nrows, k, (pc + 1) * SW);
 #pragma unroll
     for (int b = 0; b < BPP; ++b) {
       const int jb = pc * BPP + b;
@@ -253,7 +338,7 @@ __device__ __forceinline__ void sweep(float* __restrict__ panel, const float* __
 #pragma nounroll
         for (int je = 0; je < jn; ++je) {
           const int j = jb * W + je;
-          const float q = mine[b * W + je];
+          const float q = qb[b * W + je];
           const float t = dot_row<KC, W>(gp + j * KC, u);
           const float v = fminf(fmaxf((q - t) * inv[j], 0.f), ub);
           if (act) u.b[jb][je] = v;
@@ -267,18 +352,20 @@ __device__ __forceinline__ void sweep(float* __restrict__ panel, const float* __
 // min_{u >= 0} 1/2 u Q u^T - q u^T, Q = G + mu I: zero exactly at its
 // minimiser.
 template <int KC, int W, int SW>
-__device__ __forceinline__ float kkt(float* __restrict__ panel, const float* __restrict__ gp,
+__device__ __forceinline__ float kkt(QPanel<SW>& qp, const float* __restrict__ gp,
                                      const float* __restrict__ den, const float* __restrict__ R,
                                      const float* __restrict__ C, int64_t row0, int nrows, int k,
                                      float mu, const RowBlocks<KC, W>& u) {
   constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
-  const float* mine = panel + threadIdx.x * Panel<SW>::STR;
   float pg2 = 0.f, q2 = 0.f;
+  wait_lds_reads();
+  q_issue<SW>(qp, R, C, row0, nrows, k, 0);
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
-    __syncthreads();
-    stage<SW, true>(panel, R, C, mu, row0, nrows, k, pc * SW);
-    __syncthreads();
+    typename RowBlocks<SW, SW>::vec qb;
+    q_read<SW>(qp, mu, pc * SW, k, qb);
+    wait_lds_reads();
+    if (pc + 1 < NP) q_issue<SW>(qp, R, C, row0, nrows, k, (pc + 1) * SW);
 #pragma unroll
     for (int b = 0; b < BPP; ++b) {
       const int lb = pc * BPP + b;
@@ -287,7 +374,7 @@ __device__ __forceinline__ float kkt(float* __restrict__ panel, const float* __r
 #pragma nounroll
         for (int le = 0; le < ln; ++le) {
           const int l = lb * W + le;
-          const float q = mine[b * W + le];
+          const float q = qb[b * W + le];
           const float ul = u.b[lb][le];
           float g = dot_row<KC, W>(gp + l * KC, u) + den[l] * ul - q;
           if (!(ul > 0.f)) g = fminf(g, 0.f);
@@ -315,7 +402,12 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
   // C (the proximal centre) may alias U: the rows of C are read only before
   // U is written, at the end.  start (to-tolerance mode only) is a warm
   // start; without it the solve starts from U.
-  __shared__ float panel[Panel<SW>::WORDS];
+  // one LDS block, used in turn by the row panels (load, store) and by the
+  // streamed right-hand side: every phase waits for its own traffic
+  constexpr int kWords = Panel<SW>::WORDS > 2 * 64 * SW ? Panel<SW>::WORDS : 2 * 64 * SW;
+  __shared__ float lds[kWords];
+  float* panel = lds;
+  QPanel<SW>& qp = *reinterpret_cast<QPanel<SW>*>(lds);
   const int64_t row0 = blockIdx.x * 64ll;
   const int nrows = static_cast<int>(rows - row0 < 64 ? rows - row0 : 64);
   const bool valid = static_cast<int>(threadIdx.x) < nrows;
@@ -326,7 +418,7 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
   bool unconverged = false, fell_back = false;
   if (!TO_TOL) {
     for (int s = 0; s < sweeps; ++s)
-      sweep<KC, W, SW>(panel, gp, inv, R, C, row0, nrows, k, mu, ub, true, u);
+      sweep<KC, W, SW>(qp, gp, inv, R, C, row0, nrows, k, mu, ub, true, u);
     used = valid ? sweeps : 0;
   } else {
     // Sweeps run on the lanes whose row is pending (projected-gradient norm
@@ -346,7 +438,7 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
 #pragma nounroll
     for (int c = 0; c < ncand; ++c) {
       if (c == 1) load_rows<KC, W, SW>(panel, C, row0, nrows, k, true, u);
-      const float r = kkt<KC, W, SW>(panel, gp, den, R, C, row0, nrows, k, mu, u);
+      const float r = kkt<KC, W, SW>(qp, gp, den, R, C, row0, nrows, k, mu, u);
       if (c == 0) res_w = r;
       else res_c = r;
     }
@@ -362,9 +454,9 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
       if (valid) pend = res > tol;
       const bool run = valid && pend && used < max_sweeps;
       if (!__any(run)) break;
-      sweep<KC, W, SW>(panel, gp, inv, R, C, row0, nrows, k, mu, ub, run, u);
+      sweep<KC, W, SW>(qp, gp, inv, R, C, row0, nrows, k, mu, ub, run, u);
       if (run) ++used;
-      res = kkt<KC, W, SW>(panel, gp, den, R, C, row0, nrows, k, mu, u);
+      res = kkt<KC, W, SW>(qp, gp, den, R, C, row0, nrows, k, mu, u);
     }
     unconverged = pend;
   }
@@ -438,9 +530,9 @@ __global__ __launch_bounds__(64) void pgd_kernel(const float* __restrict__ gp,
   const float ub = upper > 0.f ? upper : INFINITY;
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
-    __syncthreads();
+    lds_order();
     stage<SW, false>(panel, R, nullptr, 0.f, row0, nrows, k, pc * SW);
-    __syncthreads();
+    lds_order();
 #pragma unroll
     for (int b = 0; b < BPP; ++b) {
       const int jb = pc * BPP + b;
@@ -455,7 +547,7 @@ __global__ __launch_bounds__(64) void pgd_kernel(const float* __restrict__ gp,
         }
       }
     }
-    __syncthreads();
+    lds_order();
     unstage<SW>(panel, U, row0, nrows, k, pc * SW);
   }
 }
