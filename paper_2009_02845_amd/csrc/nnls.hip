@@ -34,6 +34,9 @@ struct Prep {
 
 constexpr int kMaxKC = 128;
 
+// Lane within the wave (a workgroup is one wave of 64 rows).
+__device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x & 63); }
+
 size_t prep_floats(int KC) { return static_cast<size_t>(KC) * KC + 4 * KC + 64; }
 
 Prep carve_prep(void* ws, int KC) {
@@ -123,12 +126,12 @@ __device__ __forceinline__ void stage(float* __restrict__ panel, const float* __
   // them all in registers; opaque copies of the corner and the lane index
   // keep the loads where they are.
   int64_t corner = row0 * k + c0;
-  int lane = threadIdx.x;
+  int lane = lane_id();
   asm volatile("" : "+s"(corner));
   asm volatile("" : "+v"(lane));
   const int rl = lane / SW, cl = lane % SW;
   float* dst = panel + rl * STR + cl;
-  if (c0 >= k) {
+  if (c0 >= k || nrows <= 0) {
 #pragma unroll
     for (int s = 0; s < SW; ++s) dst[s * RPS * STR] = 0.f;
     return;
@@ -169,7 +172,7 @@ __device__ __forceinline__ void unstage(const float* __restrict__ panel, float* 
                                         int nrows, int k, int c0) {
   constexpr int STR = Panel<SW>::STR, RPS = Panel<SW>::RPS;
   int64_t corner = row0 * k + c0;
-  int lane = threadIdx.x;
+  int lane = lane_id();
   asm volatile("" : "+s"(corner));
   asm volatile("" : "+v"(lane));
   const int rl = lane / SW, cl = lane % SW;
@@ -221,13 +224,13 @@ __device__ __forceinline__ void lds_order() { asm volatile("s_waitcnt lgkmcnt(0)
 template <int SW>
 __device__ __forceinline__ void q_issue(QPanel<SW>& qp, const float* __restrict__ R,
                                         const float* __restrict__ C, int64_t row0, int nrows, int k,
-                                        int c0) {
+                                        int c0, bool with_c) {
   constexpr int RPS = Panel<SW>::RPS;
-  if (c0 >= k) return;
+  if (c0 >= k || nrows <= 0) return;
   // opaque copies, or the compiler hoists every panel's addresses out of the
   // sweep loop and keeps them all in registers
   int64_t corner = row0 * k + c0;
-  int lane = threadIdx.x;
+  int lane = lane_id();
   asm volatile("" : "+s"(corner));
   asm volatile("" : "+v"(lane));
   const float* rb = R + corner;
@@ -238,15 +241,15 @@ __device__ __forceinline__ void q_issue(QPanel<SW>& qp, const float* __restrict_
     const int c = (lane % SW) ^ swz<SW>(r);
     const int off = r < nrows && c0 + c < k ? r * k + c : 0;
     __builtin_amdgcn_global_load_lds(rb + off, qp.r + 64 * s, 4, 0, 0);
-    __builtin_amdgcn_global_load_lds(cb + off, qp.c + 64 * s, 4, 0, 0);
+    if (with_c) __builtin_amdgcn_global_load_lds(cb + off, qp.c + 64 * s, 4, 0, 0);
   }
 }
 
-// q[e] = r + mu c of this lane's row at panel column e.
+// q[e] = r + mu c of this lane's row at panel column e (r alone without c).
 template <int SW>
-__device__ __forceinline__ void q_read(const QPanel<SW>& qp, float mu, int c0, int k,
+__device__ __forceinline__ void q_read(const QPanel<SW>& qp, float mu, int c0, int k, bool with_c,
                                        typename RowBlocks<SW, SW>::vec& q) {
-  int lane = threadIdx.x;
+  int lane = lane_id();
   asm volatile("" : "+v"(lane));
   const int f = swz<SW>(lane);
   wait_panel_loads();
@@ -259,20 +262,54 @@ __device__ __forceinline__ void q_read(const QPanel<SW>& qp, float mu, int c0, i
 #pragma unroll
   for (int e = 0; e < SW; ++e) {
     x[e] = qp.r[SW * lane + (e ^ f)];
-    y[e] = qp.c[SW * lane + (e ^ f)];
+    y[e] = with_c ? qp.c[SW * lane + (e ^ f)] : 0.f;
   }
 #pragma unroll
   for (int e = 0; e < SW; ++e) q[e] = x[e] + mu * y[e];
 }
 
-// u <- this lane's row of P on the lanes where take holds (the panel load
-// itself is cooperative: every lane of the wave takes part).
-template <int KC, int W, int SW>
+// u <- this lane's row of P on the lanes where take holds.  A first load
+// (u not yet live) of rows of 16 B multiples: per-lane float4 loads, all
+// in flight at once; a reload (MASKED: u stays live, and 25 float4s beside
+// it would cost occupancy) goes through the LDS panel, a cooperative load
+// in which every lane of the wave takes part.
+template <int KC, int W, int SW, bool MASKED = false>
 __device__ __forceinline__ void load_rows(float* __restrict__ panel, const float* __restrict__ P,
                                           int64_t row0, int nrows, int k, bool take,
                                           RowBlocks<KC, W>& u) {
   constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
-  const float* mine = panel + threadIdx.x * Panel<SW>::STR;
+  if (!MASKED && nrows <= 0) {   // a wave without rows (last workgroup)
+#pragma unroll
+    for (int l = 0; l < NB * W; ++l) u.b[l / W][l % W] = 0.f;
+    return;
+  }
+  if (!MASKED && k % 4 == 0 && (reinterpret_cast<uintptr_t>(P) & 15) == 0) {
+    // rows of 16 B multiples: each lane reads its own row as float4s (a
+    // lane's row is contiguous, so every line is fetched once), all loads
+    // in flight together; lanes past nrows read the last row and drop it
+    constexpr int NQ = (KC + 3) / 4;
+    const int rl = lane_id() < nrows ? lane_id() : nrows - 1;
+    const float4* src = reinterpret_cast<const float4*>(P + (row0 + rl) * k);
+    const int kq = k / 4;
+    float4 x[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) x[q] = src[q < kq ? q : kq - 1];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const bool in = q < kq;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int l = 4 * q + e;
+        const float v = in ? (e == 0 ? x[q].x : e == 1 ? x[q].y : e == 2 ? x[q].z : x[q].w) : 0.f;
+        if (take) u.b[l / W][l % W] = v;
+      }
+    }
+#pragma unroll
+    for (int l = 4 * NQ; l < NB * W; ++l)
+      if (take) u.b[l / W][l % W] = 0.f;
+    return;
+  }
+  const float* mine = panel + lane_id() * Panel<SW>::STR;
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
     lds_order();
@@ -294,7 +331,21 @@ template <int KC, int W, int SW>
 __device__ __forceinline__ void store_rows(float* __restrict__ panel, float* P, int64_t row0,
                                            int nrows, int k, const RowBlocks<KC, W>& u) {
   constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
-  float* mine = panel + threadIdx.x * Panel<SW>::STR;
+  if (k % 4 == 0 && (reinterpret_cast<uintptr_t>(P) & 15) == 0) {
+    // each lane writes its own row as float4s (every line written whole by
+    // one lane)
+    constexpr int NQ = (KC + 3) / 4;
+    if (lane_id() >= nrows) return;
+    float4* dst = reinterpret_cast<float4*>(P + (row0 + lane_id()) * k);
+    const int kq = k / 4;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (q < kq)
+        dst[q] = make_float4(u.b[(4 * q) / W][(4 * q) % W], u.b[(4 * q + 1) / W][(4 * q + 1) % W],
+                             u.b[(4 * q + 2) / W][(4 * q + 2) % W], u.b[(4 * q + 3) / W][(4 * q + 3) % W]);
+    return;
+  }
+  float* mine = panel + lane_id() * Panel<SW>::STR;
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
     lds_order();
@@ -320,16 +371,19 @@ template <int KC, int W, int SW>
 __device__ __forceinline__ void sweep(QPanel<SW>& qp, const float* __restrict__ gp,
                                       const float* __restrict__ inv, const float* __restrict__ R,
                                       const float* __restrict__ C, int64_t row0, int nrows, int k,
-                                      float mu, float ub, bool act, RowBlocks<KC, W>& u) {
+                                      float mu, float ub, bool act, bool c_is_u,
+                                      RowBlocks<KC, W>& u) {
+  // c_is_u: the centre is the iterate this sweep starts from, so c_j is
+  // u_j as it stands when coordinate j is reached, and C is not read
   constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
   wait_lds_reads();
-  q_issue<SW>(qp, R, C, row0, nrows, k, 0);
+  q_issue<SW>(qp, R, C, row0, nrows, k, 0, !c_is_u);
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
     typename RowBlocks<SW, SW>::vec qb;
-    q_read<SW>(qp, mu, pc * SW, k, qb);
+    q_read<SW>(qp, mu, pc * SW, k, !c_is_u, qb);
     wait_lds_reads();
-    if (pc + 1 < NP) q_issue<SW>(qp, R, C, row0, nrows, k, (pc + 1) * SW);
+    if (pc + 1 < NP) q_issue<SW>(qp, R, C, row0, nrows, k, (pc + 1) * SW, !c_is_u);
 #pragma unroll
     for (int b = 0; b < BPP; ++b) {
       const int jb = pc * BPP + b;
@@ -338,7 +392,7 @@ __device__ __forceinline__ void sweep(QPanel<SW>& qp, const float* __restrict__ 
 #pragma nounroll
         for (int je = 0; je < jn; ++je) {
           const int j = jb * W + je;
-          const float q = qb[b * W + je];
+          const float q = c_is_u ? qb[b * W + je] + mu * u.b[jb][je] : qb[b * W + je];
           const float t = dot_row<KC, W>(gp + j * KC, u);
           const float v = fminf(fmaxf((q - t) * inv[j], 0.f), ub);
           if (act) u.b[jb][je] = v;
@@ -359,13 +413,13 @@ __device__ __forceinline__ float kkt(QPanel<SW>& qp, const float* __restrict__ g
   constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
   float pg2 = 0.f, q2 = 0.f;
   wait_lds_reads();
-  q_issue<SW>(qp, R, C, row0, nrows, k, 0);
+  q_issue<SW>(qp, R, C, row0, nrows, k, 0, true);
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
     typename RowBlocks<SW, SW>::vec qb;
-    q_read<SW>(qp, mu, pc * SW, k, qb);
+    q_read<SW>(qp, mu, pc * SW, k, true, qb);
     wait_lds_reads();
-    if (pc + 1 < NP) q_issue<SW>(qp, R, C, row0, nrows, k, (pc + 1) * SW);
+    if (pc + 1 < NP) q_issue<SW>(qp, R, C, row0, nrows, k, (pc + 1) * SW, true);
 #pragma unroll
     for (int b = 0; b < BPP; ++b) {
       const int lb = pc * BPP + b;
@@ -407,10 +461,11 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
   constexpr int kWords = Panel<SW>::WORDS > 2 * 64 * SW ? Panel<SW>::WORDS : 2 * 64 * SW;
   __shared__ float lds[kWords];
   float* panel = lds;
-  QPanel<SW>& qp = *reinterpret_cast<QPanel<SW>*>(lds);
-  const int64_t row0 = blockIdx.x * 64ll;
+  QPanel<SW>& qp = *reinterpret_cast<QPanel<SW>*>(panel);
+  const int64_t wave_id = blockIdx.x;
+  const int64_t row0 = wave_id * 64;
   const int nrows = static_cast<int>(rows - row0 < 64 ? rows - row0 : 64);
-  const bool valid = static_cast<int>(threadIdx.x) < nrows;
+  const bool valid = lane_id() < nrows;
   const float ub = upper > 0.f ? upper : INFINITY;
   RowBlocks<KC, W> u;
   load_rows<KC, W, SW>(panel, TO_TOL && start != nullptr ? start : U, row0, nrows, k, true, u);
@@ -418,7 +473,7 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
   bool unconverged = false, fell_back = false;
   if (!TO_TOL) {
     for (int s = 0; s < sweeps; ++s)
-      sweep<KC, W, SW>(qp, gp, inv, R, C, row0, nrows, k, mu, ub, true, u);
+      sweep<KC, W, SW>(qp, gp, inv, R, C, row0, nrows, k, mu, ub, true, s == 0 && C == U, u);
     used = valid ? sweeps : 0;
   } else {
     // Sweeps run on the lanes whose row is pending (projected-gradient norm
@@ -437,7 +492,7 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
     const int ncand = start != nullptr ? 2 : 1;
 #pragma nounroll
     for (int c = 0; c < ncand; ++c) {
-      if (c == 1) load_rows<KC, W, SW>(panel, C, row0, nrows, k, true, u);
+      if (c == 1) load_rows<KC, W, SW, true>(panel, C, row0, nrows, k, true, u);
       const float r = kkt<KC, W, SW>(qp, gp, den, R, C, row0, nrows, k, mu, u);
       if (c == 0) res_w = r;
       else res_c = r;
@@ -446,7 +501,7 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
     if (start != nullptr) {
       const bool warm = ok && res_w < res_c;
       fell_back = valid && !warm;
-      if (__any(warm)) load_rows<KC, W, SW>(panel, start, row0, nrows, k, warm, u);
+      if (__any(warm)) load_rows<KC, W, SW, true>(panel, start, row0, nrows, k, warm, u);
       res = warm ? res_w : res_c;
     }
     bool pend = false;
@@ -454,14 +509,14 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
       if (valid) pend = res > tol;
       const bool run = valid && pend && used < max_sweeps;
       if (!__any(run)) break;
-      sweep<KC, W, SW>(qp, gp, inv, R, C, row0, nrows, k, mu, ub, run, u);
+      sweep<KC, W, SW>(qp, gp, inv, R, C, row0, nrows, k, mu, ub, run, false, u);
       if (run) ++used;
       res = kkt<KC, W, SW>(qp, gp, den, R, C, row0, nrows, k, mu, u);
     }
     unconverged = pend;
   }
   store_rows<KC, W, SW>(panel, U, row0, nrows, k, u);
-  if (valid && sweeps_used != nullptr) sweeps_used[row0 + threadIdx.x] = used;
+  if (valid && sweeps_used != nullptr) sweeps_used[row0 + lane_id()] = used;
   if (TO_TOL && wave_counts != nullptr) {
     // wave totals, stored per wave and summed by count_reduce_kernel (one
     // atomic per wave on three shared addresses serialises in L2 and stalls
@@ -474,8 +529,8 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
       b += __shfl_down(b, o, 64);
       f += __shfl_down(f, o, 64);
     }
-    if (threadIdx.x == 0) {
-      unsigned long long* w = wave_counts + 3 * static_cast<int64_t>(blockIdx.x);
+    if (lane_id() == 0) {
+      unsigned long long* w = wave_counts + 3 * wave_id;
       w[0] = a;
       w[1] = b;
       w[2] = f;
@@ -567,9 +622,8 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
     pgd_kernel<KC, W, SW><<<grid, 64, 0, s>>>(p.gp, p.gdiag, p.colsum, R, U, rows, k, mu, upper);
     DSANLS_LAUNCHED("pgd_kernel");
   } else if (sweeps > 0) {
-    prox_cd_kernel<KC, W, SW, false><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, nullptr, U, rows, k,
-                                                         mu, sweeps, tol, max_sweeps, upper,
-                                                         sweeps_used, nullptr);
+    prox_cd_kernel<KC, W, SW, false><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, nullptr, U, rows, k, mu,
+                                                         sweeps, tol, max_sweeps, upper, sweeps_used, nullptr);
     DSANLS_LAUNCHED("prox_cd_kernel");
   } else {
     const bool count = counters != nullptr && wave_counts != nullptr;

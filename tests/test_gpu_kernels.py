@@ -162,6 +162,22 @@ def test_prox_cd_upper_clip_and_empty(torch_dev):
     B.nnls_prox_cd(torch.from_numpy(G).cuda(), E, E, E, 0.5)
 
 
+@pytest.mark.parametrize("k,sweeps", [(100, 1), (100, 3), (10, 1), (64, 2)])
+def test_prox_cd_centre_differs_from_start(torch_dev, k, sweeps):
+    # the proximal centre C is not the starting point: every sweep must read
+    # C (rows of 16 B multiples and not, one and several sweeps)
+    torch, B = torch_dev
+    rows, mu = 700 + 13, 0.9
+    G, R, U0 = _nnls_problem(rows, k, 3 * k + 5, 50 + k)
+    C0 = np.random.default_rng(k).random((rows, k)).astype(np.float32)
+    U = torch.from_numpy(U0.copy()).cuda()
+    B.nnls_prox_cd(torch.from_numpy(G).cuda(), torch.from_numpy(R).cuda(), torch.from_numpy(C0).cuda(), U, mu,
+                   sweeps=sweeps)
+    ref, _ = O.prox_cd_solve(U0.astype(np.float64), C0.astype(np.float64), G.astype(np.float64),
+                             R.astype(np.float64), mu, sweeps)
+    assert _rel(U.cpu().numpy(), ref) < 1e-4
+
+
 @pytest.mark.parametrize("rows,cols,K", [(200, 40, 150), (257, 130, 1001), (300, 4096, 2048), (128, 128, 64),
                                          (129, 65, 17)])
 def test_gemm_nt_bf16_matches_fp64(torch_dev, rows, cols, K):
