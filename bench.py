@@ -122,7 +122,44 @@ def cpu_baseline(w, M, U0, V0, budget_s=12.0, max_iters=5, Mt=None):
                       f"{el:.1f} s"}
 
 
-def sparse_roofline(w, M, tm, launches):
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged over the profiled
+# launches), each scaled by what the same counter reads for a plain copy of
+# 1 GiB on the same GPU (FETCH_SIZE reads 524300 KiB of the 1048576 read:
+# x2.0; WRITE_SIZE reads 1048576: x1.0).  The figure holds only for the
+# kernel sources it was taken with (sha256 of the listed files, in order);
+# after any change to them the traffic is reported as null.
+CAL_FETCH, CAL_WRITE = 2.0, 1.0
+TRAFFIC = {
+    "dense-20000x10000": {"files": ["gemm.hip", "common.hpp"],
+                          "sha256": "9c40bb69116ffb612564fde1c2d43c3e0faf99a3152cf7f8ee13ea55b70fbe8a",
+                          "fetch_kib": 4164995.65, "write_kib": 120000.0},
+    "sparse-500000x200000": {"files": ["nnls.hip", "common.hpp"],
+                             "sha256": "8027805254c85711f365fd3acc4902404ca7b5565c482d02a260bb603c96f807",
+                             "fetch_kib": 221049.53, "write_kib": 183561.73},
+    "dense-50000x20000-bf16": {"files": ["gemm.hip", "common.hpp"],
+                               "sha256": "9c40bb69116ffb612564fde1c2d43c3e0faf99a3152cf7f8ee13ea55b70fbe8a",
+                               "fetch_kib": 23778515.9, "write_kib": 1120000.0},
+}
+
+
+def sources_sha256(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2009_02845_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(workload):
+    t = TRAFFIC.get(workload)
+    if t is None or sources_sha256(t["files"]) != t["sha256"]:
+        return None
+    return 1024.0 * (CAL_FETCH * t["fetch_kib"] + CAL_WRITE * t["write_kib"])
+
+
+def sparse_roofline(w, M, tm, launches, workload):
     """Roofline of the dominant sparse phase: the NNLS sweep (VALU) or the
     sampled-column sketch product (HBM), whichever takes longer per launch."""
     m, n, k, d = w["m"], w["n"], w["k"], w["d"]
@@ -135,7 +172,7 @@ def sparse_roofline(w, M, tm, launches):
         ach = flops / nnls_avg / 1e12
         peak = PEAK["fp32_valu_tflops"]
         return {"kernel": "prox-CD sweep (prox_cd_kernel)", "bound": "alu", "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None, "flops_per_launch": flops,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic_bytes(workload), "flops_per_launch": flops,
                 "avg_launch_ms": nnls_avg * 1e3}
     # sampled-column gather: E = nnz d / lng sampled entries per side (their
     # expectation under uniform sampling), each read once from CSR(X^T)
@@ -360,15 +397,19 @@ def main():
     its = K / el
     launches = 2 * K
     if w["kind"] == "dense":
-        prod_avg_s = tm["product_ms"] / 1e3 / launches
-        flops_launch = 2.0 * m * n * d      # A = M S (m x n x d) and A' = M^T S' (n x m x d')
+        # one grouped launch per iteration computes A = M S (m x n x d) and
+        # A' = M^T S' (n x m x d'); the V side reuses A'
+        prod_avg_s = tm["product_ms"] / 1e3 / K
+        flops_launch = 2.0 * m * n * d + 2.0 * n * m * d
         peak = PEAK["bf16_mfma_tflops"] if w["precision"] == "bf16" else PEAK["fp32_mfma_tflops"]
         achieved = flops_launch / prod_avg_s / 1e12
-        roof = {"kernel": "sketch GEMM A = M S (gemm_nt_kernel)", "bound": "mfma", "achieved": achieved,
-                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                "flops_per_launch": flops_launch, "avg_launch_ms": prod_avg_s * 1e3}
+        name = "gemm_nt_bf16_kernel" if w["precision"] == "bf16" else "gemm_nt_grouped_kernel"
+        roof = {"kernel": f"sketch GEMMs A = M S, A' = M^T S' ({name}, one launch per iteration)",
+                "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": traffic_bytes(args.workload), "flops_per_launch": flops_launch,
+                "avg_launch_ms": prod_avg_s * 1e3}
     else:
-        roof = sparse_roofline(w, M, tm, launches)
+        roof = sparse_roofline(w, M, tm, launches, args.workload)
     out = {
         "metric": "sketched-ANLS iterations/s (and NNLS rows/s) to a fixed relative objective",
         "value": its,
