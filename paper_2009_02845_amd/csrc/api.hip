@@ -74,7 +74,7 @@ struct Layout {
   float* red = nullptr;             // 64 floats of small results
   int* err = nullptr;               // 16 ints of device flags
   unsigned long long* counters = nullptr;
-  unsigned long long* wave_counts = nullptr;   // 3 per NNLS wave
+  TolWork tol{};                    // to-tolerance passes (null pointers when unused)
   size_t total = 0;
 };
 
@@ -176,8 +176,19 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
   L.red = reinterpret_cast<float*>(take(sizeof(float) * 64));
   L.err = reinterpret_cast<int*>(take(sizeof(int) * 16));
   L.counters = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * 8));
-  L.wave_counts = reinterpret_cast<unsigned long long*>(
-      take(sizeof(unsigned long long) * 3 * ((rowsmax + 63) / 64)));
+  L.tol.counters = L.counters;
+  if (c.solver == DSANLS_SOLVER_PROX_CD && c.sweeps == 0) {
+    const int64_t nw = (rowsmax + 63) / 64;
+    L.tol.used = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * rowsmax));
+    L.tol.flags = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * rowsmax));
+    L.tol.wave_cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * nw));
+    L.tol.wave_off = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (nw + 1)));
+    L.tol.wave_rows = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * nw * 64));
+    L.tol.list[0] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * rowsmax));
+    L.tol.list[1] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * rowsmax));
+    L.tol.scan_ws = reinterpret_cast<int32_t*>(take(scan_ws_bytes(nw)));
+    L.tol.centre = reinterpret_cast<float*>(take(sizeof(float) * rowsmax * k));
+  }
   L.total = off;
   return L;
 }
@@ -472,7 +483,7 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
   CHECK(mark(ctx, kPhNnls));
   CHECK(launch_nnls(pgd, L.G, L.R, Wself, Wself, rows, static_cast<int>(k), static_cast<float>(mu),
                     c.sweeps, static_cast<float>(c.tol), c.max_sweeps, ctx->upper, nullptr,
-                    L.counters, L.wave_counts, L.nnls_ws, L.nnls_ws_bytes, s, start));
+                    L.tol.used != nullptr ? &L.tol : nullptr, L.nnls_ws, L.nnls_ws_bytes, s, start));
   if (!pgd && c.sweeps > 0) ctx->stats.sweeps_total += rows * c.sweeps;
   CHECK(mark(ctx, kPhNnls));
   if (ctx->timing) ctx->timed_updates += 1;

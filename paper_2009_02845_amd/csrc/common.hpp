@@ -110,19 +110,32 @@ dsanls_status launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, 
 
 // ---------------------------------------------------------------- nnls.hip
 size_t nnls_ws_bytes(int k);
+// Workspace of the to-tolerance mode's compacted passes (rows = the most
+// rows of any update; nw = ceil(rows / 64)): per-row sweep counts and flags,
+// per-wave pending counts (nw), their scan (nw + 1), pending rows per wave
+// (64 nw), two row lists (rows each), the scan's own workspace and a copy
+// of the centre (rows x k).
+struct TolWork {
+  unsigned long long* counters;  // may be null: [0] += row-sweeps, [1] += unconverged rows,
+                                 // [2] += rows that started cold although a warm start was given
+  int32_t* used;
+  int32_t* flags;
+  int32_t* wave_cnt;
+  int32_t* wave_off;
+  int32_t* wave_rows;
+  int32_t* list[2];
+  int32_t* scan_ws;
+  float* centre;                 // rows x k: a copy of C when C aliases U (U changes between passes)
+};
 // pgd = false: prox-CD (sweeps >= 1, or 0 = to tol); pgd = true: one PGD step.
-// counters (may be null; to-tolerance mode only): [0] += row-sweeps run,
-// [1] += rows left unconverged, [2] += rows that started from the centre C
-// although a warm start was given; wave_counts (3 * ceil(rows / 64)
-// entries) holds the per-wave counts that are summed into counters.
-// start (may be null: start from U) is a warm start for the to-tolerance
-// mode; a row starts from C instead when its warm start is not finite or
-// has the larger projected-gradient norm.
+// tw (to-tolerance mode; may be null: one pass to the end, no counts): the
+// compaction workspace.  start (may be null: start from U) is a warm start
+// for the to-tolerance mode; a row starts from C instead when its warm start
+// is not finite or has the larger projected-gradient norm.
 dsanls_status launch_nnls(bool pgd, const float* G, const float* R, const float* C, float* U,
                           int64_t rows, int k, float mu, int sweeps, float tol, int max_sweeps,
-                          float upper, int32_t* sweeps_used, unsigned long long* counters,
-                          unsigned long long* wave_counts, void* ws, size_t ws_bytes,
-                          hipStream_t s, const float* start = nullptr);
+                          float upper, int32_t* sweeps_used, const TolWork* tw, void* ws,
+                          size_t ws_bytes, hipStream_t s, const float* start = nullptr);
 
 // ---------------------------------------------------------------- sparse.hip
 // Longest run of nnz one wave streams in the segmented CSR kernels.

@@ -119,7 +119,7 @@ struct Panel {
 template <int SW, bool ADD>
 __device__ __forceinline__ void stage(float* __restrict__ panel, const float* __restrict__ P,
                                       const float* __restrict__ C, float mu, int64_t row0,
-                                      int nrows, int k, int c0) {
+                                      int nrows, int k, int c0, const int32_t* rmap = nullptr) {
   constexpr int STR = Panel<SW>::STR, RPS = Panel<SW>::RPS;
   // The inputs do not change during the kernel, so the compiler would hoist
   // every panel's loads (and their addresses) out of the sweep loop and keep
@@ -136,11 +136,27 @@ __device__ __forceinline__ void stage(float* __restrict__ panel, const float* __
     for (int s = 0; s < SW; ++s) dst[s * RPS * STR] = 0.f;
     return;
   }
+  float x[SW];
+  if (rmap != nullptr) {
+    // listed rows (a compacted pass): row r of the panel is rmap[r]
+    const bool col_ok = c0 + cl < k;
+#pragma unroll
+    for (int s = 0; s < SW; ++s) {
+      const int r = s * RPS + rl;
+      const bool ok = col_ok && r < nrows;
+      const int64_t o = static_cast<int64_t>(rmap[ok ? r : 0]) * k + (ok ? c0 + cl : 0);
+      float v = P[o];
+      if (ADD) v += mu * C[o];
+      x[s] = ok ? v : 0.f;
+    }
+#pragma unroll
+    for (int s = 0; s < SW; ++s) dst[s * RPS * STR] = x[s];
+    return;
+  }
   const float* p = P + corner;
   const float* c = ADD ? C + corner : nullptr;
   const unsigned lane_off = static_cast<unsigned>(rl * k + cl) * 4u;
   const int64_t step = static_cast<int64_t>(RPS) * k;
-  float x[SW];
   if (nrows == 64 && c0 + SW <= k) {
     // whole panel inside the matrix: a wave-uniform row base per step plus
     // the lane's 32-bit byte offset
@@ -169,7 +185,7 @@ __device__ __forceinline__ void stage(float* __restrict__ panel, const float* __
 // Columns [c0, c0 + SW) of rows [row0, row0 + nrows) of P <- panel.
 template <int SW>
 __device__ __forceinline__ void unstage(const float* __restrict__ panel, float* P, int64_t row0,
-                                        int nrows, int k, int c0) {
+                                        int nrows, int k, int c0, const int32_t* rmap = nullptr) {
   constexpr int STR = Panel<SW>::STR, RPS = Panel<SW>::RPS;
   int64_t corner = row0 * k + c0;
   int lane = lane_id();
@@ -178,6 +194,14 @@ __device__ __forceinline__ void unstage(const float* __restrict__ panel, float* 
   const int rl = lane / SW, cl = lane % SW;
   if (c0 >= k || c0 + cl >= k) return;
   const float* src = panel + rl * STR + cl;
+  if (rmap != nullptr) {
+#pragma unroll
+    for (int s = 0; s < SW; ++s) {
+      const int r = s * RPS + rl;
+      if (r < nrows) P[static_cast<int64_t>(rmap[r]) * k + c0 + cl] = src[s * RPS * STR];
+    }
+    return;
+  }
   char* p = reinterpret_cast<char*>(P + corner);
   const unsigned lane_off = static_cast<unsigned>(rl * k + cl) * 4u;
   const unsigned step = static_cast<unsigned>(RPS * k) * 4u;
@@ -224,7 +248,7 @@ __device__ __forceinline__ void lds_order() { asm volatile("s_waitcnt lgkmcnt(0)
 template <int SW>
 __device__ __forceinline__ void q_issue(QPanel<SW>& qp, const float* __restrict__ R,
                                         const float* __restrict__ C, int64_t row0, int nrows, int k,
-                                        int c0, bool with_c) {
+                                        int c0, bool with_c, const int32_t* rmap = nullptr) {
   constexpr int RPS = Panel<SW>::RPS;
   if (c0 >= k || nrows <= 0) return;
   // opaque copies, or the compiler hoists every panel's addresses out of the
@@ -233,6 +257,19 @@ __device__ __forceinline__ void q_issue(QPanel<SW>& qp, const float* __restrict_
   int lane = lane_id();
   asm volatile("" : "+s"(corner));
   asm volatile("" : "+v"(lane));
+  if (rmap != nullptr) {
+    // listed rows (a compacted pass): row r of the panel is rmap[r]
+#pragma unroll
+    for (int s = 0; s < SW; ++s) {
+      const int r = RPS * s + lane / SW;
+      const int c = (lane % SW) ^ swz<SW>(r);
+      const bool ok = r < nrows && c0 + c < k;
+      const int64_t off = static_cast<int64_t>(rmap[ok ? r : 0]) * k + c0 + (ok ? c : 0);
+      __builtin_amdgcn_global_load_lds(R + off, qp.r + 64 * s, 4, 0, 0);
+      if (with_c) __builtin_amdgcn_global_load_lds(C + off, qp.c + 64 * s, 4, 0, 0);
+    }
+    return;
+  }
   const float* rb = R + corner;
   const float* cb = C + corner;
 #pragma unroll
@@ -276,7 +313,7 @@ __device__ __forceinline__ void q_read(const QPanel<SW>& qp, float mu, int c0, i
 template <int KC, int W, int SW, bool MASKED = false>
 __device__ __forceinline__ void load_rows(float* __restrict__ panel, const float* __restrict__ P,
                                           int64_t row0, int nrows, int k, bool take,
-                                          RowBlocks<KC, W>& u) {
+                                          RowBlocks<KC, W>& u, const int32_t* rmap = nullptr) {
   constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
   if (!MASKED && nrows <= 0) {   // a wave without rows (last workgroup)
 #pragma unroll
@@ -289,7 +326,8 @@ __device__ __forceinline__ void load_rows(float* __restrict__ panel, const float
     // in flight together; lanes past nrows read the last row and drop it
     constexpr int NQ = (KC + 3) / 4;
     const int rl = lane_id() < nrows ? lane_id() : nrows - 1;
-    const float4* src = reinterpret_cast<const float4*>(P + (row0 + rl) * k);
+    const int64_t grow = rmap != nullptr ? static_cast<int64_t>(rmap[rl]) : row0 + rl;
+    const float4* src = reinterpret_cast<const float4*>(P + grow * k);
     const int kq = k / 4;
     float4 x[NQ];
 #pragma unroll
@@ -313,7 +351,7 @@ __device__ __forceinline__ void load_rows(float* __restrict__ panel, const float
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
     lds_order();
-    stage<SW, false>(panel, P, nullptr, 0.f, row0, nrows, k, pc * SW);
+    stage<SW, false>(panel, P, nullptr, 0.f, row0, nrows, k, pc * SW, rmap);
     lds_order();
 #pragma unroll
     for (int b = 0; b < BPP; ++b) {
@@ -329,14 +367,16 @@ __device__ __forceinline__ void load_rows(float* __restrict__ panel, const float
 
 template <int KC, int W, int SW>
 __device__ __forceinline__ void store_rows(float* __restrict__ panel, float* P, int64_t row0,
-                                           int nrows, int k, const RowBlocks<KC, W>& u) {
+                                           int nrows, int k, const RowBlocks<KC, W>& u,
+                                           const int32_t* rmap = nullptr) {
   constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
   if (k % 4 == 0 && (reinterpret_cast<uintptr_t>(P) & 15) == 0) {
     // each lane writes its own row as float4s (every line written whole by
     // one lane)
     constexpr int NQ = (KC + 3) / 4;
     if (lane_id() >= nrows) return;
-    float4* dst = reinterpret_cast<float4*>(P + (row0 + lane_id()) * k);
+    const int64_t grow = rmap != nullptr ? static_cast<int64_t>(rmap[lane_id()]) : row0 + lane_id();
+    float4* dst = reinterpret_cast<float4*>(P + grow * k);
     const int kq = k / 4;
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
@@ -358,7 +398,7 @@ __device__ __forceinline__ void store_rows(float* __restrict__ panel, float* P, 
       }
     }
     lds_order();
-    unstage<SW>(panel, P, row0, nrows, k, pc * SW);
+    unstage<SW>(panel, P, row0, nrows, k, pc * SW, rmap);
   }
 }
 
@@ -372,18 +412,18 @@ __device__ __forceinline__ void sweep(QPanel<SW>& qp, const float* __restrict__ 
                                       const float* __restrict__ inv, const float* __restrict__ R,
                                       const float* __restrict__ C, int64_t row0, int nrows, int k,
                                       float mu, float ub, bool act, bool c_is_u,
-                                      RowBlocks<KC, W>& u) {
+                                      RowBlocks<KC, W>& u, const int32_t* rmap = nullptr) {
   // c_is_u: the centre is the iterate this sweep starts from, so c_j is
   // u_j as it stands when coordinate j is reached, and C is not read
   constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
   wait_lds_reads();
-  q_issue<SW>(qp, R, C, row0, nrows, k, 0, !c_is_u);
+  q_issue<SW>(qp, R, C, row0, nrows, k, 0, !c_is_u, rmap);
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
     typename RowBlocks<SW, SW>::vec qb;
     q_read<SW>(qp, mu, pc * SW, k, !c_is_u, qb);
     wait_lds_reads();
-    if (pc + 1 < NP) q_issue<SW>(qp, R, C, row0, nrows, k, (pc + 1) * SW, !c_is_u);
+    if (pc + 1 < NP) q_issue<SW>(qp, R, C, row0, nrows, k, (pc + 1) * SW, !c_is_u, rmap);
 #pragma unroll
     for (int b = 0; b < BPP; ++b) {
       const int jb = pc * BPP + b;
@@ -409,17 +449,17 @@ template <int KC, int W, int SW>
 __device__ __forceinline__ float kkt(QPanel<SW>& qp, const float* __restrict__ gp,
                                      const float* __restrict__ den, const float* __restrict__ R,
                                      const float* __restrict__ C, int64_t row0, int nrows, int k,
-                                     float mu, const RowBlocks<KC, W>& u) {
+                                     float mu, const RowBlocks<KC, W>& u, const int32_t* rmap = nullptr) {
   constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
   float pg2 = 0.f, q2 = 0.f;
   wait_lds_reads();
-  q_issue<SW>(qp, R, C, row0, nrows, k, 0, true);
+  q_issue<SW>(qp, R, C, row0, nrows, k, 0, true, rmap);
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
     typename RowBlocks<SW, SW>::vec qb;
     q_read<SW>(qp, mu, pc * SW, k, true, qb);
     wait_lds_reads();
-    if (pc + 1 < NP) q_issue<SW>(qp, R, C, row0, nrows, k, (pc + 1) * SW, true);
+    if (pc + 1 < NP) q_issue<SW>(qp, R, C, row0, nrows, k, (pc + 1) * SW, true, rmap);
 #pragma unroll
     for (int b = 0; b < BPP; ++b) {
       const int lb = pc * BPP + b;
@@ -443,46 +483,93 @@ __device__ __forceinline__ float kkt(QPanel<SW>& qp, const float* __restrict__ g
   return sqrtf(pg2) / fmaxf(sqrtf(q2), 1e-30f);
 }
 
-template <int KC, int W, int SW, bool TO_TOL>
+// Fixed number of sweeps (the paper's one, or s).  C (the proximal centre)
+// may alias U: the rows of C are read only before U is written, at the end.
+template <int KC, int W, int SW>
 __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ gp,
-                                                     const float* __restrict__ den,
                                                      const float* __restrict__ inv,
-                                                     const float* __restrict__ R,
-                                                     const float* C, const float* start, float* U,
-                                                     int64_t rows, int k, float mu, int sweeps,
-                                                     float tol, int max_sweeps, float upper,
-                                                     int32_t* __restrict__ sweeps_used,
-                                                     unsigned long long* __restrict__ wave_counts) {
-  // C (the proximal centre) may alias U: the rows of C are read only before
-  // U is written, at the end.  start (to-tolerance mode only) is a warm
-  // start; without it the solve starts from U.
+                                                     const float* __restrict__ R, const float* C,
+                                                     float* U, int64_t rows, int k, float mu,
+                                                     int sweeps, float upper,
+                                                     int32_t* __restrict__ sweeps_used) {
   // one LDS block, used in turn by the row panels (load, store) and by the
   // streamed right-hand side: every phase waits for its own traffic
   constexpr int kWords = Panel<SW>::WORDS > 2 * 64 * SW ? Panel<SW>::WORDS : 2 * 64 * SW;
   __shared__ float lds[kWords];
   float* panel = lds;
   QPanel<SW>& qp = *reinterpret_cast<QPanel<SW>*>(panel);
-  const int64_t wave_id = blockIdx.x;
-  const int64_t row0 = wave_id * 64;
+  const int64_t row0 = blockIdx.x * 64ll;
   const int nrows = static_cast<int>(rows - row0 < 64 ? rows - row0 : 64);
   const bool valid = lane_id() < nrows;
   const float ub = upper > 0.f ? upper : INFINITY;
   RowBlocks<KC, W> u;
-  load_rows<KC, W, SW>(panel, TO_TOL && start != nullptr ? start : U, row0, nrows, k, true, u);
-  int used = 0;
-  bool unconverged = false, fell_back = false;
-  if (!TO_TOL) {
-    for (int s = 0; s < sweeps; ++s)
-      sweep<KC, W, SW>(qp, gp, inv, R, C, row0, nrows, k, mu, ub, true, s == 0 && C == U, u);
-    used = valid ? sweeps : 0;
+  load_rows<KC, W, SW>(panel, U, row0, nrows, k, true, u);
+  for (int s = 0; s < sweeps; ++s)
+    sweep<KC, W, SW>(qp, gp, inv, R, C, row0, nrows, k, mu, ub, true, s == 0 && C == U, u);
+  store_rows<KC, W, SW>(panel, U, row0, nrows, k, u);
+  if (valid && sweeps_used != nullptr) sweeps_used[row0 + lane_id()] = sweeps;
+}
+
+// One pass of the to-tolerance solve.  Sweeps run on the lanes whose row is
+// pending (relative projected-gradient norm above tol) until every row of
+// the wave has converged, spent max_sweeps, or spent this pass's budget; the
+// loop is wave-uniform (the panels are loaded by the whole wave) and a lane
+// that is done keeps its row.  The first pass takes the rows in order and
+// picks their start: with a warm start, each row starts from whichever of
+// the warm start and the cold start (the centre U^t) has the smaller
+// projected-gradient norm, and a start that is not finite is never taken.
+// A row still pending when the budget runs out is listed (per wave, in lane
+// order) for the next pass, which takes only listed rows and resumes from
+// the row's current iterate and sweep count: a wave then waits only for
+// rows as slow as its own, not for the slowest row of 64 neighbours.  The
+// arithmetic of every row is the same as in one pass to the end.
+struct TolPass {
+  const int32_t* list_in;    // rows of this pass (null: all rows in order, first pass)
+  const int32_t* count_in;   // number of listed rows (device)
+  int budget;                // sweeps per row in this pass
+  int32_t* used;             // per row: sweeps so far (may be null in a single pass)
+  int32_t* flags;            // per row: bit 0 unconverged, bit 1 started cold (may be null)
+  int32_t* wave_cnt;         // per wave: rows left pending (null: last pass, none kept)
+  int32_t* wave_rows;        // per wave: those rows, 64 slots
+};
+
+template <int KC, int W, int SW>
+__global__ __launch_bounds__(64) void prox_cd_tol_kernel(const float* __restrict__ gp,
+                                                         const float* __restrict__ den,
+                                                         const float* __restrict__ inv,
+                                                         const float* __restrict__ R, const float* C,
+                                                         const float* start, float* U, int64_t rows,
+                                                         int k, float mu, float tol, int max_sweeps,
+                                                         float upper, TolPass pass) {
+  constexpr int kWords = Panel<SW>::WORDS > 2 * 64 * SW ? Panel<SW>::WORDS : 2 * 64 * SW;
+  __shared__ float lds[kWords];
+  float* panel = lds;
+  QPanel<SW>& qp = *reinterpret_cast<QPanel<SW>*>(panel);
+  const int64_t wave = blockIdx.x;
+  const int lane = lane_id();
+  int64_t row0 = wave * 64;
+  const int32_t* rmap = nullptr;
+  int nrows;
+  if (pass.list_in != nullptr) {
+    const int64_t cnt = *pass.count_in;
+    if (row0 >= cnt) {
+      if (pass.wave_cnt != nullptr && lane == 0) pass.wave_cnt[wave] = 0;
+      return;
+    }
+    nrows = static_cast<int>(cnt - row0 < 64 ? cnt - row0 : 64);
+    rmap = pass.list_in + row0;
   } else {
-    // Sweeps run on the lanes whose row is pending (projected-gradient norm
-    // above tol) until every row has converged or spent max_sweeps; the
-    // loop is wave-uniform (the panels are loaded by the whole wave) and a
-    // lane that is done keeps its row.  With a warm start, each row starts
-    // from whichever of the warm start and the cold start (the centre U^t)
-    // has the smaller projected-gradient norm; a start that is not finite
-    // is never taken.
+    nrows = static_cast<int>(rows - row0 < 64 ? rows - row0 : 64);
+  }
+  const bool valid = lane < nrows;
+  const int64_t myrow = valid ? (rmap != nullptr ? static_cast<int64_t>(rmap[lane]) : row0 + lane) : 0;
+  const float ub = upper > 0.f ? upper : INFINITY;
+  RowBlocks<KC, W> u;
+  int used = 0;
+  bool fell_back = false;
+  float res = INFINITY;   // a listed row is pending
+  if (rmap == nullptr) {
+    load_rows<KC, W, SW>(panel, start != nullptr ? start : U, row0, nrows, k, true, u);
     bool ok = valid;
     if (start != nullptr) {
 #pragma unroll
@@ -497,57 +584,72 @@ __global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ g
       if (c == 0) res_w = r;
       else res_c = r;
     }
-    float res = res_w;
+    res = res_w;
     if (start != nullptr) {
       const bool warm = ok && res_w < res_c;
       fell_back = valid && !warm;
       if (__any(warm)) load_rows<KC, W, SW, true>(panel, start, row0, nrows, k, warm, u);
       res = warm ? res_w : res_c;
     }
-    bool pend = false;
-    for (;;) {
-      if (valid) pend = res > tol;
-      const bool run = valid && pend && used < max_sweeps;
-      if (!__any(run)) break;
-      sweep<KC, W, SW>(qp, gp, inv, R, C, row0, nrows, k, mu, ub, run, false, u);
-      if (run) ++used;
-      res = kkt<KC, W, SW>(qp, gp, den, R, C, row0, nrows, k, mu, u);
-    }
-    unconverged = pend;
+  } else {
+    load_rows<KC, W, SW>(panel, U, row0, nrows, k, true, u, rmap);
+    used = valid && pass.used != nullptr ? pass.used[myrow] : 0;
   }
-  store_rows<KC, W, SW>(panel, U, row0, nrows, k, u);
-  if (valid && sweeps_used != nullptr) sweeps_used[row0 + lane_id()] = used;
-  if (TO_TOL && wave_counts != nullptr) {
-    // wave totals, stored per wave and summed by count_reduce_kernel (one
-    // atomic per wave on three shared addresses serialises in L2 and stalls
-    // the loads of every other wave behind it)
-    unsigned long long a = static_cast<unsigned long long>(used);
-    unsigned long long b = unconverged ? 1ull : 0ull;
-    unsigned long long f = fell_back ? 1ull : 0ull;
-    for (int o = 32; o > 0; o >>= 1) {
-      a += __shfl_down(a, o, 64);
-      b += __shfl_down(b, o, 64);
-      f += __shfl_down(f, o, 64);
+  int here = 0;
+  bool pend = false;
+  for (;;) {
+    if (valid) pend = res > tol;
+    const bool run = valid && pend && used < max_sweeps && here < pass.budget;
+    if (!__any(run)) break;
+    sweep<KC, W, SW>(qp, gp, inv, R, C, row0, nrows, k, mu, ub, run, false, u, rmap);
+    if (run) {
+      ++used;
+      ++here;
     }
-    if (lane_id() == 0) {
-      unsigned long long* w = wave_counts + 3 * wave_id;
-      w[0] = a;
-      w[1] = b;
-      w[2] = f;
+    res = kkt<KC, W, SW>(qp, gp, den, R, C, row0, nrows, k, mu, u, rmap);
+  }
+  store_rows<KC, W, SW>(panel, U, row0, nrows, k, u, rmap);
+  const bool keep = valid && pend && used < max_sweeps && pass.wave_cnt != nullptr;
+  if (valid) {
+    if (pass.used != nullptr) pass.used[myrow] = used;
+    if (pass.flags != nullptr) {
+      const int32_t unconv = !keep && pend ? 1 : 0;
+      if (rmap == nullptr) pass.flags[myrow] = (fell_back ? 2 : 0) | unconv;
+      else if (unconv) pass.flags[myrow] |= 1;
     }
+  }
+  if (pass.wave_cnt != nullptr) {
+    const unsigned long long m = __ballot(keep);
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    if (keep) pass.wave_rows[wave * 64 + rank] = static_cast<int32_t>(myrow);
+    if (lane == 0) pass.wave_cnt[wave] = __popcll(m);
   }
 }
 
-// counters[c] += sum over waves of wave_counts[3 w + c] (one block).
-__global__ __launch_bounds__(256) void count_reduce_kernel(const unsigned long long* __restrict__ wave_counts,
-                                                           int64_t nwaves,
-                                                           unsigned long long* __restrict__ counters) {
+// list[wave_off[w] + r] = wave_rows[64 w + r] for r < wave_cnt[w]: the rows
+// left pending, in wave order.
+__global__ __launch_bounds__(256) void tol_compact_kernel(const int32_t* __restrict__ wave_cnt,
+                                                          const int32_t* __restrict__ wave_off,
+                                                          const int32_t* __restrict__ wave_rows,
+                                                          int64_t nwaves, int32_t* __restrict__ list) {
+  const int64_t t = blockIdx.x * 256ll + threadIdx.x;
+  const int64_t w = t >> 6;
+  const int r = static_cast<int>(t & 63);
+  if (w < nwaves && r < wave_cnt[w]) list[wave_off[w] + r] = wave_rows[t];
+}
+
+// counters += (sum of used, rows with bit 0, rows with bit 1) over all rows
+// (one block, fixed order).
+__global__ __launch_bounds__(256) void tol_stats_kernel(const int32_t* __restrict__ used,
+                                                        const int32_t* __restrict__ flags,
+                                                        int64_t rows,
+                                                        unsigned long long* __restrict__ counters) {
   __shared__ unsigned long long part[3][256];
   unsigned long long a = 0, b = 0, f = 0;
-  for (int64_t w = threadIdx.x; w < nwaves; w += 256) {
-    a += wave_counts[3 * w];
-    b += wave_counts[3 * w + 1];
-    f += wave_counts[3 * w + 2];
+  for (int64_t i = threadIdx.x; i < rows; i += 256) {
+    a += static_cast<unsigned long long>(used[i]);
+    b += flags[i] & 1;
+    f += (flags[i] >> 1) & 1;
   }
   part[0][threadIdx.x] = a;
   part[1][threadIdx.x] = b;
@@ -610,32 +712,63 @@ __global__ __launch_bounds__(64) void pgd_kernel(const float* __restrict__ gp,
 template <int KC, int W, int SW>
 dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, float* U,
                      int64_t rows, int k, float mu, int sweeps, float tol, int max_sweeps,
-                     float upper, int32_t* sweeps_used, unsigned long long* counters,
-                     unsigned long long* wave_counts, void* ws, hipStream_t s, const float* start) {
+                     float upper, int32_t* sweeps_used, const TolWork* tw, void* ws, hipStream_t s,
+                     const float* start) {
   static_assert(SW % W == 0, "a panel holds whole register blocks");
   Prep p = carve_prep(ws, KC);
   prep_kernel<<<KC, 64, 0, s>>>(G, k, KC, mu, p.gp, p.gdiag, p.den, p.inv, p.colsum);
   DSANLS_LAUNCHED("prep_kernel");
   if (rows == 0) return DSANLS_OK;
-  const unsigned grid = static_cast<unsigned>(ceil_div(rows, 64));
+  const int64_t nw = ceil_div(rows, 64);
+  const unsigned grid = static_cast<unsigned>(nw);
   if (pgd) {
     pgd_kernel<KC, W, SW><<<grid, 64, 0, s>>>(p.gp, p.gdiag, p.colsum, R, U, rows, k, mu, upper);
     DSANLS_LAUNCHED("pgd_kernel");
-  } else if (sweeps > 0) {
-    prox_cd_kernel<KC, W, SW, false><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, nullptr, U, rows, k, mu,
-                                                         sweeps, tol, max_sweeps, upper, sweeps_used, nullptr);
-    DSANLS_LAUNCHED("prox_cd_kernel");
-  } else {
-    const bool count = counters != nullptr && wave_counts != nullptr;
-    prox_cd_kernel<KC, W, SW, true><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, start, U, rows, k,
-                                                        mu, sweeps, tol, max_sweeps, upper,
-                                                        sweeps_used, count ? wave_counts : nullptr);
-    DSANLS_LAUNCHED("prox_cd_kernel");
-    if (count) {
-      count_reduce_kernel<<<1, 256, 0, s>>>(wave_counts, static_cast<int64_t>(grid), counters);
-      DSANLS_LAUNCHED("count_reduce_kernel");
-    }
+    return DSANLS_OK;
   }
+  if (sweeps > 0) {
+    prox_cd_kernel<KC, W, SW><<<grid, 64, 0, s>>>(p.gp, p.inv, R, C, U, rows, k, mu, sweeps, upper, sweeps_used);
+    DSANLS_LAUNCHED("prox_cd_kernel");
+    return DSANLS_OK;
+  }
+  if (tw == nullptr) {
+    // one pass to the end (no compaction workspace)
+    const TolPass one{nullptr, nullptr, max_sweeps, sweeps_used, nullptr, nullptr, nullptr};
+    prox_cd_tol_kernel<KC, W, SW><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, start, U, rows, k, mu, tol,
+                                                      max_sweeps, upper, one);
+    DSANLS_LAUNCHED("prox_cd_tol_kernel");
+    return DSANLS_OK;
+  }
+  // passes with budgets 16, 16, 32, 64, ... sweeps; the last pass runs to
+  // max_sweeps and lists nothing.  Each pass writes U, so a centre that
+  // aliases U is copied first.
+  if (C == U) {
+    DSANLS_HIP(hipMemcpyAsync(tw->centre, C, sizeof(float) * rows * k, hipMemcpyDeviceToDevice, s));
+    C = tw->centre;
+  }
+  int budget = 16, spent = 0;
+  for (int pass_no = 0;; ++pass_no) {
+    const bool last = spent + budget >= max_sweeps;
+    TolPass ps{pass_no == 0 ? nullptr : tw->list[pass_no & 1], pass_no == 0 ? nullptr : tw->wave_off + nw,
+               last ? max_sweeps : budget, tw->used, tw->flags, last ? nullptr : tw->wave_cnt, tw->wave_rows};
+    prox_cd_tol_kernel<KC, W, SW><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, start, U, rows, k, mu, tol,
+                                                      max_sweeps, upper, ps);
+    DSANLS_LAUNCHED("prox_cd_tol_kernel");
+    if (last) break;
+    dsanls_status st = launch_exclusive_scan(tw->wave_cnt, tw->wave_off, nw, tw->scan_ws, s);
+    if (st != DSANLS_OK) return st;
+    tol_compact_kernel<<<static_cast<unsigned>(ceil_div(nw * 64, 256)), 256, 0, s>>>(
+        tw->wave_cnt, tw->wave_off, tw->wave_rows, nw, tw->list[(pass_no + 1) & 1]);
+    DSANLS_LAUNCHED("tol_compact_kernel");
+    spent += budget;
+    if (pass_no > 0) budget *= 2;
+  }
+  if (tw->counters != nullptr) {
+    tol_stats_kernel<<<1, 256, 0, s>>>(tw->used, tw->flags, rows, tw->counters);
+    DSANLS_LAUNCHED("tol_stats_kernel");
+  }
+  if (sweeps_used != nullptr)
+    DSANLS_HIP(hipMemcpyAsync(sweeps_used, tw->used, sizeof(int32_t) * rows, hipMemcpyDeviceToDevice, s));
   return DSANLS_OK;
 }
 
@@ -659,16 +792,15 @@ size_t nnls_ws_bytes(int k) {
 
 dsanls_status launch_nnls(bool pgd, const float* G, const float* R, const float* C, float* U,
                           int64_t rows, int k, float mu, int sweeps, float tol, int max_sweeps,
-                          float upper, int32_t* sweeps_used, unsigned long long* counters,
-                          unsigned long long* wave_counts, void* ws, size_t ws_bytes,
-                          hipStream_t s, const float* start) {
+                          float upper, int32_t* sweeps_used, const TolWork* tw, void* ws,
+                          size_t ws_bytes, hipStream_t s, const float* start) {
   if (k < 1 || k > kMaxK) return fail(DSANLS_E_UNSUPPORTED, "NNLS supports 1 <= k <= 128");
   if (ws_bytes < nnls_ws_bytes(k)) return fail(DSANLS_E_WORKSPACE, "NNLS workspace too small");
   switch (nnls_kc(k)) {
 #define DSANLS_KC(KC, W, SW)                                                                         \
   case KC:                                                                                           \
     return run_kc<KC, W, SW>(pgd, G, R, C, U, rows, k, mu, sweeps, tol, max_sweeps, upper,          \
-                             sweeps_used, counters, wave_counts, ws, s, start);
+                             sweeps_used, tw, ws, s, start);
     DSANLS_KC(4, 4, 4)
     DSANLS_KC(8, 8, 8)
     DSANLS_KC(10, 16, 16)
@@ -702,7 +834,7 @@ extern "C" dsanls_status dsanls_nnls_prox_cd(const float* G, const float* R, con
   if (sweeps < 0 || (sweeps == 0 && (max_sweeps < 1 || !(tol >= 0.f))) || !(mu >= 0.f))
     return fail(DSANLS_E_INVALID_ARG, "nnls_prox_cd: bad sweeps/tol/mu");
   return launch_nnls(false, G, R, C, U, rows, k, mu, sweeps, tol, max_sweeps, upper, sweeps_used,
-                     nullptr, nullptr, workspace, workspace_bytes, static_cast<hipStream_t>(hip_stream));
+                     nullptr, workspace, workspace_bytes, static_cast<hipStream_t>(hip_stream));
 }
 
 extern "C" dsanls_status dsanls_pgd_step(const float* G, const float* R, float* U, int64_t rows,
@@ -710,6 +842,6 @@ extern "C" dsanls_status dsanls_pgd_step(const float* G, const float* R, float* 
                                          size_t workspace_bytes, void* hip_stream) {
   if (rows < 0 || !G || (rows > 0 && (!R || !U)) || !workspace || !(mu >= 0.f))
     return fail(DSANLS_E_INVALID_ARG, "pgd_step: bad arguments");
-  return launch_nnls(true, G, R, nullptr, U, rows, k, mu, 1, 0.f, 1, upper, nullptr, nullptr, nullptr,
+  return launch_nnls(true, G, R, nullptr, U, rows, k, mu, 1, 0.f, 1, upper, nullptr, nullptr,
                      workspace, workspace_bytes, static_cast<hipStream_t>(hip_stream));
 }
