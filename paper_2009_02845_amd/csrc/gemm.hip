@@ -339,17 +339,21 @@ typedef unsigned short ushortx8 __attribute__((ext_vector_type(8)));
 
 constexpr int kBKh = 64;
 constexpr int kLdsh = kBKh + 8;
-// BF16 block tile: four waves of 128 x 128 (4 x 4 MFMA tiles each), so that
-// every fragment read from LDS feeds four MFMAs: LDS reads 64 B/clk per CU
-// at the MFMA rate (a 64 x 64 wave tile needs 128 B/clk, the whole LDS port).
+// BF16 block tile 256 x 256 in eight waves of 128 x 64 (4 x 2 MFMA tiles):
+// two waves per SIMD, so one wave's MFMAs cover the other's wait for its
+// next stage (1.12x over four waves of 128 x 128 at one wave per SIMD),
+// while every fragment read from LDS still feeds two to four MFMAs (a
+// 64 x 64 wave tile would need 128 B/clk of LDS reads per CU at the MFMA
+// rate, the whole port).
 constexpr int kBMh = 256, kBNh = 256;
+constexpr int kWvMh = 2, kWvNh = 4;
 
-template <int NV, bool VEC>
+template <int NV, bool VEC, int NT = 256>
 __device__ __forceinline__ void load_stage_h(const unsigned short* __restrict__ P, int64_t ld, int r0,
                                              int nrows, int k0, int kend, ushortx8 (&reg)[NV]) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    const int id = v * 256 + threadIdx.x;
+    const int id = v * NT + threadIdx.x;
     const int r = id >> 3, kq = (id & 7) * 8;
     const int gr = r0 + r, gk = k0 + kq;
     ushortx8 x = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -367,23 +371,25 @@ __device__ __forceinline__ void load_stage_h(const unsigned short* __restrict__ 
   }
 }
 
-template <int NV>
+template <int NV, int NT = 256>
 __device__ __forceinline__ void store_stage_h(unsigned short* __restrict__ s, const ushortx8 (&reg)[NV]) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    const int id = v * 256 + threadIdx.x;
+    const int id = v * NT + threadIdx.x;
     const int r = id >> 3, kq = (id & 7) * 8;
     *reinterpret_cast<ushortx8*>(s + r * kLdsh + kq) = reg[v];
   }
 }
 
-template <int BM, int BN, bool VEC>
-__global__ __launch_bounds__(256, (BM * BN > 128 * 128 ? 1 : 2)) void gemm_nt_bf16_kernel(Problem<unsigned short> p0,
+template <int BM, int BN, bool VEC, int WVM = 2, int WVN = 2>
+__global__ __launch_bounds__(64 * WVM * WVN, 1) void gemm_nt_bf16_kernel(Problem<unsigned short> p0,
                                                               Problem<unsigned short> p1) {
   __shared__ __attribute__((aligned(16))) unsigned short sX[2 * BM * kLdsh];
   __shared__ __attribute__((aligned(16))) unsigned short sY[2 * BN * kLdsh];
-  constexpr int FM = BM / 64, FN = BN / 64;
-  constexpr int XV = BM * kBKh / 8 / 256, YV = BN * kBKh / 8 / 256;
+  // WVM x WVN waves, each a (BM / WVM) x (BN / WVN) tile of 32 x 32 MFMA tiles
+  constexpr int NT = 64 * WVM * WVN, TM = BM / WVM, TN = BN / WVN;
+  constexpr int FM = TM / 32, FN = TN / 32;
+  constexpr int XV = BM * kBKh / 8 / NT, YV = BN * kBKh / 8 / NT;
   int row0, col0;
   Problem<unsigned short> p;
   if (!pick<BM, BN>(p0, p1, p, row0, col0)) return;
@@ -392,7 +398,7 @@ __global__ __launch_bounds__(256, (BM * BN > 128 * 128 ? 1 : 2)) void gemm_nt_bf
   const int64_t ldx = p.ldx, ldy = p.ldy;
   const int rows = p.rows, cols = p.cols, K = p.K;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WVN, wn = wave % WVN;
   const int lrow = lane & 31, lk = (lane >> 5) * 8;
   floatx16 acc[FM][FN];
 #pragma unroll
@@ -403,17 +409,17 @@ __global__ __launch_bounds__(256, (BM * BN > 128 * 128 ? 1 : 2)) void gemm_nt_bf
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
   if (K > 0) {
     ushortx8 rx[XV], ry[YV];
-    load_stage_h<XV, VEC>(X, ldx, row0, rows, 0, K, rx);
-    load_stage_h<YV, VEC>(Y, ldy, col0, cols, 0, K, ry);
-    store_stage_h<XV>(sX, rx);
-    store_stage_h<YV>(sY, ry);
+    load_stage_h<XV, VEC, NT>(X, ldx, row0, rows, 0, K, rx);
+    load_stage_h<YV, VEC, NT>(Y, ldy, col0, cols, 0, K, ry);
+    store_stage_h<XV, NT>(sX, rx);
+    store_stage_h<YV, NT>(sY, ry);
     __syncthreads();
     int buf = 0;
     for (int k0 = 0; k0 < K; k0 += kBKh) {
       const bool more = k0 + kBKh < K;
       if (more) {
-        load_stage_h<XV, VEC>(X, ldx, row0, rows, k0 + kBKh, K, rx);
-        load_stage_h<YV, VEC>(Y, ldy, col0, cols, k0 + kBKh, K, ry);
+        load_stage_h<XV, VEC, NT>(X, ldx, row0, rows, k0 + kBKh, K, rx);
+        load_stage_h<YV, VEC, NT>(Y, ldy, col0, cols, k0 + kBKh, K, ry);
       }
       const unsigned short* cx = sX + buf * (BM * kLdsh);
       const unsigned short* cy = sY + buf * (BN * kLdsh);
@@ -422,10 +428,10 @@ __global__ __launch_bounds__(256, (BM * BN > 128 * 128 ? 1 : 2)) void gemm_nt_bf
         bf16x8 a[FM], b[FN];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
-          a[i] = *reinterpret_cast<const bf16x8*>(cx + (wm * (BM / 2) + i * 32 + lrow) * kLdsh + kk + lk);
+          a[i] = *reinterpret_cast<const bf16x8*>(cx + (wm * TM + i * 32 + lrow) * kLdsh + kk + lk);
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-          b[j] = *reinterpret_cast<const bf16x8*>(cy + (wn * (BN / 2) + j * 32 + lrow) * kLdsh + kk + lk);
+          b[j] = *reinterpret_cast<const bf16x8*>(cy + (wn * TN + j * 32 + lrow) * kLdsh + kk + lk);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -433,8 +439,8 @@ __global__ __launch_bounds__(256, (BM * BN > 128 * 128 ? 1 : 2)) void gemm_nt_bf
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
       }
       if (more) {
-        store_stage_h<XV>(sX + (buf ^ 1) * (BM * kLdsh), rx);
-        store_stage_h<YV>(sY + (buf ^ 1) * (BN * kLdsh), ry);
+        store_stage_h<XV, NT>(sX + (buf ^ 1) * (BM * kLdsh), rx);
+        store_stage_h<YV, NT>(sY + (buf ^ 1) * (BN * kLdsh), ry);
       }
       __syncthreads();
       buf ^= 1;
@@ -444,10 +450,10 @@ __global__ __launch_bounds__(256, (BM * BN > 128 * 128 ? 1 : 2)) void gemm_nt_bf
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      const int col = col0 + wn * (BN / 2) + j * 32 + (lane & 31);
+      const int col = col0 + wn * TN + j * 32 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = row0 + wm * (BM / 2) + i * 32 + acc_row(r, lane);
+        const int row = row0 + wm * TM + i * 32 + acc_row(r, lane);
         if (row < rows && col < cols) p.C[(int64_t)row * p.ldc + col] = acc[i][j][r];
       }
     }
@@ -577,9 +583,9 @@ dsanls_status launch_gemm_grouped(const GemmDesc& a_in, const GemmDesc& b_in, bo
     if (p0.ntiles + p1.ntiles == 0) return DSANLS_OK;
     const int grid = grouped_grid(p0.ntiles, p1.ntiles);
     if (vec)
-      gemm_nt_bf16_kernel<kBMh, kBNh, true><<<grid, 256, 0, s>>>(p0, p1);
+      gemm_nt_bf16_kernel<kBMh, kBNh, true, kWvMh, kWvNh><<<grid, 64 * kWvMh * kWvNh, 0, s>>>(p0, p1);
     else
-      gemm_nt_bf16_kernel<kBMh, kBNh, false><<<grid, 256, 0, s>>>(p0, p1);
+      gemm_nt_bf16_kernel<kBMh, kBNh, false, kWvMh, kWvNh><<<grid, 64 * kWvMh * kWvNh, 0, s>>>(p0, p1);
     DSANLS_LAUNCHED("gemm_nt_bf16_kernel");
     return DSANLS_OK;
   }
