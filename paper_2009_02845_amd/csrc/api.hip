@@ -30,6 +30,9 @@ constexpr int64_t kMaxRank = 128;
 
 int64_t r4(int64_t x) { return (x + 3) / 4 * 4; }
 int64_t r8(int64_t x) { return (x + 7) / 8 * 8; }
+// BF16 operands of the sketch product: rows padded with zeros to 32 bf16, so
+// the product runs on the ring kernel with K rounded up to 32 (zeros add nothing)
+int64_t r32(int64_t x) { return (x + 31) / 32 * 32; }
 
 // Device buffers carved from the caller's workspace.
 struct Layout {
@@ -99,8 +102,8 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
     L.Mt = reinterpret_cast<float*>(take(sizeof(float) * n * L.ldmt));
   }
   if (is_dense && bf16) {
-    L.ldmb = r8(n);
-    L.ldmtb = r8(m);
+    L.ldmb = r32(n);
+    L.ldmtb = r32(m);
     L.Mb = reinterpret_cast<__hip_bfloat16*>(take(2 * m * L.ldmb));
     L.Mtb = reinterpret_cast<__hip_bfloat16*>(take(2 * n * L.ldmtb));
   }
@@ -109,7 +112,7 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
   for (int sd = 0; sd < 2; ++sd) {
     if (gauss) {
       L.St[sd] = reinterpret_cast<float*>(take(sizeof(float) * side_d[sd] * r4(side_lng[sd])));
-      if (bf16) L.Sb[sd] = reinterpret_cast<__hip_bfloat16*>(take(2 * side_d[sd] * r8(side_lng[sd])));
+      if (bf16) L.Sb[sd] = reinterpret_cast<__hip_bfloat16*>(take(2 * side_d[sd] * r32(side_lng[sd])));
     }
     if (is_dense && (gauss || sub))
       L.A[sd] = reinterpret_cast<float*>(take(sizeof(float) * side_rows[sd] * r4(side_d[sd])));
@@ -381,7 +384,7 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
       for (int sd = both ? 0 : 1; sd < 2; ++sd) {
         const int64_t lng_s = sd == 0 ? c.n : c.m, d_s = sd == 0 ? c.d : c.d_prime;
         CHECK(launch_gaussian_sketch_t(c.seed, tt, sd, lng_s, d_s, L.St[sd], r4(lng_s),
-                                       bf16 ? L.Sb[sd] : nullptr, s));
+                                       bf16 ? L.Sb[sd] : nullptr, r32(lng_s), s));
       }
       CHECK(mark(ctx, kPhSketch));
       CHECK(mark(ctx, kPhProduct));
@@ -390,8 +393,8 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
         const int64_t rows_s = sd == 0 ? c.m : c.n, lng_s = sd == 0 ? c.n : c.m;
         const int64_t d_s = sd == 0 ? c.d : c.d_prime;
         if (bf16)
-          g[sd] = GemmDesc{sd == 0 ? L.Mb : L.Mtb, sd == 0 ? L.ldmb : L.ldmtb, L.Sb[sd], r8(lng_s), L.A[sd],
-                           r4(d_s), rows_s, d_s, lng_s};
+          g[sd] = GemmDesc{sd == 0 ? L.Mb : L.Mtb, sd == 0 ? L.ldmb : L.ldmtb, L.Sb[sd], r32(lng_s), L.A[sd],
+                           r4(d_s), rows_s, d_s, r32(lng_s)};
         else
           g[sd] = GemmDesc{sd == 0 ? ctx->mat.dense : ctx->Mt, sd == 0 ? ctx->mat.ld : ctx->ldmt, L.St[sd],
                            r4(lng_s), L.A[sd], r4(d_s), rows_s, d_s, lng_s};
@@ -572,6 +575,12 @@ dsanls_status dsanls_init(const dsanls_config* cfg, const dsanls_matrix* M, floa
     if (c.precision == DSANLS_PREC_BF16_SKETCH) {
       if ((st = launch_to_bf16(M->dense, M->ld, L.Mb, L.ldmb, c.m, c.n, s)) != DSANLS_OK) return bail(st);
       if ((st = launch_to_bf16(ctx->Mt, ctx->ldmt, L.Mtb, L.ldmtb, c.n, c.m, s)) != DSANLS_OK) return bail(st);
+      // the sketch kernel writes columns < lng of S^T only: zero the padding once
+      for (int sd = 0; sd < 2; ++sd)
+        if (L.Sb[sd] != nullptr) {
+          const int64_t lng_s = sd == 0 ? c.n : c.m, d_s = sd == 0 ? c.d : c.d_prime;
+          if ((st = launch_to_bf16(nullptr, 0, L.Sb[sd], r32(lng_s), d_s, 0, s)) != DSANLS_OK) return bail(st);
+        }
     }
     if ((st = launch_sumsq(M->dense, M->ld, c.m, c.n, L.partials, s)) != DSANLS_OK) return bail(st);
     if ((st = launch_combine_partials(L.partials, sumsq_partials(c.m, c.n), 2, L.red, L.err, s)) != DSANLS_OK)

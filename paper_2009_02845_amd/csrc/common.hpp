@@ -39,7 +39,7 @@ constexpr int kNumXcd = 8;
 
 // ---------------------------------------------------------------- philox.hip
 dsanls_status launch_gaussian_sketch_t(uint64_t seed, uint32_t t, int side, int64_t n, int64_t d,
-                                       float* St, int64_t ld, __hip_bfloat16* St_bf16,
+                                       float* St, int64_t ld, __hip_bfloat16* St_bf16, int64_t ld_bf16,
                                        hipStream_t s);
 // Workspace layout of the subsample selection.
 size_t subsample_ws_bytes(int64_t n);
@@ -79,6 +79,7 @@ dsanls_status launch_residual_sq(const float* M, int64_t ldm, const float* U, co
 // ---------------------------------------------------------------- small.hip
 dsanls_status launch_transpose(const float* X, int64_t ldx, float* Y, int64_t ldy, int64_t rows,
                                int64_t cols, hipStream_t s);
+// Y = bf16(X) (rows x cols, round to nearest even), zeros in columns cols .. ldy - 1
 dsanls_status launch_to_bf16(const float* X, int64_t ldx, __hip_bfloat16* Y, int64_t ldy,
                              int64_t rows, int64_t cols, hipStream_t s);
 // G = B B^T (k x k) with compensated FP32 sums; B is k x d (ld).

@@ -329,8 +329,9 @@ __global__ __launch_bounds__(256, 2) void residual_kernel(const float* __restric
 
 
 // ---------------------------------------------------------------- BF16
-// A = M S with M and S rounded to BF16 (the precision form): the same
-// 2 x 2 wave layout with v_mfma_f32_32x32x16_bf16 (FP32 accumulation).
+// A = M S with M and S rounded to BF16 (the precision form) on
+// v_mfma_f32_32x32x16_bf16 (FP32 accumulation).  General kernel (any K,
+// leading dimension or alignment): operands staged through registers.
 // K advances 64 bf16 (128 bytes per row) per stage; the LDS row stride of
 // 72 bf16 (36 dwords) keeps 16-byte fragment reads conflict-free.  Lane
 // halves take k blocks 0-7 and 8-15 of each 16-wide step for both operands.
@@ -444,6 +445,137 @@ __global__ __launch_bounds__(64 * WVM * WVN, 1) void gemm_nt_bf16_kernel(Problem
       }
       __syncthreads();
       buf ^= 1;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = col0 + wn * TN + j * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = row0 + wm * TM + i * 32 + acc_row(r, lane);
+        if (row < rows && col < cols) p.C[(int64_t)row * p.ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+// Fast BF16 kernel, for K a multiple of 32 and 16-byte aligned rows (the
+// method pads its BF16 copies of M and S with zero columns to that).  The
+// operands go from HBM straight into LDS (global_load_lds_dwordx4, no
+// register staging) through a ring of NS stages of 32 k each: while one
+// stage feeds the MFMAs, the next NS - 1 are in flight, so a load has NS - 1
+// stage times to arrive (the register-staged kernel gives it one).  One DMA
+// load writes 64 consecutive 16-byte slots (16 tile rows of 32 bf16), so the
+// rows cannot be padded apart; instead chunk c of tile row r lives in slot
+// c ^ f(r), and each lane fetches the chunk that belongs in its slot.  With
+// bits r1, r2, r3 of r, f(r) = r2 | (r1 ^ r3) << 1 puts the eight lanes that
+// a 16-byte LDS read serves together on distinct banks whether those are
+// eight consecutive lanes or two quads q, q ^ x (x odd) of a half-wave; the
+// 0 bank-conflict cycles it measures compare with 1.5e9 per launch for
+// ((r >> 1) ^ (r >> 3)) & 3, which only spreads consecutive lanes (a 2.4%
+// difference in time).  Tile rows past the end of an operand re-read its
+// last row (their results are not stored).  The compiler orders neither the
+// DMA writes before the fragment reads nor the reads before the next DMA
+// into the same stage, so the waits are explicit: vmcnt for this wave's own
+// loads, then lgkmcnt(0) and a barrier for every wave's.
+constexpr int kBKd = 32;
+// four stages (128 KB of LDS): 1.01x over three, 1.01x over five
+constexpr int kRingd = 4;
+
+__device__ __forceinline__ int swz_bf16(int r) { return ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1); }
+
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N == 0 || N == 4 || N == 8 || N == 16 || N == 32, "vmcnt immediate");
+  if constexpr (N == 0) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  else if constexpr (N == 4) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+  else if constexpr (N == 8) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+  else if constexpr (N == 16) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+  else asm volatile("s_waitcnt vmcnt(32)" ::: "memory");
+}
+
+// every wave's LDS reads done, then all waves meet
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// 256 rows x 32 bf16 of one operand (16 DMA loads of 16 rows) into a stage.
+// (Dword loads, each writing 256 contiguous bytes, were 1.27x slower.)
+template <int NW>
+__device__ __forceinline__ void dma_tile(const unsigned short* __restrict__ P, int64_t ld, int r0,
+                                         int nrows, int k0, unsigned short* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 16 / NW; ++i) {
+    const int blk = i * NW + wave;
+    const int r = blk * 16 + (lane >> 2);
+    const int c = (lane & 3) ^ swz_bf16(r);
+    const int gr = min(r0 + r, nrows - 1);
+    __builtin_amdgcn_global_load_lds(P + (int64_t)gr * ld + k0 + c * 8, lds + blk * 16 * kBKd, 16, 0, 0);
+  }
+}
+
+template <int WVM, int WVN, int NS>
+__global__ __launch_bounds__(64 * WVM * WVN, 1) void gemm_nt_bf16_dma_kernel(Problem<unsigned short> p0,
+                                                                             Problem<unsigned short> p1) {
+  constexpr int BM = 256, BN = 256, NW = WVM * WVN, TM = BM / WVM, TN = BN / WVN;
+  constexpr int FM = TM / 32, FN = TN / 32;
+  constexpr int STAGE = (BM + BN) * kBKd;   // bf16 per stage (X tile, then Y tile)
+  constexpr int IPW = 2 * 16 / NW;          // DMA loads per wave per stage
+  static_assert(16 % NW == 0 && NS >= 2, "tile split");
+  __shared__ __attribute__((aligned(1024))) unsigned short sm[NS * STAGE];
+  int row0, col0;
+  Problem<unsigned short> p;
+  if (!pick<BM, BN>(p0, p1, p, row0, col0)) return;
+  const unsigned short* X = p.X;
+  const unsigned short* Y = p.Y;
+  const int64_t ldx = p.ldx, ldy = p.ldy;
+  const int rows = p.rows, cols = p.cols, nk = p.K / kBKd;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WVN, wn = wave % WVN;
+  const int lrow = lane & 31, hi = lane >> 5;
+  // tile rows of a fragment are 32-aligned, so the slot swizzle depends on lrow only
+  const int sw = swz_bf16(lrow);
+  const int off0 = lrow * kBKd + ((hi ^ sw) << 3), off1 = lrow * kBKd + (((2 + hi) ^ sw) << 3);
+  floatx16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+#pragma unroll
+  for (int st = 0; st < NS - 1; ++st)
+    if (st < nk) {
+      dma_tile<NW>(X, ldx, row0, rows, st * kBKd, sm + st * STAGE);
+      dma_tile<NW>(Y, ldy, col0, cols, st * kBKd, sm + st * STAGE + BM * kBKd);
+    }
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + NS - 2 < nk)
+      wait_vm<(NS - 2) * IPW>();
+    else
+      wait_vm<0>();
+    lds_barrier();
+    const int nx = kt + NS - 1;
+    if (nx < nk) {
+      unsigned short* dst = sm + (nx % NS) * STAGE;
+      dma_tile<NW>(X, ldx, row0, rows, nx * kBKd, dst);
+      dma_tile<NW>(Y, ldy, col0, cols, nx * kBKd, dst + BM * kBKd);
+    }
+    const unsigned short* sx = sm + (kt % NS) * STAGE + wm * TM * kBKd;
+    const unsigned short* sy = sm + (kt % NS) * STAGE + BM * kBKd + wn * TN * kBKd;
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const int off = kk == 0 ? off0 : off1;
+      bf16x8 a[FM], b[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const bf16x8*>(sx + i * 32 * kBKd + off);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = *reinterpret_cast<const bf16x8*>(sy + j * 32 * kBKd + off);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -582,6 +714,12 @@ dsanls_status launch_gemm_grouped(const GemmDesc& a_in, const GemmDesc& b_in, bo
       return fail(DSANLS_E_SHAPE, "gemm: dimension exceeds int32");
     if (p0.ntiles + p1.ntiles == 0) return DSANLS_OK;
     const int grid = grouped_grid(p0.ntiles, p1.ntiles);
+    const bool dma = vec && p0.K % kBKd == 0 && (p1.ntiles == 0 || p1.K % kBKd == 0);
+    if (dma) {
+      gemm_nt_bf16_dma_kernel<kWvMh, kWvNh, kRingd><<<grid, 64 * kWvMh * kWvNh, 0, s>>>(p0, p1);
+      DSANLS_LAUNCHED("gemm_nt_bf16_dma_kernel");
+      return DSANLS_OK;
+    }
     if (vec)
       gemm_nt_bf16_kernel<kBMh, kBNh, true, kWvMh, kWvNh><<<grid, 64 * kWvMh * kWvNh, 0, s>>>(p0, p1);
     else

@@ -65,7 +65,7 @@ __global__ void philox_kernel(const uint32_t* __restrict__ ctr, const uint32_t* 
 // sketch GEMM; consecutive threads write consecutive j (coalesced).
 __global__ void gaussian_t_kernel(uint32_t k0, uint32_t k1, uint32_t t, uint32_t side_word,
                                   int64_t n, int64_t d, float scale, float* __restrict__ St,
-                                  int64_t ld, __hip_bfloat16* __restrict__ Sb) {
+                                  int64_t ld, __hip_bfloat16* __restrict__ Sb, int64_t ldb) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const uint32_t q = blockIdx.y;
   if (j >= n) return;
@@ -92,7 +92,7 @@ __global__ void gaussian_t_kernel(uint32_t k0, uint32_t k1, uint32_t t, uint32_t
       float v = z[e] * scale;
       if (Sb != nullptr) {
         const __hip_bfloat16 b = __float2bfloat16(v);  // round to nearest even
-        Sb[c * ld + j] = b;
+        Sb[c * ldb + j] = b;
         v = __bfloat162float(b);
       }
       St[c * ld + j] = v;
@@ -352,7 +352,7 @@ SubWs carve_sub(void* base, int64_t n) {
 }  // namespace
 
 dsanls_status launch_gaussian_sketch_t(uint64_t seed, uint32_t t, int side, int64_t n, int64_t d,
-                                       float* St, int64_t ld, __hip_bfloat16* St_bf16,
+                                       float* St, int64_t ld, __hip_bfloat16* St_bf16, int64_t ld_bf16,
                                        hipStream_t s) {
   if (n <= 0 || d <= 0) return DSANLS_OK;
   const int64_t nq = ceil_div(d, 4);
@@ -361,7 +361,7 @@ dsanls_status launch_gaussian_sketch_t(uint64_t seed, uint32_t t, int side, int6
   dim3 grid(static_cast<unsigned>(ceil_div(n, 256)), static_cast<unsigned>(nq));
   gaussian_t_kernel<<<grid, 256, 0, s>>>(static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), t,
                                          (static_cast<uint32_t>(side) & 0xFFu) | (kKindGaussian << 8), n,
-                                         d, scale, St, ld, St_bf16);
+                                         d, scale, St, ld, St_bf16, ld_bf16);
   DSANLS_LAUNCHED("gaussian_t_kernel");
   return DSANLS_OK;
 }
@@ -421,7 +421,7 @@ extern "C" dsanls_status dsanls_gaussian_sketch_t(uint64_t seed, int64_t t, int3
                                                   void* hip_stream) {
   if (!St || n < 1 || d < 1 || ld_st < n || t < 0 || side < 0 || side > 255)
     return fail(DSANLS_E_INVALID_ARG, "gaussian_sketch_t: bad arguments");
-  return launch_gaussian_sketch_t(seed, static_cast<uint32_t>(t), side, n, d, St, ld_st, nullptr,
+  return launch_gaussian_sketch_t(seed, static_cast<uint32_t>(t), side, n, d, St, ld_st, nullptr, 0,
                                   static_cast<hipStream_t>(hip_stream));
 }
 

@@ -42,14 +42,15 @@ struct ToBf16 {
   __device__ __hip_bfloat16 operator()(float x) const { return __float2bfloat16(x); }
 };
 
+// Y = bf16(X) on rows x cols, zeros in columns cols .. ldy - 1
 __global__ __launch_bounds__(256) void to_bf16_kernel(const float* __restrict__ X, int64_t ldx,
                                                       __hip_bfloat16* __restrict__ Y, int64_t ldy,
                                                       int64_t rows, int64_t cols) {
-  const int64_t total = rows * cols;
+  const int64_t total = rows * ldy;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / cols, c = i % cols;
-    Y[r * ldy + c] = __float2bfloat16(X[r * ldx + c]);
+    const int64_t r = i / ldy, c = i % ldy;
+    Y[i] = c < cols ? __float2bfloat16(X[r * ldx + c]) : __float2bfloat16(0.0f);
   }
 }
 
@@ -287,8 +288,9 @@ dsanls_status launch_transpose(const float* X, int64_t ldx, float* Y, int64_t ld
 
 dsanls_status launch_to_bf16(const float* X, int64_t ldx, __hip_bfloat16* Y, int64_t ldy,
                              int64_t rows, int64_t cols, hipStream_t s) {
-  if (rows <= 0 || cols <= 0) return DSANLS_OK;
-  to_bf16_kernel<<<grid_for(rows * cols, 256 * 8, 1 << 20), 256, 0, s>>>(X, ldx, Y, ldy, rows, cols);
+  if (rows <= 0 || ldy <= 0) return DSANLS_OK;
+  if (cols > ldy) return fail(DSANLS_E_SHAPE, "to_bf16: cols exceed the leading dimension");
+  to_bf16_kernel<<<grid_for(rows * ldy, 256 * 8, 1 << 20), 256, 0, s>>>(X, ldx, Y, ldy, rows, cols);
   DSANLS_LAUNCHED("to_bf16_kernel");
   return DSANLS_OK;
 }

@@ -178,8 +178,11 @@ def test_prox_cd_centre_differs_from_start(torch_dev, k, sweeps):
     assert _rel(U.cpu().numpy(), ref) < 1e-4
 
 
+# K % 32 == 0 with 16-byte rows takes the LDS-ring kernel (ragged rows and
+# columns included), the others the register-staged one
 @pytest.mark.parametrize("rows,cols,K", [(200, 40, 150), (257, 130, 1001), (300, 4096, 2048), (128, 128, 64),
-                                         (129, 65, 17)])
+                                         (129, 65, 17), (257, 300, 96), (513, 1000, 640), (40, 600, 32),
+                                         (700, 520, 4096)])
 def test_gemm_nt_bf16_matches_fp64(torch_dev, rows, cols, K):
     torch, B = torch_dev
     from oracle.bf16 import round_to_bf16

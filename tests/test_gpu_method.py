@@ -325,12 +325,13 @@ def test_sparse_subsample_fetch_indices(env):
     assert np.array_equal(prob.solver.fetch(0, (60,), "int32"), P.subsample_indices(17, 4, 1, 500, 60))
 
 
-def test_bf16_sketch_form_per_update(env):
-    # planted 2000 x 1200 rank-16 + 1% noise, Gaussian d = 256: the BF16 form
-    # matches the oracle of the same form (M, S rounded to bfloat16, exact
-    # products) to FP32 accuracy, and its error against the plain FP64 method
-    # is reported by the bench; here it must stay small
-    m, n, k, d = 2000, 1200, 16, 256
+@pytest.mark.parametrize("m,n,k,d", [(2000, 1200, 16, 256), (300, 180, 8, 40)])
+def test_bf16_sketch_form_per_update(env, m, n, k, d):
+    # planted rank-k + 1% noise, Gaussian sketch: the BF16 form matches the
+    # oracle of the same form (M, S rounded to bfloat16, exact products) to
+    # FP32 accuracy, and its error against the plain FP64 method is reported
+    # by the bench; here it must stay small.  Neither m nor n is a multiple of
+    # 32 (the BF16 copies are zero-padded to that) and 300, 180 are not of 8.
     M = synth.planted_dense(m, n, k, 2, noise_sd=0.01, noise_relative=True).astype(np.float64)
     U0, V0 = synth.init_factors(m, n, k, 2, dtype=np.float64)
     ocfg = _ocfg(k, d, d, O.SKETCH_GAUSSIAN, O.SOLVER_PROX_CD)
