@@ -403,7 +403,10 @@ def main():
         flops_launch = 2.0 * m * n * d + 2.0 * n * m * d
         peak = PEAK["bf16_mfma_tflops"] if w["precision"] == "bf16" else PEAK["fp32_mfma_tflops"]
         achieved = flops_launch / prod_avg_s / 1e12
-        name = "gemm_nt_bf16_dma_kernel" if w["precision"] == "bf16" else "gemm_nt_grouped_kernel"
+        if w["precision"] == "bf16":
+            name = "gemm_nt_bf16_dma_kernel"
+        else:   # the LDS-ring kernel needs both contraction lengths (n, m) to be multiples of 16
+            name = "gemm_nt_f32_dma_kernel" if m % 16 == 0 and n % 16 == 0 else "gemm_nt_grouped_kernel"
         roof = {"kernel": f"sketch GEMMs A = M S, A' = M^T S' ({name}, one launch per iteration)",
                 "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": traffic_bytes(args.workload), "flops_per_launch": flops_launch,

@@ -6,6 +6,10 @@
 // M^T is kept resident next to M, as the paper's node keeps both its row
 // block and its column block of M (Alg. 2 input).
 //
+// The sketch products run on LDS-ring kernels (gemm_nt_f32_dma_kernel,
+// gemm_nt_bf16_dma_kernel, below) when K and the rows allow; otherwise, and
+// for the other products:
+//
 // Tiling (FP32): 256 threads = 4 waves in a 2 x 2 grid; a workgroup owns a
 // BM x BN tile and each wave a (BM/2) x (BN/2) sub-tile made of 32 x 32
 // v_mfma_f32_32x32x2f32 blocks.  K advances in stages of 32 through a double
@@ -483,7 +487,7 @@ constexpr int kBKd = 32;
 // four stages (128 KB of LDS): 1.01x over three, 1.01x over five
 constexpr int kRingd = 4;
 
-__device__ __forceinline__ int swz_bf16(int r) { return ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1); }
+__device__ __forceinline__ int swz64(int r) { return ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1); }
 
 template <int N>
 __device__ __forceinline__ void wait_vm() {
@@ -498,19 +502,21 @@ __device__ __forceinline__ void wait_vm() {
 // every wave's LDS reads done, then all waves meet
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// 256 rows x 32 bf16 of one operand (16 DMA loads of 16 rows) into a stage.
-// (Dword loads, each writing 256 contiguous bytes, were 1.27x slower.)
-template <int NW>
-__device__ __forceinline__ void dma_tile(const unsigned short* __restrict__ P, int64_t ld, int r0,
-                                         int nrows, int k0, unsigned short* lds) {
+// ROWS tile rows of one operand, 64 bytes of k each (32 bf16 or 16 floats),
+// into a stage: ROWS / 16 DMA loads of 16 rows, spread over the NW waves.
+template <typename T, int ROWS, int NW>
+__device__ __forceinline__ void dma_tile(const T* __restrict__ P, int64_t ld, int r0, int nrows, int k0,
+                                         T* lds) {
+  constexpr int RowE = 64 / sizeof(T), ChE = 16 / sizeof(T);
+  static_assert((ROWS / 16) % NW == 0, "tile split");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < 16 / NW; ++i) {
+  for (int i = 0; i < ROWS / 16 / NW; ++i) {
     const int blk = i * NW + wave;
     const int r = blk * 16 + (lane >> 2);
-    const int c = (lane & 3) ^ swz_bf16(r);
+    const int c = (lane & 3) ^ swz64(r);
     const int gr = min(r0 + r, nrows - 1);
-    __builtin_amdgcn_global_load_lds(P + (int64_t)gr * ld + k0 + c * 8, lds + blk * 16 * kBKd, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(P + (int64_t)gr * ld + k0 + c * ChE, lds + blk * 16 * RowE, 16, 0, 0);
   }
 }
 
@@ -534,7 +540,7 @@ __global__ __launch_bounds__(64 * WVM * WVN, 1) void gemm_nt_bf16_dma_kernel(Pro
   const int wm = wave / WVN, wn = wave % WVN;
   const int lrow = lane & 31, hi = lane >> 5;
   // tile rows of a fragment are 32-aligned, so the slot swizzle depends on lrow only
-  const int sw = swz_bf16(lrow);
+  const int sw = swz64(lrow);
   const int off0 = lrow * kBKd + ((hi ^ sw) << 3), off1 = lrow * kBKd + (((2 + hi) ^ sw) << 3);
   floatx16 acc[FM][FN];
 #pragma unroll
@@ -546,8 +552,8 @@ __global__ __launch_bounds__(64 * WVM * WVN, 1) void gemm_nt_bf16_dma_kernel(Pro
 #pragma unroll
   for (int st = 0; st < NS - 1; ++st)
     if (st < nk) {
-      dma_tile<NW>(X, ldx, row0, rows, st * kBKd, sm + st * STAGE);
-      dma_tile<NW>(Y, ldy, col0, cols, st * kBKd, sm + st * STAGE + BM * kBKd);
+      dma_tile<unsigned short, BM, NW>(X, ldx, row0, rows, st * kBKd, sm + st * STAGE);
+      dma_tile<unsigned short, BN, NW>(Y, ldy, col0, cols, st * kBKd, sm + st * STAGE + BM * kBKd);
     }
   for (int kt = 0; kt < nk; ++kt) {
     if (kt + NS - 2 < nk)
@@ -558,8 +564,8 @@ __global__ __launch_bounds__(64 * WVM * WVN, 1) void gemm_nt_bf16_dma_kernel(Pro
     const int nx = kt + NS - 1;
     if (nx < nk) {
       unsigned short* dst = sm + (nx % NS) * STAGE;
-      dma_tile<NW>(X, ldx, row0, rows, nx * kBKd, dst);
-      dma_tile<NW>(Y, ldy, col0, cols, nx * kBKd, dst + BM * kBKd);
+      dma_tile<unsigned short, BM, NW>(X, ldx, row0, rows, nx * kBKd, dst);
+      dma_tile<unsigned short, BN, NW>(Y, ldy, col0, cols, nx * kBKd, dst + BM * kBKd);
     }
     const unsigned short* sx = sm + (kt % NS) * STAGE + wm * TM * kBKd;
     const unsigned short* sy = sm + (kt % NS) * STAGE + BM * kBKd + wn * TN * kBKd;
@@ -586,6 +592,94 @@ __global__ __launch_bounds__(64 * WVM * WVN, 1) void gemm_nt_bf16_dma_kernel(Pro
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = row0 + wm * TM + i * 32 + acc_row(r, lane);
+        if (row < rows && col < cols) p.C[(int64_t)row * p.ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+// FP32 sketch product on the same LDS ring: 128 x 128 tile, four waves of
+// 64 x 64 (2 x 2 v_mfma_f32_32x32x2f32), stages of 16 k (64-byte rows, the
+// same chunk swizzle), NS stages of 16 KB so that two workgroups share a CU.
+// A lane reads four consecutive k of its row (one 16-byte chunk) and feeds
+// them to four MFMAs; lanes 0-31 and 32-63 take chunks 2g and 2g + 1, a
+// permutation of the contraction index shared by both operands.  Used when
+// K is a multiple of 16 with 16-byte aligned rows.
+constexpr int kBKf = 16;
+// three stages (48 KB: three workgroups per CU): 0.824 of the FP32 MFMA peak
+// on the 20000 x 10000 sketch product, 0.820 with four, 0.807 with two, 0.748
+// for the register-staged kernel
+constexpr int kRingf = 3;
+
+template <int NS>
+__global__ __launch_bounds__(256, 2) void gemm_nt_f32_dma_kernel(Problem<float> p0, Problem<float> p1) {
+  constexpr int BM = 128, BN = 128, NW = 4, FM = 2, FN = 2;
+  constexpr int STAGE = (BM + BN) * kBKf;   // floats per stage (X tile, then Y tile)
+  constexpr int IPW = (BM + BN) / 16 / NW;  // DMA loads per wave per stage
+  __shared__ __attribute__((aligned(1024))) float sm[NS * STAGE];
+  int row0, col0;
+  Problem<float> p;
+  if (!pick<BM, BN>(p0, p1, p, row0, col0)) return;
+  const float* X = p.X;
+  const float* Y = p.Y;
+  const int64_t ldx = p.ldx, ldy = p.ldy;
+  const int rows = p.rows, cols = p.cols, nk = p.K / kBKf;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lrow = lane & 31, hi = lane >> 5;
+  const int sw = swz64(lrow);
+  const int off0 = lrow * kBKf + ((hi ^ sw) << 2), off1 = lrow * kBKf + (((2 + hi) ^ sw) << 2);
+  floatx16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+#pragma unroll
+  for (int st = 0; st < NS - 1; ++st)
+    if (st < nk) {
+      dma_tile<float, BM, NW>(X, ldx, row0, rows, st * kBKf, sm + st * STAGE);
+      dma_tile<float, BN, NW>(Y, ldy, col0, cols, st * kBKf, sm + st * STAGE + BM * kBKf);
+    }
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + NS - 2 < nk)
+      wait_vm<(NS - 2) * IPW>();
+    else
+      wait_vm<0>();
+    lds_barrier();
+    const int nx = kt + NS - 1;
+    if (nx < nk) {
+      float* dst = sm + (nx % NS) * STAGE;
+      dma_tile<float, BM, NW>(X, ldx, row0, rows, nx * kBKf, dst);
+      dma_tile<float, BN, NW>(Y, ldy, col0, cols, nx * kBKf, dst + BM * kBKf);
+    }
+    const float* sx = sm + (kt % NS) * STAGE + wm * (BM / 2) * kBKf;
+    const float* sy = sm + (kt % NS) * STAGE + BM * kBKf + wn * (BN / 2) * kBKf;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int off = g == 0 ? off0 : off1;
+      floatx4 a[FM], b[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const floatx4*>(sx + i * 32 * kBKf + off);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = *reinterpret_cast<const floatx4*>(sy + j * 32 * kBKf + off);
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][s4], b[j][s4], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = col0 + wn * (BN / 2) + j * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = row0 + wm * (BM / 2) + i * 32 + acc_row(r, lane);
         if (row < rows && col < cols) p.C[(int64_t)row * p.ldc + col] = acc[i][j][r];
       }
     }
@@ -732,6 +826,11 @@ dsanls_status launch_gemm_grouped(const GemmDesc& a_in, const GemmDesc& b_in, bo
     return fail(DSANLS_E_SHAPE, "gemm: dimension exceeds int32");
   if (p0.ntiles + p1.ntiles == 0) return DSANLS_OK;
   const int grid = grouped_grid(p0.ntiles, p1.ntiles);
+  if (vec && (p0.ntiles == 0 || p0.K % kBKf == 0) && (p1.ntiles == 0 || p1.K % kBKf == 0)) {
+    gemm_nt_f32_dma_kernel<kRingf><<<grid, 256, 0, s>>>(p0, p1);
+    DSANLS_LAUNCHED("gemm_nt_f32_dma_kernel");
+    return DSANLS_OK;
+  }
   if (vec)
     gemm_nt_grouped_kernel<128, 128, true><<<grid, 256, 0, s>>>(p0, p1);
   else

@@ -325,6 +325,39 @@ def test_sparse_subsample_fetch_indices(env):
     assert np.array_equal(prob.solver.fetch(0, (60,), "int32"), P.subsample_indices(17, 4, 1, 500, 60))
 
 
+@pytest.mark.parametrize("m,n,d", [(336, 208, 40), (1040, 784, 200)])
+def test_sketch_product_lds_ring_shapes(env, m, n, d):
+    # m and n multiples of 16 (the contraction lengths of A = M S and
+    # A' = M^T S'), so the FP32 sketch product runs on the LDS-ring kernel;
+    # row tiles and d are ragged.  Intermediates and one update per side
+    # against the oracle.
+    k = 8
+    M = synth.dense_uniform(m, n, 5, dtype=np.float64)
+    U0, V0 = synth.init_factors(m, n, k, 5, dtype=np.float64)
+    ocfg = _ocfg(k, d, d, O.SKETCH_GAUSSIAN, O.SOLVER_PROX_CD)
+    prob = Dense(env, M, U0, V0, ocfg)
+    M64 = M.astype(np.float32).astype(np.float64)
+    U, V = U0.astype(np.float32).astype(np.float64), V0.astype(np.float32).astype(np.float64)
+    for t in range(2):
+        prob.set(U, V)
+        prob.solver.update_U(t)
+        S = P.gaussian_sketch(ocfg.seed, t, 0, n, d)
+        A, _ = O.sketch_products(M64, V, S)
+        assert _rel(prob.solver.fetch(1, (m, d)), A) < 1e-5
+        Ug, _ = prob.get()
+        Uo = O.update_U(M64, U, V, t, ocfg)
+        assert _rel(Ug, Uo) < 1e-4
+        prob.set(Uo, V)
+        prob.solver.update_V(t)
+        Sp = P.gaussian_sketch(ocfg.seed, t, 1, m, d)
+        Ap, _ = O.sketch_products(M64.T, Uo, Sp)
+        assert _rel(prob.solver.fetch(1, (n, d)), Ap) < 1e-5
+        _, Vg = prob.get()
+        Vo = O.update_V(M64, Uo, V, t, ocfg)
+        assert _rel(Vg, Vo) < 1e-4
+        U, V = Uo, Vo
+
+
 @pytest.mark.parametrize("m,n,k,d", [(2000, 1200, 16, 256), (300, 180, 8, 40)])
 def test_bf16_sketch_form_per_update(env, m, n, k, d):
     # planted rank-k + 1% noise, Gaussian sketch: the BF16 form matches the
