@@ -171,7 +171,7 @@ def sparse_roofline(w, M, tm, launches, workload):
         flops = 2.0 * k * k * (m + n) / 2      # k^2 FMAs per row-sweep, mean over the two sides
         ach = flops / nnls_avg / 1e12
         peak = PEAK["fp32_valu_tflops"]
-        return {"kernel": "prox-CD sweep (prox_cd_kernel)", "bound": "alu", "achieved": ach, "peak": peak,
+        return {"kernel": "prox-CD sweep (prox_cd_lds_kernel)", "bound": "alu", "achieved": ach, "peak": peak,
                 "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic_bytes(workload), "flops_per_launch": flops,
                 "avg_launch_ms": nnls_avg * 1e3}
     # sampled-column gather: E = nnz d / lng sampled entries per side (their

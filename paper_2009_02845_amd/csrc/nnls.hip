@@ -97,6 +97,40 @@ __device__ __forceinline__ float dot_row(const float* __restrict__ g, const RowB
   return t0 + t1;
 }
 
+// The same dot product with the row in LDS (broadcast reads).  The row's
+// address goes through an opaque VGPR copy so that every read is that one
+// register plus an immediate offset (the compiler otherwise materialises
+// each address in an SGPR and moves it to a VGPR, two instructions a read).
+template <int KC, int W>
+__device__ __forceinline__ float dot_row_lds(const float* g, const RowBlocks<KC, W>& u) {
+  typedef __attribute__((address_space(3))) const float* lds_ptr;
+  uint32_t a = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_ptr)g));
+  asm volatile("" : "+v"(a));
+  const lds_ptr gl = reinterpret_cast<lds_ptr>(static_cast<uintptr_t>(a));
+  float t0 = 0.f, t1 = 0.f;
+  if constexpr (KC % 4 == 0) {
+    // rows start 16-byte aligned: four values per read
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(3))) const f4* lds_ptr4;
+    const lds_ptr4 g4 = reinterpret_cast<lds_ptr4>(gl);
+#pragma unroll
+    for (int l = 0; l < KC; l += 4) {
+      const f4 g = g4[l / 4];
+      t0 += g[0] * u.b[l / W][l % W];
+      t1 += g[1] * u.b[(l + 1) / W][(l + 1) % W];
+      t0 += g[2] * u.b[(l + 2) / W][(l + 2) % W];
+      t1 += g[3] * u.b[(l + 3) / W][(l + 3) % W];
+    }
+  } else {
+#pragma unroll
+    for (int l = 0; l < KC; l += 2) {
+      t0 += gl[l] * u.b[l / W][l % W];
+      if (l + 1 < KC) t1 += gl[l + 1] * u.b[(l + 1) / W][(l + 1) % W];
+    }
+  }
+  return t0 + t1;
+}
+
 // The 64 rows of a wave move between HBM and registers through an LDS panel
 // of SW columns (SW divides 64): row r of the panel starts at word r * STR,
 // STR odd, so the 64 lanes reading one column of their own rows hit 64
@@ -407,7 +441,7 @@ __device__ __forceinline__ void store_rows(float* __restrict__ panel, float* P, 
 // with u_l already updated for l < j, q = r + mu c one panel at a time,
 // clipped at ub (+inf without a bound).  Only lanes with act set change
 // their row.
-template <int KC, int W, int SW>
+template <int KC, int W, int SW, bool GLDS = false>
 __device__ __forceinline__ void sweep(QPanel<SW>& qp, const float* __restrict__ gp,
                                       const float* __restrict__ inv, const float* __restrict__ R,
                                       const float* __restrict__ C, int64_t row0, int nrows, int k,
@@ -433,7 +467,7 @@ __device__ __forceinline__ void sweep(QPanel<SW>& qp, const float* __restrict__ 
         for (int je = 0; je < jn; ++je) {
           const int j = jb * W + je;
           const float q = c_is_u ? qb[b * W + je] + mu * u.b[jb][je] : qb[b * W + je];
-          const float t = dot_row<KC, W>(gp + j * KC, u);
+          const float t = GLDS ? dot_row_lds<KC, W>(gp + j * KC, u) : dot_row<KC, W>(gp + j * KC, u);
           const float v = fminf(fmaxf((q - t) * inv[j], 0.f), ub);
           if (act) u.b[jb][je] = v;
         }
@@ -485,27 +519,37 @@ __device__ __forceinline__ float kkt(QPanel<SW>& qp, const float* __restrict__ g
 
 // Fixed number of sweeps (the paper's one, or s).  C (the proximal centre)
 // may alias U: the rows of C are read only before U is written, at the end.
-template <int KC, int W, int SW>
-__global__ __launch_bounds__(64) void prox_cd_kernel(const float* __restrict__ gp,
-                                                     const float* __restrict__ inv,
-                                                     const float* __restrict__ R, const float* C,
-                                                     float* U, int64_t rows, int k, float mu,
-                                                     int sweeps, float upper,
-                                                     int32_t* __restrict__ sweeps_used) {
-  // one LDS block, used in turn by the row panels (load, store) and by the
-  // streamed right-hand side: every phase waits for its own traffic
+// A workgroup of NWV waves (each with its own 64 rows, panels and
+// right-hand-side stream) copies the padded G into LDS once and reads its
+// rows with broadcast LDS loads; fetching every row through the scalar
+// cache instead, which the 100 x 100 Gram of the text workload overflows,
+// was 1.32x slower.
+template <int KC, int W, int SW, int NWV>
+__global__ __launch_bounds__(64 * NWV) void prox_cd_lds_kernel(const float* __restrict__ gp,
+                                                               const float* __restrict__ inv,
+                                                               const float* __restrict__ R, const float* C,
+                                                               float* U, int64_t rows, int k, float mu,
+                                                               int sweeps, float upper,
+                                                               int32_t* __restrict__ sweeps_used) {
   constexpr int kWords = Panel<SW>::WORDS > 2 * 64 * SW ? Panel<SW>::WORDS : 2 * 64 * SW;
-  __shared__ float lds[kWords];
-  float* panel = lds;
+  __shared__ __attribute__((aligned(16))) float sg[KC * KC];
+  __shared__ float lds[NWV][kWords];
+  for (int i = threadIdx.x * 4; i < KC * KC; i += 64 * NWV * 4)
+    *reinterpret_cast<float4*>(sg + i) = *reinterpret_cast<const float4*>(gp + i);
+  __syncthreads();
+  // wave-uniform (scalar) wave index: the row addressing lives in SGPRs
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int64_t row0 = (blockIdx.x * static_cast<int64_t>(NWV) + wave) * 64;
+  if (row0 >= rows) return;
+  float* panel = lds[wave];
   QPanel<SW>& qp = *reinterpret_cast<QPanel<SW>*>(panel);
-  const int64_t row0 = blockIdx.x * 64ll;
   const int nrows = static_cast<int>(rows - row0 < 64 ? rows - row0 : 64);
   const bool valid = lane_id() < nrows;
   const float ub = upper > 0.f ? upper : INFINITY;
   RowBlocks<KC, W> u;
   load_rows<KC, W, SW>(panel, U, row0, nrows, k, true, u);
   for (int s = 0; s < sweeps; ++s)
-    sweep<KC, W, SW>(qp, gp, inv, R, C, row0, nrows, k, mu, ub, true, s == 0 && C == U, u);
+    sweep<KC, W, SW, true>(qp, sg, inv, R, C, row0, nrows, k, mu, ub, true, s == 0 && C == U, u);
   store_rows<KC, W, SW>(panel, U, row0, nrows, k, u);
   if (valid && sweeps_used != nullptr) sweeps_used[row0 + lane_id()] = sweeps;
 }
@@ -727,8 +771,15 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
     return DSANLS_OK;
   }
   if (sweeps > 0) {
-    prox_cd_kernel<KC, W, SW><<<grid, 64, 0, s>>>(p.gp, p.inv, R, C, U, rows, k, mu, sweeps, upper, sweeps_used);
-    DSANLS_LAUNCHED("prox_cd_kernel");
+    // four waves per workgroup: two workgroups share a CU, so the two waves
+    // on a SIMD come from different workgroups and do not wait for the LDS
+    // in step (eight waves in one workgroup: 1.57x slower at k = 100; two
+    // waves, one wave per SIMD: 2.7x slower)
+    constexpr int NWV = 4;
+    const unsigned gl = static_cast<unsigned>(ceil_div(rows, 64 * NWV));
+    prox_cd_lds_kernel<KC, W, SW, NWV><<<gl, 64 * NWV, 0, s>>>(p.gp, p.inv, R, C, U, rows, k, mu, sweeps, upper,
+                                                               sweeps_used);
+    DSANLS_LAUNCHED("prox_cd_lds_kernel");
     return DSANLS_OK;
   }
   if (tw == nullptr) {
