@@ -479,7 +479,7 @@ __device__ __forceinline__ void sweep(QPanel<SW>& qp, const float* __restrict__ 
 // Relative projected-gradient norm of the row problem
 // min_{u >= 0} 1/2 u Q u^T - q u^T, Q = G + mu I: zero exactly at its
 // minimiser.
-template <int KC, int W, int SW>
+template <int KC, int W, int SW, bool GLDS = false>
 __device__ __forceinline__ float kkt(QPanel<SW>& qp, const float* __restrict__ gp,
                                      const float* __restrict__ den, const float* __restrict__ R,
                                      const float* __restrict__ C, int64_t row0, int nrows, int k,
@@ -504,7 +504,7 @@ __device__ __forceinline__ float kkt(QPanel<SW>& qp, const float* __restrict__ g
           const int l = lb * W + le;
           const float q = qb[b * W + le];
           const float ul = u.b[lb][le];
-          float g = dot_row<KC, W>(gp + l * KC, u) + den[l] * ul - q;
+          float g = (GLDS ? dot_row_lds<KC, W>(gp + l * KC, u) : dot_row<KC, W>(gp + l * KC, u)) + den[l] * ul - q;
           if (!(ul > 0.f)) g = fminf(g, 0.f);
           if (l < k) {
             pg2 += g * g;
@@ -577,19 +577,27 @@ struct TolPass {
   int32_t* wave_rows;        // per wave: those rows, 64 slots
 };
 
-template <int KC, int W, int SW>
-__global__ __launch_bounds__(64) void prox_cd_tol_kernel(const float* __restrict__ gp,
+template <int KC, int W, int SW, int NWV>
+__global__ __launch_bounds__(64 * NWV) void prox_cd_tol_kernel(const float* __restrict__ gp,
                                                          const float* __restrict__ den,
                                                          const float* __restrict__ inv,
                                                          const float* __restrict__ R, const float* C,
                                                          const float* start, float* U, int64_t rows,
                                                          int k, float mu, float tol, int max_sweeps,
                                                          float upper, TolPass pass) {
+  // the Gram in LDS, shared by the NWV waves of the workgroup (as in the
+  // fixed-sweep kernel); every wave is otherwise on its own
   constexpr int kWords = Panel<SW>::WORDS > 2 * 64 * SW ? Panel<SW>::WORDS : 2 * 64 * SW;
-  __shared__ float lds[kWords];
-  float* panel = lds;
+  __shared__ __attribute__((aligned(16))) float sg[KC * KC];
+  __shared__ float lds[NWV][kWords];
+  for (int i = threadIdx.x * 4; i < KC * KC; i += 64 * NWV * 4)
+    *reinterpret_cast<float4*>(sg + i) = *reinterpret_cast<const float4*>(gp + i);
+  __syncthreads();
+  const int wib = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int64_t wave = blockIdx.x * static_cast<int64_t>(NWV) + wib;
+  if (wave * 64 >= rows) return;   // past the last wave (its per-wave slots do not exist)
+  float* panel = lds[wib];
   QPanel<SW>& qp = *reinterpret_cast<QPanel<SW>*>(panel);
-  const int64_t wave = blockIdx.x;
   const int lane = lane_id();
   int64_t row0 = wave * 64;
   const int32_t* rmap = nullptr;
@@ -624,7 +632,7 @@ __global__ __launch_bounds__(64) void prox_cd_tol_kernel(const float* __restrict
 #pragma nounroll
     for (int c = 0; c < ncand; ++c) {
       if (c == 1) load_rows<KC, W, SW, true>(panel, C, row0, nrows, k, true, u);
-      const float r = kkt<KC, W, SW>(qp, gp, den, R, C, row0, nrows, k, mu, u);
+      const float r = kkt<KC, W, SW, true>(qp, sg, den, R, C, row0, nrows, k, mu, u);
       if (c == 0) res_w = r;
       else res_c = r;
     }
@@ -645,12 +653,12 @@ __global__ __launch_bounds__(64) void prox_cd_tol_kernel(const float* __restrict
     if (valid) pend = res > tol;
     const bool run = valid && pend && used < max_sweeps && here < pass.budget;
     if (!__any(run)) break;
-    sweep<KC, W, SW>(qp, gp, inv, R, C, row0, nrows, k, mu, ub, run, false, u, rmap);
+    sweep<KC, W, SW, true>(qp, sg, inv, R, C, row0, nrows, k, mu, ub, run, false, u, rmap);
     if (run) {
       ++used;
       ++here;
     }
-    res = kkt<KC, W, SW>(qp, gp, den, R, C, row0, nrows, k, mu, u, rmap);
+    res = kkt<KC, W, SW, true>(qp, sg, den, R, C, row0, nrows, k, mu, u, rmap);
   }
   store_rows<KC, W, SW>(panel, U, row0, nrows, k, u, rmap);
   const bool keep = valid && pend && used < max_sweeps && pass.wave_cnt != nullptr;
@@ -765,18 +773,19 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
   if (rows == 0) return DSANLS_OK;
   const int64_t nw = ceil_div(rows, 64);
   const unsigned grid = static_cast<unsigned>(nw);
+  // NNLS workgroups of four waves (64 rows each) sharing the Gram in LDS:
+  // two workgroups share a CU, so the two waves on a SIMD come from
+  // different workgroups and do not wait for the LDS in step (eight waves
+  // in one workgroup: 1.57x slower at k = 100; two waves, one wave per
+  // SIMD: 2.7x slower)
+  constexpr int NWV = 4;
+  const unsigned gl = static_cast<unsigned>(ceil_div(nw, NWV));
   if (pgd) {
     pgd_kernel<KC, W, SW><<<grid, 64, 0, s>>>(p.gp, p.gdiag, p.colsum, R, U, rows, k, mu, upper);
     DSANLS_LAUNCHED("pgd_kernel");
     return DSANLS_OK;
   }
   if (sweeps > 0) {
-    // four waves per workgroup: two workgroups share a CU, so the two waves
-    // on a SIMD come from different workgroups and do not wait for the LDS
-    // in step (eight waves in one workgroup: 1.57x slower at k = 100; two
-    // waves, one wave per SIMD: 2.7x slower)
-    constexpr int NWV = 4;
-    const unsigned gl = static_cast<unsigned>(ceil_div(rows, 64 * NWV));
     prox_cd_lds_kernel<KC, W, SW, NWV><<<gl, 64 * NWV, 0, s>>>(p.gp, p.inv, R, C, U, rows, k, mu, sweeps, upper,
                                                                sweeps_used);
     DSANLS_LAUNCHED("prox_cd_lds_kernel");
@@ -785,8 +794,8 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
   if (tw == nullptr) {
     // one pass to the end (no compaction workspace)
     const TolPass one{nullptr, nullptr, max_sweeps, sweeps_used, nullptr, nullptr, nullptr};
-    prox_cd_tol_kernel<KC, W, SW><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, start, U, rows, k, mu, tol,
-                                                      max_sweeps, upper, one);
+    prox_cd_tol_kernel<KC, W, SW, NWV><<<gl, 64 * NWV, 0, s>>>(p.gp, p.den, p.inv, R, C, start, U, rows, k,
+                                                               mu, tol, max_sweeps, upper, one);
     DSANLS_LAUNCHED("prox_cd_tol_kernel");
     return DSANLS_OK;
   }
@@ -802,8 +811,8 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
     const bool last = spent + budget >= max_sweeps;
     TolPass ps{pass_no == 0 ? nullptr : tw->list[pass_no & 1], pass_no == 0 ? nullptr : tw->wave_off + nw,
                last ? max_sweeps : budget, tw->used, tw->flags, last ? nullptr : tw->wave_cnt, tw->wave_rows};
-    prox_cd_tol_kernel<KC, W, SW><<<grid, 64, 0, s>>>(p.gp, p.den, p.inv, R, C, start, U, rows, k, mu, tol,
-                                                      max_sweeps, upper, ps);
+    prox_cd_tol_kernel<KC, W, SW, NWV><<<gl, 64 * NWV, 0, s>>>(p.gp, p.den, p.inv, R, C, start, U, rows, k,
+                                                               mu, tol, max_sweeps, upper, ps);
     DSANLS_LAUNCHED("prox_cd_tol_kernel");
     if (last) break;
     dsanls_status st = launch_exclusive_scan(tw->wave_cnt, tw->wave_off, nw, tw->scan_ws, s);
