@@ -429,31 +429,119 @@ __global__ __launch_bounds__(256) void gather_entries_kernel(const int64_t* __re
   }
 }
 
-// Listed rows (kShortRow < length <= kLongCap): one workgroup per row, a
-// bitonic sort of (slot, value) by slot in LDS; the workgroups walk the list.
+// Listed rows of kShortRow < length <= kMidRow entries (most of the listed
+// rows): one wave each, a bitonic sort of (slot, value) by slot in
+// registers, lane i holding entry i and its partner reached by a shuffle
+// (no barriers); the waves walk the list.  Slots within a row are distinct.
+constexpr int kMidRow = 64;
+__global__ __launch_bounds__(256) void row_sort_mid_kernel(const int32_t* __restrict__ a_rowptr,
+                                                           int32_t* __restrict__ a_cols,
+                                                           float* __restrict__ a_vals,
+                                                           const int32_t* __restrict__ long_rows,
+                                                           const int32_t* __restrict__ nlong) {
+  const int lane = threadIdx.x & 63;
+  const int n_long = *nlong;
+  const int64_t nw = gridDim.x * 4ll;
+  for (int64_t li = blockIdx.x * 4ll + (threadIdx.x >> 6); li < n_long; li += nw) {
+    const int32_t i = long_rows[li];
+    const int32_t b = a_rowptr[i], n = a_rowptr[i + 1] - b;
+    if (n > kMidRow) continue;
+    int32_t key = lane < n ? a_cols[b + lane] : 0x7fffffff;
+    float val = lane < n ? a_vals[b + lane] : 0.f;
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        const int32_t ok = __shfl_xor(key, stride, 64);
+        const float ov = __shfl_xor(val, stride, 64);
+        // the pair's lower lane keeps the smaller key in an ascending block
+        // (lane & size == 0) and the larger in a descending one
+        const bool up = (lane & size) == 0, lower = (lane & stride) == 0;
+        if (lower == up ? ok < key : ok > key) {
+          key = ok;
+          val = ov;
+        }
+      }
+    }
+    if (lane < n) {
+      a_cols[b + lane] = key;
+      a_vals[b + lane] = val;
+    }
+  }
+}
+
+// Listed rows of kMidRow < length <= kLongCap entries: one workgroup per
+// row (the workgroups walk the list).  The slots of a row are distinct
+// columns of the subsample, below d <= kLongCap, so the row is put in slot
+// order by counting: each entry marks its slot in an LDS map of d words,
+// then every thread takes a contiguous run of slots and writes the marked
+// ones at its exclusive prefix count (O(d + n) per row; the bitonic network
+// it replaces took 66 barrier-separated stages for a 2000-entry row).  A
+// row whose slots repeat (a CSR with duplicate entries, outside the
+// interface's contract) is sorted by a bitonic network instead, so no entry
+// is ever lost.
 __global__ __launch_bounds__(256) void row_sort_long_kernel(const int32_t* __restrict__ a_rowptr,
                                                             int32_t* __restrict__ a_cols,
                                                             float* __restrict__ a_vals,
                                                             const int32_t* __restrict__ long_rows,
-                                                            const int32_t* __restrict__ nlong) {
+                                                            const int32_t* __restrict__ nlong, int d) {
   __shared__ int32_t key[kLongCap];
   __shared__ float val[kLongCap];
+  __shared__ int32_t at[kLongCap];   // slot -> entry of the row, or -1
+  __shared__ int32_t wsum[4];
+  __shared__ int dup;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int run = (d + 255) / 256;   // slots per thread
   const int n_long = *nlong;
   for (int r = blockIdx.x; r < n_long; r += gridDim.x) {
     const int32_t i = long_rows[r];
     const int32_t b = a_rowptr[i], n = a_rowptr[i + 1] - b;
-    if (n > kLongCap) continue;   // only with duplicate entries in a CSR row
+    if (n <= kMidRow || n > kLongCap) continue;   // the wave sort's, or (duplicate CSR entries) too long
+    __syncthreads();
+    for (int c = tid; c < d; c += 256) at[c] = -1;
+    if (tid == 0) dup = 0;
+    __syncthreads();
+    for (int e = tid; e < n; e += 256) {
+      const int32_t c = a_cols[b + e];
+      val[e] = a_vals[b + e];
+      key[e] = c;
+      if (c < 0 || c >= d || atomicExch(&at[c], e) >= 0) dup = 1;
+    }
+    __syncthreads();
+    if (!dup) {
+      const int c0 = tid * run, c1 = c0 + run < d ? c0 + run : d;
+      int cnt = 0;
+      for (int c = c0; c < c1; ++c) cnt += at[c] >= 0;
+      int incl = cnt;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      if (lane == 63) wsum[w] = incl;
+      __syncthreads();
+      int pos = incl - cnt;
+      for (int q = 0; q < w; ++q) pos += wsum[q];
+      for (int c = c0; c < c1; ++c) {
+        const int32_t e = at[c];
+        if (e >= 0) {
+          a_cols[b + pos] = c;
+          a_vals[b + pos] = val[e];
+          ++pos;
+        }
+      }
+      continue;
+    }
     int P = 1;
     while (P < n) P <<= 1;
-    __syncthreads();
-    for (int t = threadIdx.x; t < P; t += 256) {
-      key[t] = t < n ? a_cols[b + t] : 0x7fffffff;
-      val[t] = t < n ? a_vals[b + t] : 0.f;
+    for (int t = n + tid; t < P; t += 256) {
+      key[t] = 0x7fffffff;
+      val[t] = 0.f;
     }
     for (int size = 2; size <= P; size <<= 1) {
       for (int stride = size >> 1; stride > 0; stride >>= 1) {
         __syncthreads();
-        for (int t = threadIdx.x; t < (P >> 1); t += 256) {
+        for (int t = tid; t < (P >> 1); t += 256) {
           const int lo = 2 * stride * (t / stride) + (t % stride), hi = lo + stride;
           const bool up = (lo & size) == 0;
           if ((key[lo] > key[hi]) == up) {
@@ -468,7 +556,7 @@ __global__ __launch_bounds__(256) void row_sort_long_kernel(const int32_t* __res
       }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < n; t += 256) {
+    for (int t = tid; t < n; t += 256) {
       a_cols[b + t] = key[t];
       a_vals[b + t] = val[t];
     }
@@ -596,20 +684,26 @@ __global__ __launch_bounds__(256) void a_rhs_kernel(const int32_t* __restrict__ 
   }
 }
 
-// R rows of the listed (long, sorted) rows of A: one workgroup per row, the
-// row's entries split into four consecutive quarters, one per wave; a wave
-// loads 64 entries at a time (slot, value, W row), then walks them with the
-// lanes over the columns of R, eight W rows in flight.  The four partial
-// sums are added in wave order, so the result depends only on the row.
-__global__ __launch_bounds__(256) void a_rhs_long_kernel(const int32_t* __restrict__ a_rowptr,
-                                                         const int32_t* __restrict__ a_cols,
-                                                         const float* __restrict__ a_vals,
-                                                         const int32_t* __restrict__ idx,
-                                                         const float* __restrict__ W, int k, float scale,
-                                                         const int32_t* __restrict__ long_rows,
-                                                         const int32_t* __restrict__ nlong,
-                                                         float* __restrict__ R) {
-  __shared__ float part[4][128];
+// R rows of the listed (long, sorted) rows of A with min_len <= length <=
+// max_len: one workgroup per row, the row's entries split into NWV
+// consecutive parts, one per wave (four waves up to kVeryLongRow entries,
+// sixteen beyond, so that a 2000-entry row is not one wave's 500-step
+// chain); a wave loads 64 entries at a time (slot, value, W row), then walks
+// them with the lanes over the columns of R, kLongBatch W rows in flight.
+// The partial sums are added in wave order, so the result depends only on
+// the row.
+constexpr int kLongBatch = 8;      // W rows in flight per wave (16: 1.2x slower)
+constexpr int kVeryLongRow = 512;  // longer rows get four times the waves
+template <int NWV>
+__global__ __launch_bounds__(64 * NWV) void a_rhs_long_kernel(const int32_t* __restrict__ a_rowptr,
+                                                              const int32_t* __restrict__ a_cols,
+                                                              const float* __restrict__ a_vals,
+                                                              const int32_t* __restrict__ idx,
+                                                              const float* __restrict__ W, int k, float scale,
+                                                              const int32_t* __restrict__ long_rows,
+                                                              const int32_t* __restrict__ nlong, int min_len,
+                                                              int max_len, float* __restrict__ R) {
+  __shared__ float part[NWV][128];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const bool in0 = lane < k, in1 = lane + 64 < k;
   const int col0 = in0 ? lane : k - 1, col1 = in1 ? lane + 64 : k - 1;
@@ -617,18 +711,19 @@ __global__ __launch_bounds__(256) void a_rhs_long_kernel(const int32_t* __restri
   for (int li = blockIdx.x; li < n_long; li += gridDim.x) {
     const int32_t row = long_rows[li];
     const int32_t rb = a_rowptr[row], n = a_rowptr[row + 1] - rb;
-    const int32_t q4 = (n + 3) / 4;
-    const int32_t beg = rb + (w * q4 < n ? w * q4 : n), end = rb + ((w + 1) * q4 < n ? (w + 1) * q4 : n);
+    if (n < min_len || n > max_len) continue;
+    const int32_t qn = (n + NWV - 1) / NWV;
+    const int32_t beg = rb + (w * qn < n ? w * qn : n), end = rb + ((w + 1) * qn < n ? (w + 1) * qn : n);
     float a0 = 0.f, a1 = 0.f;
     for (int32_t e0 = beg; e0 < end; e0 += 64) {
       const int cn = end - e0 < 64 ? end - e0 : 64;
       const int32_t e = e0 + (lane < cn ? lane : 0);
       const int32_t j = idx[a_cols[e]];
       const float v = a_vals[e];
-      for (int r0 = 0; r0 < cn; r0 += 8) {
-        float x0[8], x1[8], vv[8];
+      for (int r0 = 0; r0 < cn; r0 += kLongBatch) {
+        float x0[kLongBatch], x1[kLongBatch], vv[kLongBatch];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < kLongBatch; ++q) {
           const int r = r0 + q < cn ? r0 + q : r0;
           const float* wr = W + static_cast<int64_t>(__shfl(j, r, 64)) * k;
           const float y0 = wr[col0], y1 = wr[col1];
@@ -637,7 +732,7 @@ __global__ __launch_bounds__(256) void a_rhs_long_kernel(const int32_t* __restri
           vv[q] = r0 + q < cn ? __shfl(v, r, 64) : 0.f;
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < kLongBatch; ++q) {
           if (r0 + q < cn) {
             a0 += vv[q] * x0[q];
             a1 += vv[q] * x1[q];
@@ -650,8 +745,12 @@ __global__ __launch_bounds__(256) void a_rhs_long_kernel(const int32_t* __restri
     part[w][lane + 64] = a1;
     __syncthreads();
     if (w == 0) {
-      const float s0 = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-      const float s1 = ((part[0][lane + 64] + part[1][lane + 64]) + part[2][lane + 64]) + part[3][lane + 64];
+      float s0 = part[0][lane], s1 = part[0][lane + 64];
+#pragma unroll
+      for (int q = 1; q < NWV; ++q) {
+        s0 += part[q][lane];
+        s1 += part[q][lane + 64];
+      }
       if (in0) R[static_cast<int64_t>(row) * k + lane] = scale * s0;
       if (in1) R[static_cast<int64_t>(row) * k + lane + 64] = scale * s1;
     }
@@ -714,7 +813,9 @@ dsanls_status launch_sampled_rows(const int64_t* t_rowptr, const int32_t* t_coli
                                                   a_rowptr, a_cols, a_vals, scale, long_rows, nlong);
   DSANLS_LAUNCHED("gather_entries_kernel");
   if (rows > 0) {
-    row_sort_long_kernel<<<1024, 256, 0, s>>>(a_rowptr, a_cols, a_vals, long_rows, nlong);
+    row_sort_mid_kernel<<<1024, 256, 0, s>>>(a_rowptr, a_cols, a_vals, long_rows, nlong);
+    DSANLS_LAUNCHED("row_sort_mid_kernel");
+    row_sort_long_kernel<<<1024, 256, 0, s>>>(a_rowptr, a_cols, a_vals, long_rows, nlong, static_cast<int>(d));
     DSANLS_LAUNCHED("row_sort_long_kernel");
   }
   return DSANLS_OK;
@@ -728,8 +829,11 @@ dsanls_status launch_a_rhs(const int32_t* a_rowptr, int32_t* a_cols, float* a_va
   a_rhs_kernel<<<static_cast<unsigned>(ceil_div(rows, 256)), 256, 0, s>>>(a_rowptr, a_cols, a_vals, rows, idx, W,
                                                                          static_cast<int>(k), scale, R);
   DSANLS_LAUNCHED("a_rhs_kernel");
-  a_rhs_long_kernel<<<1024, 256, 0, s>>>(a_rowptr, a_cols, a_vals, idx, W, static_cast<int>(k), scale, long_rows,
-                                         nlong, R);
+  a_rhs_long_kernel<4><<<1024, 256, 0, s>>>(a_rowptr, a_cols, a_vals, idx, W, static_cast<int>(k), scale, long_rows,
+                                            nlong, kShortRow + 1, kVeryLongRow, R);
+  DSANLS_LAUNCHED("a_rhs_long_kernel");
+  a_rhs_long_kernel<16><<<256, 1024, 0, s>>>(a_rowptr, a_cols, a_vals, idx, W, static_cast<int>(k), scale,
+                                             long_rows, nlong, kVeryLongRow + 1, 0x7fffffff, R);
   DSANLS_LAUNCHED("a_rhs_long_kernel");
   return DSANLS_OK;
 }

@@ -270,10 +270,12 @@ def _skewed_sparse(m, n, k, seed):
     return Ms, U0, V0
 
 
-@pytest.mark.parametrize("m,n,d,dp", [(1500, 900, 200, 300), (400, 6000, 4500, 300)])
+@pytest.mark.parametrize("m,n,d,dp", [(1500, 900, 200, 300), (3000, 900, 700, 2000), (400, 6000, 4500, 300)])
 def test_sparse_subsample_skewed_parity(env, m, n, d, dp):
-    # d <= 4096: sampled rows gathered through CSR(X^T); d = 4500 on the U
-    # side: the CSR stream
+    # d <= 4096: sampled rows gathered through CSR(X^T), with sketched rows
+    # of every length class (up to 8 entries, up to 64, up to 512, beyond:
+    # the dense rows and columns give 700- and 2000-entry rows in the second
+    # case); d = 4500 on the U side: the CSR stream
     k = 12
     Ms, U0, V0 = _skewed_sparse(m, n, k, 8)
     ocfg = _ocfg(k, d, dp, O.SKETCH_SUBSAMPLE, O.SOLVER_PROX_CD, alpha=0.5, beta=0.5, seed=3)
