@@ -94,3 +94,32 @@ def test_dense_planted_full_size(env):
     sel = _sample(g, n, np.array([0, n - 1]), 400)
     Vg = V.cpu().numpy().astype(np.float64)
     assert _rel(Vg[sel], O.update_V(M64, Ug, V64, 0, ocfg, rows=sel, Mt=M64.T)) < 1e-4
+
+
+def test_dense_bf16_form_full_size(env):
+    # dense 50000 x 20000 planted rank 128 + 1% noise, Gaussian d = d' = 4096,
+    # BF16 sketch product (the LDS-ring kernel on zero-padded BF16 copies),
+    # prox-CD 1 sweep: sampled rows against the oracle of the same form
+    # (M and S rounded to bfloat16, products exact)
+    torch, B = env
+    m, n, k, d = 50000, 20000, 128, 4096
+    M = synth.planted_dense(m, n, k, 0, noise_sd=0.01, noise_relative=True)
+    U0, V0 = synth.init_factors(m, n, k, 0)
+    dev = torch.device("cuda", 0)
+    Md = torch.from_numpy(M).to(dev)
+    U, V = torch.from_numpy(U0).to(dev), torch.from_numpy(V0).to(dev)
+    cfg = B.make_config(m, n, k, d, d, sketch="gaussian", solver="prox_cd", precision="bf16", sweeps=1,
+                        alpha=1.0, beta=1.0, seed=0)
+    s = B.Solver(cfg, B.dense_matrix(Md), U, V, tensors=[Md])
+    ocfg = O.Config(k=k, d=d, d_prime=d, sketch=O.SKETCH_GAUSSIAN, solver=O.SOLVER_PROX_CD)
+    ocfg.precision = "bf16"
+    g = np.random.default_rng(3)
+    U64, V64 = U0.astype(np.float64), V0.astype(np.float64)
+    s.update_U(0)
+    sel = _sample(g, m, np.array([0, m - 1]), 200)
+    Ug = U.cpu().numpy().astype(np.float64)
+    assert _rel(Ug[sel], O.update_U(M, U64, V64, 0, ocfg, rows=sel)) < 1e-4
+    s.update_V(0)
+    sel = _sample(g, n, np.array([0, n - 1]), 200)
+    Vg = V.cpu().numpy().astype(np.float64)
+    assert _rel(Vg[sel], O.update_V(M, Ug, V64, 0, ocfg, rows=sel, Mt=M.T)) < 1e-4
