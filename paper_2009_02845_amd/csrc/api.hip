@@ -53,8 +53,9 @@ struct Layout {
   size_t gemm_ws_bytes = 0;
   void* nnls_ws = nullptr;
   size_t nnls_ws_bytes = 0;
-  int32_t* idx = nullptr;
-  int32_t* slot = nullptr;
+  int32_t* idx[2] = {nullptr, nullptr};    // per side: subsample indices (d) ...
+  int32_t* slot[2] = {nullptr, nullptr};   // ... and slot map (lng); one set per side so that the
+                                           // next side's selection can run ahead on the side stream
   // sketched rows of A (CSR input, subsampling): counts, offsets, entries
   int32_t* a_cnt = nullptr;         // per-row or per-segment counts
   int32_t* a_pos = nullptr;         // per-segment start positions / column offsets
@@ -71,7 +72,7 @@ struct Layout {
   float* seg_partials = nullptr;
   void* mlp_ws = nullptr;
   size_t mlp_ws_bytes = 0;
-  void* sub_ws = nullptr;
+  void* sub_ws[2] = {nullptr, nullptr};
   size_t sub_ws_bytes = 0;
   float* partials = nullptr;
   float* red = nullptr;             // 64 floats of small results
@@ -135,10 +136,12 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
   L.nnls_ws_bytes = align_up(nnls_ws_bytes(static_cast<int>(std::min<int64_t>(k, kMaxRank))), 256);
   L.nnls_ws = take(L.nnls_ws_bytes);
   if (sub) {
-    L.idx = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * dmax));
-    L.slot = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * lngmax));
     L.sub_ws_bytes = subsample_ws_bytes(lngmax);
-    L.sub_ws = take(L.sub_ws_bytes);
+    for (int sd = 0; sd < 2; ++sd) {
+      L.idx[sd] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * dmax));
+      L.slot[sd] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * lngmax));
+      L.sub_ws[sd] = take(L.sub_ws_bytes);
+    }
   }
   if (!is_dense) {
     const int64_t nnz = std::max<int64_t>(M.nnz, 0);
@@ -266,6 +269,17 @@ struct dsanls_ctx {
   // outer iteration whose V-side sketch product A' = M^T S'^t is already in
   // A[1] (computed together with the U side), or -1
   int64_t lookahead_t = -1;
+  // subsampling: the selection of the other side's next sketch (V side of
+  // the same t after a U update, U side of t + 1 after a V update) is
+  // launched on a side stream, where it overlaps this side's products and
+  // NNLS; sel_t[side] is the iteration it was drawn for (-1: none pending),
+  // ev_sel signals its end, ev_used the end of the last main-stream use of
+  // that side's index buffers
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_sel[2] = {nullptr, nullptr};
+  hipEvent_t ev_used[2] = {nullptr, nullptr};
+  bool used_recorded[2] = {false, false};
+  int64_t sel_t[2] = {-1, -1};
   // learned warm start (device parameters, caller-owned) and sketched rows
   const float* warm = nullptr;
   bool keep_rows = false;
@@ -273,6 +287,12 @@ struct dsanls_ctx {
   ~dsanls_ctx() {
     for (auto& v : ev)
       for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    if (side_stream != nullptr) (void)hipStreamSynchronize(side_stream);
+    for (int sd = 0; sd < 2; ++sd) {
+      if (ev_sel[sd] != nullptr) (void)hipEventDestroy(ev_sel[sd]);
+      if (ev_used[sd] != nullptr) (void)hipEventDestroy(ev_used[sd]);
+    }
+    if (side_stream != nullptr) (void)hipStreamDestroy(side_stream);
   }
 };
 
@@ -410,17 +430,22 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     CHECK(launch_gemm_nt(L.Wt, ldw, L.St[side], lds, L.B, ldb, k, d, lng, L.gemm_ws, L.gemm_ws_bytes, s));
   } else if (c.sketch == DSANLS_SKETCH_SUBSAMPLE) {
     CHECK(mark(ctx, kPhSketch));
-    CHECK(launch_subsample(c.seed, tt, side, lng, d, L.idx, is_dense ? nullptr : L.slot, L.sub_ws,
-                           L.sub_ws_bytes, L.err, s));
+    // a selection launched ahead on the side stream: used if it is for this
+    // t; otherwise waited for (it writes the same buffers) and redone here
+    if (ctx->sel_t[side] >= 0) DSANLS_HIP(hipStreamWaitEvent(s, ctx->ev_sel[side], 0));
+    if (ctx->sel_t[side] != t)
+      CHECK(launch_subsample(c.seed, tt, side, lng, d, L.idx[side], is_dense ? nullptr : L.slot[side],
+                             L.sub_ws[side], L.sub_ws_bytes, L.err, s));
+    ctx->sel_t[side] = -1;
     CHECK(mark(ctx, kPhSketch));
     const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
     if (is_dense) {
       CHECK(mark(ctx, kPhProduct));
-      CHECK(launch_gather_cols(X, ldx, L.idx, rows, d, scale, L.A[side], lda, s));
+      CHECK(launch_gather_cols(X, ldx, L.idx[side], rows, d, scale, L.A[side], lda, s));
       CHECK(mark(ctx, kPhProduct));
     }
     CHECK(mark(ctx, kPhSmall));
-    CHECK(launch_gather_rows_t(Wother, k, L.idx, d, scale, L.B, ldb, s));
+    CHECK(launch_gather_rows_t(Wother, k, L.idx[side], d, scale, L.B, ldb, s));
   } else {
     // identity: A = X, B = W^T
     CHECK(mark(ctx, kPhSmall));
@@ -448,16 +473,16 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
       const int32_t* xt_colidx = side == 0 ? ctx->mat.t_colidx : ctx->mat.colidx;
       const float* xt_vals = side == 0 ? ctx->mat.t_vals : ctx->mat.vals;
       const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
-      CHECK(launch_sampled_rows(xt_rowptr, xt_colidx, xt_vals, rows, L.idx, d, scale, L.a_cnt, L.a_pos,
+      CHECK(launch_sampled_rows(xt_rowptr, xt_colidx, xt_vals, rows, L.idx[side], d, scale, L.a_cnt, L.a_pos,
                                 L.scan_ws, L.a_rowptr, L.a_cols, L.a_vals, L.long_rows, L.nlong, s));
-      CHECK(launch_a_rhs(L.a_rowptr, L.a_cols, L.a_vals, rows, L.idx, Wother, k, scale, L.long_rows, L.nlong, L.R,
+      CHECK(launch_a_rhs(L.a_rowptr, L.a_cols, L.a_vals, rows, L.idx[side], Wother, k, scale, L.long_rows, L.nlong, L.R,
                          s));
       ctx->rows_kept = rows;
     } else {
       // the CSR stream: every nnz of X, the sampled ones (or all, identity)
       // folded into R
       const float scale = sub ? static_cast<float>(static_cast<double>(lng) / static_cast<double>(d)) : 1.0f;
-      CHECK(launch_csr_rhs_seg(rowptr, colidx, vals, L.seg[side], sub ? L.slot : nullptr, Wother, k, scale,
+      CHECK(launch_csr_rhs_seg(rowptr, colidx, vals, L.seg[side], sub ? L.slot[side] : nullptr, Wother, k, scale,
                                L.R, L.seg_partials, s));
     }
     CHECK(mark(ctx, kPhProduct));
@@ -470,7 +495,7 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     // sketched rows from the CSR stream (d too large for the gather)
     CHECK(mark(ctx, kPhProduct));
     const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
-    CHECK(launch_sketched_rows(rowptr, colidx, vals, rows, L.seg[side], L.slot, scale, L.a_cnt, L.a_pos,
+    CHECK(launch_sketched_rows(rowptr, colidx, vals, rows, L.seg[side], L.slot[side], scale, L.a_cnt, L.a_pos,
                                L.scan_ws, L.a_rowptr, L.a_cols, L.a_vals, s));
     CHECK(mark(ctx, kPhProduct));
     ctx->rows_kept = rows;
@@ -490,6 +515,23 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
   if (!pgd && c.sweeps > 0) ctx->stats.sweeps_total += rows * c.sweeps;
   CHECK(mark(ctx, kPhNnls));
   if (ctx->timing) ctx->timed_updates += 1;
+  if (ctx->side_stream != nullptr) {
+    // this side's index buffers are free once the main stream gets here
+    DSANLS_HIP(hipEventRecord(ctx->ev_used[side], s));
+    ctx->used_recorded[side] = true;
+    const int ns = 1 - side;
+    const int64_t nt = side == 0 ? t : t + 1;
+    if (nt <= UINT32_MAX) {
+      const int64_t nlng = ns == 0 ? c.n : c.m, nd = ns == 0 ? c.d : c.d_prime;
+      if (ctx->sel_t[ns] >= 0) DSANLS_HIP(hipStreamWaitEvent(ctx->side_stream, ctx->ev_sel[ns], 0));
+      if (ctx->used_recorded[ns]) DSANLS_HIP(hipStreamWaitEvent(ctx->side_stream, ctx->ev_used[ns], 0));
+      CHECK(launch_subsample(c.seed, static_cast<uint32_t>(nt), ns, nlng, nd, L.idx[ns],
+                             is_dense ? nullptr : L.slot[ns], L.sub_ws[ns], L.sub_ws_bytes, L.err,
+                             ctx->side_stream));
+      DSANLS_HIP(hipEventRecord(ctx->ev_sel[ns], ctx->side_stream));
+      ctx->sel_t[ns] = nt;
+    }
+  }
 #undef CHECK
   ctx->last_side = side;
   ctx->last_rows = rows;
@@ -560,6 +602,16 @@ dsanls_status dsanls_init(const dsanls_config* cfg, const dsanls_matrix* M, floa
     delete ctx;
     return e;
   };
+  if (c.sketch == DSANLS_SKETCH_SUBSAMPLE) {
+    // side stream (default priority) and events for the selection run-ahead
+    if (hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(DSANLS_E_HIP, "init: side stream creation failed"));
+    for (int sd = 0; sd < 2; ++sd)
+      if (hipEventCreateWithFlags(&ctx->ev_sel[sd], hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&ctx->ev_used[sd], hipEventDisableTiming) != hipSuccess)
+        return bail(fail(DSANLS_E_HIP, "init: event creation failed"));
+  }
+
   if (hipMemsetAsync(L.err, 0, sizeof(int) * 16, s) != hipSuccess ||
       hipMemsetAsync(L.counters, 0, sizeof(unsigned long long) * 8, s) != hipSuccess)
     return bail(fail(DSANLS_E_HIP, "init: memset failed"));
@@ -775,7 +827,7 @@ dsanls_status dsanls_debug_fetch(dsanls_ctx* ctx, int32_t which, void* dst, size
     case 0:
       if (c.sketch == DSANLS_SKETCH_GAUSSIAN)
         return copy2d(ctx->L.St[ctx->last_side], ctx->last_lds, d, lng, sizeof(float));
-      if (c.sketch == DSANLS_SKETCH_SUBSAMPLE) return copy2d(ctx->L.idx, d, 1, d, sizeof(int32_t));
+      if (c.sketch == DSANLS_SKETCH_SUBSAMPLE) return copy2d(ctx->L.idx[ctx->last_side], d, 1, d, sizeof(int32_t));
       return fail(DSANLS_E_UNSUPPORTED, "debug_fetch: identity sketch has no stored S");
     case 1:
       if (!ctx->last_A) return fail(DSANLS_E_UNSUPPORTED, "debug_fetch: A is not formed on the CSR path");
