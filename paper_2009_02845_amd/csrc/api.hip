@@ -57,14 +57,16 @@ struct Layout {
   int32_t* slot[2] = {nullptr, nullptr};   // ... and slot map (lng); one set per side so that the
                                            // next side's selection can run ahead on the side stream
   // sketched rows of A (CSR input, subsampling): counts, offsets, entries
-  int32_t* a_cnt = nullptr;         // per-row or per-segment counts
-  int32_t* a_pos = nullptr;         // per-segment start positions / column offsets
-  int32_t* long_rows = nullptr;     // rows of A longer than a lane sorts
-  int32_t* nlong = nullptr;
-  int32_t* a_rowptr = nullptr;
-  int32_t* a_cols = nullptr;
-  float* a_vals = nullptr;
-  int32_t* scan_ws = nullptr;
+  // sketched rows of A, one set per side (the next side's gather can run
+  // ahead on the side stream while this side's are still in use)
+  int32_t* a_cnt[2] = {nullptr, nullptr};      // per-row or per-segment counts
+  int32_t* a_pos[2] = {nullptr, nullptr};      // per-segment start positions / column offsets
+  int32_t* long_rows[2] = {nullptr, nullptr};  // rows of A longer than a lane sorts
+  int32_t* nlong[2] = {nullptr, nullptr};
+  int32_t* a_rowptr[2] = {nullptr, nullptr};
+  int32_t* a_cols[2] = {nullptr, nullptr};
+  float* a_vals[2] = {nullptr, nullptr};
+  int32_t* scan_ws[2] = {nullptr, nullptr};
   float* ustart = nullptr;          // warm start, rows x k
   // segment tables of CSR(M) (side 0) and CSR(M^T) (side 1), partial sums
   CsrSegments seg[2];
@@ -161,14 +163,16 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
   }
   if (!is_dense && sub) {
     const int64_t cnt_len = std::max({rowsmax + 1, L.seg_cap[0] + 1, L.seg_cap[1] + 1});
-    L.a_cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * cnt_len));
-    L.a_pos = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * cnt_len));
-    L.a_rowptr = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (rowsmax + 1)));
-    L.a_cols = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * std::max<int64_t>(M.nnz, 1)));
-    L.a_vals = reinterpret_cast<float*>(take(sizeof(float) * std::max<int64_t>(M.nnz, 1)));
-    L.scan_ws = reinterpret_cast<int32_t*>(take(scan_ws_bytes(cnt_len)));
-    L.long_rows = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * rowsmax));
-    L.nlong = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 4));
+    for (int sd = 0; sd < 2; ++sd) {
+      L.a_cnt[sd] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * cnt_len));
+      L.a_pos[sd] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * cnt_len));
+      L.a_rowptr[sd] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (rowsmax + 1)));
+      L.a_cols[sd] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * std::max<int64_t>(M.nnz, 1)));
+      L.a_vals[sd] = reinterpret_cast<float*>(take(sizeof(float) * std::max<int64_t>(M.nnz, 1)));
+      L.scan_ws[sd] = reinterpret_cast<int32_t*>(take(scan_ws_bytes(cnt_len)));
+      L.long_rows[sd] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * rowsmax));
+      L.nlong[sd] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 4));
+    }
     if (c.warm_hidden > 0) {
       L.ustart = reinterpret_cast<float*>(take(sizeof(float) * rowsmax * k));
       L.mlp_ws_bytes = mlp_ws_bytes(static_cast<int>(c.d), static_cast<int>(k), c.warm_hidden, rowsmax, true);
@@ -280,6 +284,7 @@ struct dsanls_ctx {
   hipEvent_t ev_used[2] = {nullptr, nullptr};
   bool used_recorded[2] = {false, false};
   int64_t sel_t[2] = {-1, -1};
+  bool gathered_ahead[2] = {false, false};   // the run-ahead also built the sketched rows
   // learned warm start (device parameters, caller-owned) and sketched rows
   const float* warm = nullptr;
   bool keep_rows = false;
@@ -389,6 +394,7 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     if ((st = (x)) != DSANLS_OK) return st; \
   } while (0)
 
+  bool gathered = false;   // sketched rows of this side already built on the side stream
   const float* Bp = L.B;
   int64_t Bld = ldb, Bk = d;   // B is k x Bk with leading dimension Bld
   const float* Ap = L.A[side];
@@ -436,6 +442,8 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     if (ctx->sel_t[side] != t)
       CHECK(launch_subsample(c.seed, tt, side, lng, d, L.idx[side], is_dense ? nullptr : L.slot[side],
                              L.sub_ws[side], L.sub_ws_bytes, L.err, s));
+    else
+      gathered = ctx->gathered_ahead[side];
     ctx->sel_t[side] = -1;
     CHECK(mark(ctx, kPhSketch));
     const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
@@ -473,9 +481,12 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
       const int32_t* xt_colidx = side == 0 ? ctx->mat.t_colidx : ctx->mat.colidx;
       const float* xt_vals = side == 0 ? ctx->mat.t_vals : ctx->mat.vals;
       const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
-      CHECK(launch_sampled_rows(xt_rowptr, xt_colidx, xt_vals, rows, L.idx[side], d, scale, L.a_cnt, L.a_pos,
-                                L.scan_ws, L.a_rowptr, L.a_cols, L.a_vals, L.long_rows, L.nlong, s));
-      CHECK(launch_a_rhs(L.a_rowptr, L.a_cols, L.a_vals, rows, L.idx[side], Wother, k, scale, L.long_rows, L.nlong, L.R,
+      if (!gathered)
+        CHECK(launch_sampled_rows(xt_rowptr, xt_colidx, xt_vals, rows, L.idx[side], d, scale, L.a_cnt[side],
+                                  L.a_pos[side], L.scan_ws[side], L.a_rowptr[side], L.a_cols[side],
+                                  L.a_vals[side], L.long_rows[side], L.nlong[side], s));
+      CHECK(launch_a_rhs(L.a_rowptr[side], L.a_cols[side], L.a_vals[side], rows, L.idx[side], Wother, k, scale,
+                         L.long_rows[side], L.nlong[side], L.R,
                          s));
       ctx->rows_kept = rows;
     } else {
@@ -495,16 +506,17 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     // sketched rows from the CSR stream (d too large for the gather)
     CHECK(mark(ctx, kPhProduct));
     const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
-    CHECK(launch_sketched_rows(rowptr, colidx, vals, rows, L.seg[side], L.slot[side], scale, L.a_cnt, L.a_pos,
-                               L.scan_ws, L.a_rowptr, L.a_cols, L.a_vals, s));
+    CHECK(launch_sketched_rows(rowptr, colidx, vals, rows, L.seg[side], L.slot[side], scale, L.a_cnt[side],
+                               L.a_pos[side], L.scan_ws[side], L.a_rowptr[side], L.a_cols[side], L.a_vals[side],
+                               s));
     CHECK(mark(ctx, kPhProduct));
     ctx->rows_kept = rows;
   }
   const float* start = nullptr;
   if (warm) {
     CHECK(mark(ctx, kPhSmall));
-    CHECK(mlp_forward(static_cast<int>(d), static_cast<int>(k), c.warm_hidden, ctx->warm, rows, L.a_rowptr,
-                      L.a_cols, L.a_vals, Wself, L.ustart, L.mlp_ws, L.mlp_ws_bytes, s));
+    CHECK(mlp_forward(static_cast<int>(d), static_cast<int>(k), c.warm_hidden, ctx->warm, rows, L.a_rowptr[side],
+                      L.a_cols[side], L.a_vals[side], Wself, L.ustart, L.mlp_ws, L.mlp_ws_bytes, s));
     CHECK(mark(ctx, kPhSmall));
     start = L.ustart;
   }
@@ -528,6 +540,17 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
       CHECK(launch_subsample(c.seed, static_cast<uint32_t>(nt), ns, nlng, nd, L.idx[ns],
                              is_dense ? nullptr : L.slot[ns], L.sub_ws[ns], L.sub_ws_bytes, L.err,
                              ctx->side_stream));
+      // the sketched rows of that side need only M and the indices
+      ctx->gathered_ahead[ns] = !is_dense && nd <= kGatherMaxD && ctx->mat.nnz < (int64_t{1} << 31);
+      if (ctx->gathered_ahead[ns]) {
+        const int64_t nrows = ns == 0 ? c.m : c.n;
+        const float nscale = static_cast<float>(std::sqrt(static_cast<double>(nlng) / static_cast<double>(nd)));
+        CHECK(launch_sampled_rows(ns == 0 ? ctx->mat.t_rowptr : ctx->mat.rowptr,
+                                  ns == 0 ? ctx->mat.t_colidx : ctx->mat.colidx,
+                                  ns == 0 ? ctx->mat.t_vals : ctx->mat.vals, nrows, L.idx[ns], nd, nscale,
+                                  L.a_cnt[ns], L.a_pos[ns], L.scan_ws[ns], L.a_rowptr[ns], L.a_cols[ns],
+                                  L.a_vals[ns], L.long_rows[ns], L.nlong[ns], ctx->side_stream));
+      }
       DSANLS_HIP(hipEventRecord(ctx->ev_sel[ns], ctx->side_stream));
       ctx->sel_t[ns] = nt;
     }
@@ -753,7 +776,7 @@ dsanls_status dsanls_set_warm_start(dsanls_ctx* ctx, const float* params, int32_
 
 dsanls_status dsanls_set_keep_sketched_rows(dsanls_ctx* ctx, int32_t enable) {
   if (!ctx) return fail(DSANLS_E_STATE, "set_keep_sketched_rows: context is NULL");
-  if (enable && ctx->L.a_rowptr == nullptr)
+  if (enable && ctx->L.a_rowptr[0] == nullptr)
     return fail(DSANLS_E_STATE, "set_keep_sketched_rows: needs CSR input and a subsampling sketch");
   ctx->keep_rows = enable != 0;
   return DSANLS_OK;
@@ -769,17 +792,22 @@ dsanls_status dsanls_gather_sketched_rows(dsanls_ctx* ctx, const int32_t* sel, i
   if (nsel > std::max(ctx->cfg.m, ctx->cfg.n)) return fail(DSANLS_E_SHAPE, "gather_sketched_rows: nsel > max(m, n)");
   const Layout& L = ctx->L;
   hipStream_t s = ctx->stream;
+  const int sd = ctx->last_side;
   dsanls_status st;
   // lengths into out_rowptr, scanned in place through the count buffer
-  if ((st = launch_csr_select_len(L.a_rowptr, ctx->rows_kept, sel, nsel, L.a_cnt, s)) != DSANLS_OK) return st;
-  if ((st = launch_exclusive_scan(L.a_cnt, out_rowptr, nsel, L.scan_ws, s)) != DSANLS_OK) return st;
+  if ((st = launch_csr_select_len(L.a_rowptr[sd], ctx->rows_kept, sel, nsel, L.a_cnt[sd], s)) != DSANLS_OK)
+    return st;
+  if ((st = launch_exclusive_scan(L.a_cnt[sd], out_rowptr, nsel, L.scan_ws[sd], s)) != DSANLS_OK) return st;
   int32_t total = 0;
   DSANLS_HIP(hipMemcpyAsync(&total, out_rowptr + nsel, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   DSANLS_HIP(hipStreamSynchronize(s));
   *nnz = total;
   if (total > capacity) return fail(DSANLS_E_WORKSPACE, "gather_sketched_rows: capacity too small");
-  return launch_csr_select_copy(L.a_rowptr, ctx->rows_kept, L.a_cols, L.a_vals, sel, nsel, out_rowptr, out_cols,
-                                out_vals, s);
+  st = launch_csr_select_copy(L.a_rowptr[sd], ctx->rows_kept, L.a_cols[sd], L.a_vals[sd], sel, nsel, out_rowptr,
+                              out_cols, out_vals, s);
+  // this side's rows are in use until here: a run-ahead gather into them waits
+  if (st == DSANLS_OK && ctx->side_stream != nullptr) DSANLS_HIP(hipEventRecord(ctx->ev_used[sd], s));
+  return st;
 }
 
 dsanls_status dsanls_set_timing(dsanls_ctx* ctx, int32_t enable) {
