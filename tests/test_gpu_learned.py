@@ -164,3 +164,24 @@ def test_cold_to_tolerance_update_matches_oracle(env):
     s.update_U(0)
     Uo = O.update_U(M64, U0.astype(np.float64), V0.astype(np.float64), 0, ocfg)
     assert _rel(U.cpu().numpy(), Uo) < 1e-3
+
+
+@pytest.mark.parametrize("k", [10, 33, 100])
+def test_to_tolerance_passes_match_oracle(env, k):
+    # to tolerance through all the passes (budgets 16, 16, 32, 64, then to
+    # the cap, pending rows compacted between passes); k = 100 > d keeps G
+    # singular (mu = 1 + t makes Q definite), so many rows need far more
+    # than 32 sweeps.  Against the oracle with the same tolerance and sweep
+    # cap (rows stop on the same test up to rounding), and against the exact
+    # minimiser
+    m, n, d = 700, 500, 80
+    s, M64, U, V, U0, V0 = _sparse_ctx(env, m, n, k, d, 11, tol=1e-5)
+    s.update_U(0)
+    Ug = U.cpu().numpy().astype(np.float64)
+    same = O.Config(k=k, d=d, d_prime=d, sketch=O.SKETCH_SUBSAMPLE, solver=O.SOLVER_PROX_CD, sweeps=0,
+                    tol=1e-5, max_sweeps=400, seed=7)
+    assert _rel(Ug, O.update_U(M64, U0.astype(np.float64), V0.astype(np.float64), 0, same)) < 1e-4
+    exact = O.Config(k=k, d=d, d_prime=d, sketch=O.SKETCH_SUBSAMPLE, solver=O.SOLVER_PROX_CD, sweeps=0,
+                     tol=1e-12, max_sweeps=20000, seed=7)
+    assert _rel(Ug, O.update_U(M64, U0.astype(np.float64), V0.astype(np.float64), 0, exact)) < 1e-3
+    assert np.isfinite(Ug).all() and Ug.min() >= 0
