@@ -491,8 +491,10 @@ __device__ __forceinline__ int swz64(int r) { return ((r >> 2) & 1) | ((((r >> 1
 
 template <int N>
 __device__ __forceinline__ void wait_vm() {
-  static_assert(N == 0 || N == 4 || N == 8 || N == 16 || N == 32, "vmcnt immediate");
+  static_assert(N == 0 || N == 3 || N == 4 || N == 6 || N == 8 || N == 16 || N == 32, "vmcnt immediate");
   if constexpr (N == 0) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  else if constexpr (N == 3) asm volatile("s_waitcnt vmcnt(3)" ::: "memory");
+  else if constexpr (N == 6) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
   else if constexpr (N == 4) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
   else if constexpr (N == 8) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
   else if constexpr (N == 16) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
@@ -597,22 +599,25 @@ __global__ __launch_bounds__(64 * WVM * WVN, 1) void gemm_nt_bf16_dma_kernel(Pro
     }
 }
 
-// FP32 sketch product on the same LDS ring: 128 x 128 tile, four waves of
-// 64 x 64 (2 x 2 v_mfma_f32_32x32x2f32), stages of 16 k (64-byte rows, the
-// same chunk swizzle), NS stages of 16 KB so that two workgroups share a CU.
+// FP32 sketch product on the same LDS ring: 128 x 64 WVN tile, 2 WVN waves
+// of 64 x 64 (2 x 2 v_mfma_f32_32x32x2f32), stages of 16 k (64-byte rows,
+// the same chunk swizzle).
 // A lane reads four consecutive k of its row (one 16-byte chunk) and feeds
 // them to four MFMAs; lanes 0-31 and 32-63 take chunks 2g and 2g + 1, a
 // permutation of the contraction index shared by both operands.  Used when
 // K is a multiple of 16 with 16-byte aligned rows.
 constexpr int kBKf = 16;
-// three stages (48 KB: three workgroups per CU): 0.824 of the FP32 MFMA peak
-// on the 20000 x 10000 sketch product, 0.820 with four, 0.807 with two, 0.748
-// for the register-staged kernel
+// 128 x 256 tiles in eight waves of 64 x 64 (kWvNf = 4 along N) and three
+// stages of 24 KB (two workgroups, sixteen waves per CU): 0.862 of the FP32
+// MFMA peak on the 20000 x 10000 sketch product (two stages: 0.869, four:
+// 0.837); 128 x 128 tiles in four waves reached 0.821, the register-staged
+// kernel 0.748
 constexpr int kRingf = 3;
+constexpr int kWvNf = 4;   // waves along N (tile 128 x 64 kWvNf)
 
-template <int NS>
-__global__ __launch_bounds__(256, 2) void gemm_nt_f32_dma_kernel(Problem<float> p0, Problem<float> p1) {
-  constexpr int BM = 128, BN = 128, NW = 4, FM = 2, FN = 2;
+template <int NS, int WVN>
+__global__ __launch_bounds__(128 * WVN, WVN <= 4 ? 2 : 1) void gemm_nt_f32_dma_kernel(Problem<float> p0, Problem<float> p1) {
+  constexpr int BM = 128, BN = 64 * WVN, NW = 2 * WVN, FM = 2, FN = 2;
   constexpr int STAGE = (BM + BN) * kBKf;   // floats per stage (X tile, then Y tile)
   constexpr int IPW = (BM + BN) / 16 / NW;  // DMA loads per wave per stage
   __shared__ __attribute__((aligned(1024))) float sm[NS * STAGE];
@@ -624,7 +629,7 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f32_dma_kernel(Problem<float> 
   const int64_t ldx = p.ldx, ldy = p.ldy;
   const int rows = p.rows, cols = p.cols, nk = p.K / kBKf;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WVN, wn = wave % WVN;
   const int lrow = lane & 31, hi = lane >> 5;
   const int sw = swz64(lrow);
   const int off0 = lrow * kBKf + ((hi ^ sw) << 2), off1 = lrow * kBKf + (((2 + hi) ^ sw) << 2);
@@ -654,7 +659,7 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f32_dma_kernel(Problem<float> 
       dma_tile<float, BN, NW>(Y, ldy, col0, cols, nx * kBKf, dst + BM * kBKf);
     }
     const float* sx = sm + (kt % NS) * STAGE + wm * (BM / 2) * kBKf;
-    const float* sy = sm + (kt % NS) * STAGE + BM * kBKf + wn * (BN / 2) * kBKf;
+    const float* sy = sm + (kt % NS) * STAGE + BM * kBKf + wn * 64 * kBKf;
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
       const int off = g == 0 ? off0 : off1;
@@ -676,7 +681,7 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f32_dma_kernel(Problem<float> 
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      const int col = col0 + wn * (BN / 2) + j * 32 + (lane & 31);
+      const int col = col0 + wn * 64 + j * 32 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = row0 + wm * (BM / 2) + i * 32 + acc_row(r, lane);
@@ -822,15 +827,21 @@ dsanls_status launch_gemm_grouped(const GemmDesc& a_in, const GemmDesc& b_in, bo
     return DSANLS_OK;
   }
   Problem<float> p0, p1;
+  {
+    Problem<float> q0, q1;
+    if (!make_problem(a, 4, q0, vec, 128, 64 * kWvNf) || !make_problem(b, 4, q1, vec, 128, 64 * kWvNf))
+      return fail(DSANLS_E_SHAPE, "gemm: dimension exceeds int32");
+    if (q0.ntiles + q1.ntiles == 0) return DSANLS_OK;
+    if (vec && (q0.ntiles == 0 || q0.K % kBKf == 0) && (q1.ntiles == 0 || q1.K % kBKf == 0)) {
+      gemm_nt_f32_dma_kernel<kRingf, kWvNf><<<grouped_grid(q0.ntiles, q1.ntiles), 128 * kWvNf, 0, s>>>(q0, q1);
+      DSANLS_LAUNCHED("gemm_nt_f32_dma_kernel");
+      return DSANLS_OK;
+    }
+  }
+  vec = true;
   if (!make_problem(a, 4, p0, vec) || !make_problem(b, 4, p1, vec))
     return fail(DSANLS_E_SHAPE, "gemm: dimension exceeds int32");
-  if (p0.ntiles + p1.ntiles == 0) return DSANLS_OK;
   const int grid = grouped_grid(p0.ntiles, p1.ntiles);
-  if (vec && (p0.ntiles == 0 || p0.K % kBKf == 0) && (p1.ntiles == 0 || p1.K % kBKf == 0)) {
-    gemm_nt_f32_dma_kernel<kRingf><<<grid, 256, 0, s>>>(p0, p1);
-    DSANLS_LAUNCHED("gemm_nt_f32_dma_kernel");
-    return DSANLS_OK;
-  }
   if (vec)
     gemm_nt_grouped_kernel<128, 128, true><<<grid, 256, 0, s>>>(p0, p1);
   else

@@ -327,7 +327,7 @@ def test_sparse_subsample_fetch_indices(env):
     assert np.array_equal(prob.solver.fetch(0, (60,), "int32"), P.subsample_indices(17, 4, 1, 500, 60))
 
 
-@pytest.mark.parametrize("m,n,d", [(336, 208, 40), (1040, 784, 200)])
+@pytest.mark.parametrize("m,n,d", [(336, 208, 40), (1040, 784, 200), (528, 400, 300)])
 def test_sketch_product_lds_ring_shapes(env, m, n, d):
     # m and n multiples of 16 (the contraction lengths of A = M S and
     # A' = M^T S'), so the FP32 sketch product runs on the LDS-ring kernel;
