@@ -132,14 +132,14 @@ def cpu_baseline(w, M, U0, V0, budget_s=12.0, max_iters=5, Mt=None):
 CAL_FETCH, CAL_WRITE = 2.0, 1.0
 TRAFFIC = {
     "dense-20000x10000": {"files": ["gemm.hip", "common.hpp"],
-                          "sha256": "67347e58f73e9f928ac453e96432cdcfdf97881a0f636594f724ded3e5406164",
-                          "fetch_kib": 5353984.06, "write_kib": 120000.0},
+                          "sha256": "477d98a43fd4e6bed56ce09f6405edee400d8b73fe09c36268615e925d203e15",
+                          "fetch_kib": 2419643.13, "write_kib": 120000.0},
     "sparse-500000x200000": {"files": ["nnls.hip", "common.hpp"],
                              "sha256": "b02463a883b83c26e40722a08c29adfb836a64b8b7038265c06f7146f97b17e1",
-                             "fetch_kib": 188361.06, "write_kib": 155034.94},
+                             "fetch_kib": 188534.5, "write_kib": 154932.7},
     "dense-50000x20000-bf16": {"files": ["gemm.hip", "common.hpp"],
-                               "sha256": "67347e58f73e9f928ac453e96432cdcfdf97881a0f636594f724ded3e5406164",
-                               "fetch_kib": 20495732.13, "write_kib": 1120000.0},
+                               "sha256": "477d98a43fd4e6bed56ce09f6405edee400d8b73fe09c36268615e925d203e15",
+                               "fetch_kib": 20248669.94, "write_kib": 1120000.0},
 }
 
 

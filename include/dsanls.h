@@ -18,6 +18,11 @@
  *     scratch space lives in the caller's workspace.
  *   - Work is enqueued on the caller's HIP stream (hip_stream may be NULL
  *     for the null stream) and is asynchronous unless stated otherwise.
+ *     With a subsampling sketch a context also owns one stream of its own
+ *     (default priority), on which the other side's next subsample and its
+ *     sketched rows are prepared ahead (they need only M, the seed and t);
+ *     events order that work against the caller's stream, so results are
+ *     as if everything ran on the caller's stream in call order.
  *   - Every call returns a dsanls_status; nothing is thrown across the ABI.
  *     dsanls_last_error() returns a message for the calling thread's last
  *     failure.  A context is not thread-safe; separate contexts on separate
@@ -216,7 +221,9 @@ dsanls_status dsanls_get_timing(dsanls_ctx* ctx, dsanls_timing* out);
  *        4 = R (rows x k).  bytes must equal the object's size. */
 dsanls_status dsanls_debug_fetch(dsanls_ctx* ctx, int32_t which, void* dst, size_t bytes);
 
-/* Release the context (host memory only; caller buffers untouched). */
+/* Release the context (host memory, and its own stream after that stream's
+ * pending work has finished; caller buffers untouched).  The workspace may
+ * be reused or freed once this returns. */
 dsanls_status dsanls_destroy(dsanls_ctx* ctx);
 
 const char* dsanls_status_string(dsanls_status s);
