@@ -276,7 +276,7 @@ struct dsanls_ctx {
   // subsampling: the selection of the other side's next sketch (V side of
   // the same t after a U update, U side of t + 1 after a V update) is
   // launched on a side stream, where it overlaps this side's products and
-  // NNLS; sel_t[side] is the iteration it was drawn for (-1: none pending),
+  // NNLS; sel_t[side] is the iteration it was drawn for (-1: none usable),
   // ev_sel signals its end, ev_used the end of the last main-stream use of
   // that side's index buffers
   hipStream_t side_stream = nullptr;
@@ -285,6 +285,7 @@ struct dsanls_ctx {
   bool used_recorded[2] = {false, false};
   int64_t sel_t[2] = {-1, -1};
   bool gathered_ahead[2] = {false, false};   // the run-ahead also built the sketched rows
+  bool ahead_pending[2] = {false, false};    // side-stream work on that side's buffers may be in flight
   // learned warm start (device parameters, caller-owned) and sketched rows
   const float* warm = nullptr;
   bool keep_rows = false;
@@ -438,7 +439,8 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     CHECK(mark(ctx, kPhSketch));
     // a selection launched ahead on the side stream: used if it is for this
     // t; otherwise waited for (it writes the same buffers) and redone here
-    if (ctx->sel_t[side] >= 0) DSANLS_HIP(hipStreamWaitEvent(s, ctx->ev_sel[side], 0));
+    if (ctx->ahead_pending[side]) DSANLS_HIP(hipStreamWaitEvent(s, ctx->ev_sel[side], 0));
+    ctx->ahead_pending[side] = false;
     if (ctx->sel_t[side] != t)
       CHECK(launch_subsample(c.seed, tt, side, lng, d, L.idx[side], is_dense ? nullptr : L.slot[side],
                              L.sub_ws[side], L.sub_ws_bytes, L.err, s));
@@ -535,24 +537,30 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     const int64_t nt = side == 0 ? t : t + 1;
     if (nt <= UINT32_MAX) {
       const int64_t nlng = ns == 0 ? c.n : c.m, nd = ns == 0 ? c.d : c.d_prime;
-      if (ctx->sel_t[ns] >= 0) DSANLS_HIP(hipStreamWaitEvent(ctx->side_stream, ctx->ev_sel[ns], 0));
+      if (ctx->ahead_pending[ns]) DSANLS_HIP(hipStreamWaitEvent(ctx->side_stream, ctx->ev_sel[ns], 0));
       if (ctx->used_recorded[ns]) DSANLS_HIP(hipStreamWaitEvent(ctx->side_stream, ctx->ev_used[ns], 0));
-      CHECK(launch_subsample(c.seed, static_cast<uint32_t>(nt), ns, nlng, nd, L.idx[ns],
-                             is_dense ? nullptr : L.slot[ns], L.sub_ws[ns], L.sub_ws_bytes, L.err,
-                             ctx->side_stream));
+      dsanls_status ast = launch_subsample(c.seed, static_cast<uint32_t>(nt), ns, nlng, nd, L.idx[ns],
+                                           is_dense ? nullptr : L.slot[ns], L.sub_ws[ns], L.sub_ws_bytes,
+                                           L.err, ctx->side_stream);
       // the sketched rows of that side need only M and the indices
-      ctx->gathered_ahead[ns] = !is_dense && nd <= kGatherMaxD && ctx->mat.nnz < (int64_t{1} << 31);
-      if (ctx->gathered_ahead[ns]) {
+      const bool gather = !is_dense && nd <= kGatherMaxD && ctx->mat.nnz < (int64_t{1} << 31);
+      if (ast == DSANLS_OK && gather) {
         const int64_t nrows = ns == 0 ? c.m : c.n;
         const float nscale = static_cast<float>(std::sqrt(static_cast<double>(nlng) / static_cast<double>(nd)));
-        CHECK(launch_sampled_rows(ns == 0 ? ctx->mat.t_rowptr : ctx->mat.rowptr,
+        ast = launch_sampled_rows(ns == 0 ? ctx->mat.t_rowptr : ctx->mat.rowptr,
                                   ns == 0 ? ctx->mat.t_colidx : ctx->mat.colidx,
                                   ns == 0 ? ctx->mat.t_vals : ctx->mat.vals, nrows, L.idx[ns], nd, nscale,
                                   L.a_cnt[ns], L.a_pos[ns], L.scan_ws[ns], L.a_rowptr[ns], L.a_cols[ns],
-                                  L.a_vals[ns], L.long_rows[ns], L.nlong[ns], ctx->side_stream));
+                                  L.a_vals[ns], L.long_rows[ns], L.nlong[ns], ctx->side_stream);
       }
+      // the event covers whatever went out, even after a failure, and the
+      // next use of these buffers waits for it; the result is used only if
+      // everything went out
       DSANLS_HIP(hipEventRecord(ctx->ev_sel[ns], ctx->side_stream));
-      ctx->sel_t[ns] = nt;
+      ctx->ahead_pending[ns] = true;
+      ctx->gathered_ahead[ns] = ast == DSANLS_OK && gather;
+      ctx->sel_t[ns] = ast == DSANLS_OK ? nt : -1;
+      if (ast != DSANLS_OK) return ast;
     }
   }
 #undef CHECK

@@ -241,6 +241,29 @@ def test_sparse_per_update_parity(env, sketch):
     assert abs(prob.solver.objective() - O.relative_error(M64, U, V)) / O.relative_error(M64, U, V) < 1e-5
 
 
+def test_sparse_run_ahead_any_call_order(env):
+    # the next side's subsample and sketched rows are prepared ahead on the
+    # context's second stream for (V, t) after update_U(t) and (U, t + 1)
+    # after update_V(t); calls that repeat a side, skip iterations or go
+    # back must wait for that work and redraw, giving the definition's
+    # result every time
+    m, n, k = 3000, 1200, 20
+    Ms, U0, V0 = _sparse_problem(m, n, 0.01, k, 5)
+    ocfg = _ocfg(k, 120, 300, O.SKETCH_SUBSAMPLE, O.SOLVER_PROX_CD, alpha=0.5, beta=0.5)
+    prob = Sparse(env, Ms, U0, V0, ocfg)
+    M64 = Ms.astype(np.float32).astype(np.float64).tocsr()
+    U, V = U0.astype(np.float32).astype(np.float64), V0.astype(np.float32).astype(np.float64)
+    for side, t in [(0, 3), (0, 3), (1, 7), (1, 3), (0, 4), (1, 4), (0, 5), (0, 9), (1, 9), (1, 9), (0, 2)]:
+        prob.set(U, V)
+        if side == 0:
+            prob.solver.update_U(t)
+            got, ref = prob.get()[0], O.update_U(M64, U, V, t, ocfg)
+        else:
+            prob.solver.update_V(t)
+            got, ref = prob.get()[1], O.update_V(M64, U, V, t, ocfg)
+        assert _rel(got, ref) < 1e-4, (side, t)
+
+
 def _skewed_sparse(m, n, k, seed):
     # Zipf-like column popularity, a few fully dense rows and columns, empty
     # rows and many empty columns: sampled columns of every length (0 to m)
