@@ -59,7 +59,10 @@ P split(T* base, int d, int k, int h) {
 }
 
 // H[b, :] = ReLU(H[b, :] + sum_e val_e W1a[col_e, :] + b1), H holding
-// u_b W1u^T on entry.  One wave per batch row.
+// u_b W1u^T on entry.  One wave per batch row: the row's entries are read
+// 64 at a time (one per lane) and walked through shuffles, each lane adding
+// its hidden units h = lane + 64 q, so that a W1a row's four segments are
+// in flight together (hd <= 256; larger widths take one segment at a time).
 __global__ __launch_bounds__(256) void l1_sparse_kernel(const int32_t* __restrict__ rowptr,
                                                         const int32_t* __restrict__ cols,
                                                         const float* __restrict__ vals,
@@ -71,6 +74,31 @@ __global__ __launch_bounds__(256) void l1_sparse_kernel(const int32_t* __restric
   const int lane = threadIdx.x & 63;
   if (r >= rows) return;
   const int beg = rowptr[r], end = rowptr[r + 1];
+  if (hd <= 256) {
+    float acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = lane + 64 * q < hd ? H[r * hd + lane + 64 * q] : 0.f;
+    for (int e0 = beg; e0 < end; e0 += 64) {
+      const int cnt = end - e0 < 64 ? end - e0 : 64;
+      int c = 0;
+      float v = 0.f;
+      if (lane < cnt) {
+        c = cols[e0 + lane];
+        v = vals[e0 + lane];
+      }
+      for (int i = 0; i < cnt; ++i) {
+        const float* w = W1a + static_cast<int64_t>(__shfl(c, i, 64)) * hd;
+        const float vi = __shfl(v, i, 64);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (lane + 64 * q < hd) acc[q] += vi * w[lane + 64 * q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (lane + 64 * q < hd) H[r * hd + lane + 64 * q] = relu(acc[q] + b1[lane + 64 * q]);
+    return;
+  }
   for (int h = lane; h < hd; h += 64) {
     float acc = H[r * hd + h];
     for (int e = beg; e < end; ++e) acc += vals[e] * W1a[static_cast<int64_t>(cols[e]) * hd + h];

@@ -690,28 +690,35 @@ __global__ __launch_bounds__(256) void tol_compact_kernel(const int32_t* __restr
   if (w < nwaves && r < wave_cnt[w]) list[wave_off[w] + r] = wave_rows[t];
 }
 
-// counters += (sum of used, rows with bit 0, rows with bit 1) over all rows
-// (one block, fixed order).
+// counters += (sum of used, rows with bit 0, rows with bit 1) over all rows.
+// Integer sums, so the order does not matter: each block sums a grid-stride
+// share through its waves and adds it with one atomic per counter.
 __global__ __launch_bounds__(256) void tol_stats_kernel(const int32_t* __restrict__ used,
                                                         const int32_t* __restrict__ flags,
                                                         int64_t rows,
                                                         unsigned long long* __restrict__ counters) {
-  __shared__ unsigned long long part[3][256];
+  __shared__ unsigned long long part[3][4];
   unsigned long long a = 0, b = 0, f = 0;
-  for (int64_t i = threadIdx.x; i < rows; i += 256) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < rows; i += gridDim.x * 256ll) {
     a += static_cast<unsigned long long>(used[i]);
     b += flags[i] & 1;
     f += (flags[i] >> 1) & 1;
   }
-  part[0][threadIdx.x] = a;
-  part[1][threadIdx.x] = b;
-  part[2][threadIdx.x] = f;
-  __syncthreads();
-  if (threadIdx.x < 3) {
-    unsigned long long t = 0;
-    for (int i = 0; i < 256; ++i) t += part[threadIdx.x][i];
-    counters[threadIdx.x] += t;
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+    f += __shfl_xor(f, o, 64);
   }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    part[0][w] = a;
+    part[1][w] = b;
+    part[2][w] = f;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3)
+    atomicAdd(&counters[threadIdx.x], part[threadIdx.x][0] + part[threadIdx.x][1] + part[threadIdx.x][2] +
+                                          part[threadIdx.x][3]);
 }
 
 // One projected-gradient step (eq. gradient_descent), every coordinate from
@@ -824,7 +831,8 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
     if (pass_no > 0) budget *= 2;
   }
   if (tw->counters != nullptr) {
-    tol_stats_kernel<<<1, 256, 0, s>>>(tw->used, tw->flags, rows, tw->counters);
+    const unsigned sg = static_cast<unsigned>(std::min<int64_t>(ceil_div(rows, 1024), 1024));
+    tol_stats_kernel<<<sg, 256, 0, s>>>(tw->used, tw->flags, rows, tw->counters);
     DSANLS_LAUNCHED("tol_stats_kernel");
   }
   if (sweeps_used != nullptr)
