@@ -135,8 +135,8 @@ TRAFFIC = {
                           "sha256": "477d98a43fd4e6bed56ce09f6405edee400d8b73fe09c36268615e925d203e15",
                           "fetch_kib": 2419643.13, "write_kib": 120000.0},
     "sparse-500000x200000": {"files": ["nnls.hip", "common.hpp"],
-                             "sha256": "b02463a883b83c26e40722a08c29adfb836a64b8b7038265c06f7146f97b17e1",
-                             "fetch_kib": 188534.5, "write_kib": 154932.7},
+                             "sha256": "bfcff6f1909c5f94423a3b8535edc9fe20f5614acd3358d7651454c4631fe31c",
+                             "fetch_kib": 182233.41, "write_kib": 144056.13},
     "dense-50000x20000-bf16": {"files": ["gemm.hip", "common.hpp"],
                                "sha256": "477d98a43fd4e6bed56ce09f6405edee400d8b73fe09c36268615e925d203e15",
                                "fetch_kib": 20248669.94, "write_kib": 1120000.0},
@@ -160,17 +160,21 @@ def traffic_bytes(workload):
 
 
 def sparse_roofline(w, M, tm, launches, workload):
-    """Roofline of the dominant sparse kernel, the NNLS sweep (VALU; the
-    longest single launch), with the sampled-column sketch product beside it
-    (HBM; a phase of about a dozen short kernels per side)."""
+    """Roofline of the dominant sparse kernel, the NNLS sweep (the longest
+    single launch), with the sampled-column sketch product beside it (HBM; a
+    phase of about a dozen short kernels per side).  The sweep moves 12 k
+    bytes per row (U and R read, U written) for 2 k^2 flop, k / 6 flop per
+    byte: at k = 100 below the FP32 matrix-core ridge (157.3 TFLOP/s over
+    8 TB/s, about 19.7 flop/B), so its roof is HBM bandwidth."""
     m, n, k, d = w["m"], w["n"], w["k"], w["d"]
     nnz = M.nnz
     half = launches // 2
     nnls_avg = tm["nnls_ms"] / 1e3 / launches
     prod_avg = tm["product_ms"] / 1e3 / launches
     flops = 2.0 * k * k * (m + n) / 2      # k^2 FMAs per row-sweep, mean over the two sides
-    ach = flops / nnls_avg / 1e12
-    peak = PEAK["fp32_valu_tflops"]
+    nbytes = 12.0 * k * (m + n) / 2        # U and R read, U written, mean over the two sides
+    ach = nbytes / nnls_avg / 1e9
+    tflops = flops / nnls_avg / 1e12
     # sampled-column gather: E = nnz d / lng sampled entries per side (their
     # expectation under uniform sampling), each read once from CSR(X^T)
     # (8 B), written to and read back from the sketched rows (16 B); R
@@ -178,9 +182,11 @@ def sparse_roofline(w, M, tm, launches, workload):
     e_u, e_v = nnz * d / n, nnz * d / m
     moved = (24.0 * (e_u + e_v) + (4.0 * k + 8.0) * (m + n)) / 2
     pach = moved / prod_avg / 1e9
-    return {"kernel": "prox-CD sweep (prox_cd_lds_kernel)", "bound": "alu", "achieved": ach, "peak": peak,
-            "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic_bytes(workload), "flops_per_launch": flops,
-            "avg_launch_ms": nnls_avg * 1e3,
+    kern = "prox_cd_mfma_kernel" if k % 4 == 0 and 64 < k <= 100 else "prox_cd_lds_kernel"
+    return {"kernel": f"prox-CD sweep ({kern})", "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"],
+            "unit": "GB/s", "frac": ach / PEAK["hbm_gbs"], "traffic": traffic_bytes(workload),
+            "bytes_per_launch": nbytes, "flops_per_launch": flops, "tflops": tflops,
+            "frac_of_fp32_mfma": tflops / PEAK["fp32_mfma_tflops"], "avg_launch_ms": nnls_avg * 1e3,
             "product_phase": {"kernels": "gather_len, scans, gather_entries, row_sort_long, a_rhs, a_rhs_long",
                               "bound": "hbm", "achieved": pach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
                               "frac": pach / PEAK["hbm_gbs"], "bytes_per_side": moved,

@@ -3,17 +3,18 @@
 // Every row i of U solves its own k-dimensional problem (the subproblem is
 // row-independent, eq. u_block), all sharing G = B B^T.  Layout: one lane
 // per row, 64 rows per wave.  The row's iterate u lives in registers as
-// W-wide vector blocks; the Gram is copied once into a padded KC x KC block
-// (column j of G stored as row j, zero diagonal) so that coordinate j reads
-// row j with wave-uniform scalar loads (s_load_dwordx16) and the k FMAs of
-// its dot product take G as a scalar operand: 64 rows share every G value
-// and no lane reads G through LDS.  The coordinate loop runs at run time
-// inside each (statically unrolled) block, so the one dynamic register
-// access per coordinate, u_j <- new value, is an indexed register write.
-// Rows of U move between HBM and the lanes through LDS panels of SW
-// columns, loaded and stored by the whole wave with coalesced row runs; the
-// right-hand side q = r + mu c streams into LDS one panel ahead of the
-// coordinates that use it.
+// W-wide vector blocks; the Gram is prepared once as a padded KC x KC block
+// (column j of G stored as row j, zero diagonal), copied into LDS by each
+// workgroup and read by coordinate j as row j with broadcast loads, so 64
+// rows share every G value.  The coordinate loop runs at run time inside
+// each (statically unrolled) block, so the one dynamic register access per
+// coordinate, u_j <- new value, is an indexed register write.  Rows of U
+// move between HBM and the lanes through LDS panels of SW columns, loaded
+// and stored by the whole wave with coalesced row runs; the right-hand side
+// q = r + mu c streams into LDS one panel ahead of the coordinates that use
+// it.  For fixed sweeps at the larger ranks a second kernel moves the
+// coupling between coordinate blocks onto the matrix cores (see
+// prox_cd_mfma_kernel).
 #include "common.hpp"
 
 namespace dsanls {
@@ -554,6 +555,205 @@ __global__ __launch_bounds__(64 * NWV) void prox_cd_lds_kernel(const float* __re
   if (valid && sweeps_used != nullptr) sweeps_used[row0 + lane_id()] = sweeps;
 }
 
+// Fixed sweeps for the larger ranks, with the coordinates in blocks of 16
+// and the coupling between blocks on the matrix cores.  The sweep is the
+// same Gauss-Seidel pass in the same coordinate order: for a coordinate j
+// of block b,
+//   sum_{l != j} G_lj u_l = T_j + sum_{l in b, l != j} G_lj u_l,
+//   T_j = sum_{l outside b} G_lj u_l,
+// where the blocks before b already hold this sweep's values and the blocks
+// after it the previous ones.  T for the 16 coordinates of block b and the
+// wave's 64 rows is one product (16 x (KP - 16)) x ((KP - 16) x 64), taken
+// with v_mfma_f32_16x16x4f32 right before the block is swept (its G
+// operand read from L2 one block ahead); the 16 coordinates themselves run
+// one lane per row on the VALU, with the block's own 16 x 16 part of G
+// read from LDS by broadcast.  So per row and sweep the VALU does 16 k
+// FMAs instead of k^2, and G is no longer read once per coordinate.
+//
+// Registers hold u in the MFMA operand layout: lane (m, g) = (lane % 16,
+// lane / 16) holds, for each row quarter r, the values of row 16 r + m at
+// coordinates 16 b + 4 g + e (e = 0..3) of every block b, which is also the
+// layout in which the product leaves T.  A block's u and T move to one lane
+// per row, and the new u back, through a 64 x 16 LDS tile whose 4-float
+// chunks are XOR-swizzled by row.  Only for k % 4 == 0 and 16-byte aligned
+// U (rows enter and leave as float4s in the operand layout).
+template <int KC>
+struct MfmaCd {
+  static constexpr int NBK = (KC + 15) / 16;   // coordinate blocks
+  static constexpr int KP = 16 * NBK;          // padded rank
+  static constexpr int NWV = 2;                // waves per workgroup
+};
+
+__device__ __forceinline__ int cd_chunk(int n, int c) { return 16 * n + 4 * (c ^ ((n >> 1) & 3)); }
+
+// Coordinates j0 .. j0 + NJ - 1 of one lane's row, in order: t = T_j plus
+// the block's own part of the dot product, then the proximal step.  The
+// block's rows of G (gb: row jj at gb + jj * GS, zero diagonal) and
+// 1 / (G_jj + mu) (ib) are read from LDS with broadcast reads, which the
+// compiler can issue ahead of the coordinates that use them (scalar loads
+// cannot be waited for one at a time).
+template <int NJ, int GS, typename F4, typename QV>
+__device__ __forceinline__ void cd_block(const float* gb, const float* ib, float mu, float ubnd,
+                                         bool c_is_u, const QV& qb, const F4 (&tr)[4], F4 (&ur)[4]) {
+  F4 gr[4], gn[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) gr[c] = *reinterpret_cast<const F4*>(gb + 4 * c);
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) {
+    // the next coordinate's row is in flight while this one computes
+    if (jj + 1 < NJ) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) gn[c] = *reinterpret_cast<const F4*>(gb + (jj + 1) * GS + 4 * c);
+    }
+    float t0 = tr[jj / 4][jj % 4], t1 = 0.f;
+#pragma unroll
+    for (int l = 0; l < NJ; ++l) {
+      if (l == jj) continue;
+      if (l & 1)
+        t1 += gr[l / 4][l % 4] * ur[l / 4][l % 4];
+      else
+        t0 += gr[l / 4][l % 4] * ur[l / 4][l % 4];
+    }
+    const float q = c_is_u ? qb[jj] + mu * ur[jj / 4][jj % 4] : qb[jj];
+    ur[jj / 4][jj % 4] = fminf(fmaxf((q - (t0 + t1)) * ib[jj], 0.f), ubnd);
+    if (jj + 1 < NJ) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) gr[c] = gn[c];
+    }
+  }
+}
+
+template <int KC>
+__global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_kernel(
+    const float* __restrict__ gp, const float* __restrict__ inv, const float* __restrict__ R,
+    const float* C, float* U, int64_t rows, int k, float mu, int sweeps, float upper,
+    int32_t* __restrict__ sweeps_used) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int NBK = MfmaCd<KC>::NBK, KP = MfmaCd<KC>::KP, NWV = MfmaCd<KC>::NWV;
+  // LDS: the 16 x 16 diagonal blocks of G (block b row jj at sd + (16 b +
+  // jj) * 16, zero past KC), 1 / (G_jj + mu), and per wave a right-hand-side
+  // panel and the transpose tile; about 15 KB a wave, so that several
+  // workgroups share a CU and one's loads and stores overlap another's
+  // arithmetic
+  __shared__ __attribute__((aligned(16))) float sd[NBK * 256];
+  __shared__ float sinv[KP];
+  __shared__ QPanel<16> qps[NWV];
+  __shared__ __attribute__((aligned(16))) float xs[NWV][64 * 16];
+  for (int i = threadIdx.x; i < NBK * 256; i += 64 * NWV) {
+    const int bk = i >> 8, j = 16 * bk + ((i >> 4) & 15), l = 16 * bk + (i & 15);
+    sd[i] = j < KC && l < KC ? gp[j * KC + l] : 0.f;
+  }
+  for (int i = threadIdx.x; i < KP; i += 64 * NWV) sinv[i] = i < KC ? inv[i] : 0.f;
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int64_t row0 = (blockIdx.x * static_cast<int64_t>(NWV) + wave) * 64;
+  if (row0 >= rows) return;
+  const int nrows = static_cast<int>(rows - row0 < 64 ? rows - row0 : 64);
+  const int lane = lane_id(), m = lane & 15, g = lane >> 4;
+  QPanel<16>& qp = qps[wave];
+  float* X = xs[wave];
+  const float ubnd = upper > 0.f ? upper : INFINITY;
+
+  f4 ub[NBK][4];
+#pragma unroll
+  for (int b = 0; b < NBK; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = 16 * r + m, c = 16 * b + 4 * g;
+      ub[b][r] = n < nrows && c < k ? *reinterpret_cast<const f4*>(U + (row0 + n) * k + c) : f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  // The blocks rotate through ub: while block b is swept it sits in ub[0]
+  // and ub[i] holds block (b + i) mod NBK, so every register index is
+  // static while the block loop runs at run time; after a sweep the order
+  // is the original one again.
+  // The MFMA's A operand for block b, rotated block i: G values of row
+  // 16 b + m at coordinates 16 bb + 4 g .. + 3, bb = (b + i) mod NBK, read
+  // from the prepared G in global memory (L2-resident) during the previous
+  // block's coordinates; zero outside KC x KC.
+  f4 an[NBK - 1];
+  auto fetch_a = [&](int b) {
+#pragma unroll
+    for (int i = 1; i < NBK; ++i) {
+      const int bb = b + i < NBK ? b + i : b + i - NBK;
+      const int j = 16 * b + m, l = 16 * bb + 4 * g;
+      const bool in = j < KC && l < KC;
+      an[i - 1] = *reinterpret_cast<const f4*>(gp + (in ? j * KC + l : 0));
+      if (!in) an[i - 1] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  fetch_a(0);
+  for (int s = 0; s < sweeps; ++s) {
+    const bool c_is_u = s == 0 && C == U;
+    wait_lds_reads();
+    q_issue<16>(qp, R, C, row0, nrows, k, 0, !c_is_u);
+#pragma nounroll
+    for (int b = 0; b < NBK; ++b) {
+      f4 a[NBK - 1];
+#pragma unroll
+      for (int i = 0; i + 1 < NBK; ++i) a[i] = an[i];
+      // T of block b's coordinates from every other block
+      f4 acc[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 1; i < NBK; ++i) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i - 1][e], ub[i][r][e], acc[r], 0, 0, 0);
+      }
+      // the block's u and T to one lane per row (one wave's LDS accesses
+      // are carried out in order, so the tile is reused without waits: the
+      // compiler waits only where the values read are used)
+      f4 ur[4], tr[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) *reinterpret_cast<f4*>(X + cd_chunk(16 * r + m, g)) = ub[0][r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ur[c] = *reinterpret_cast<const f4*>(X + cd_chunk(lane, c));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) *reinterpret_cast<f4*>(X + cd_chunk(16 * r + m, g)) = acc[r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) tr[c] = *reinterpret_cast<const f4*>(X + cd_chunk(lane, c));
+      typename RowBlocks<16, 16>::vec qb;
+      q_read<16>(qp, mu, 16 * b, k, !c_is_u, qb);
+      wait_lds_reads();
+      if (b + 1 < NBK) q_issue<16>(qp, R, C, row0, nrows, k, 16 * (b + 1), !c_is_u);
+      // the next block's operands, issued after the panel wait above (which
+      // waits for every load in flight)
+      fetch_a(b + 1 < NBK ? b + 1 : 0);
+      // the block's coordinates in order (the last block of a rank that is
+      // not a multiple of 16 has only KC % 16 of them)
+      const float* gb = sd + 256 * b;
+      if (KC % 16 != 0 && b == NBK - 1)
+        cd_block<(KC % 16 != 0 ? KC % 16 : 16), 16>(gb, sinv + 16 * b, mu, ubnd, c_is_u, qb, tr, ur);
+      else
+        cd_block<16, 16>(gb, sinv + 16 * b, mu, ubnd, c_is_u, qb, tr, ur);
+      // the new values back to the operand layout, then rotate
+#pragma unroll
+      for (int c = 0; c < 4; ++c) *reinterpret_cast<f4*>(X + cd_chunk(lane, c)) = ur[c];
+      f4 nb[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) nb[r] = *reinterpret_cast<const f4*>(X + cd_chunk(16 * r + m, g));
+#pragma unroll
+      for (int i = 0; i + 1 < NBK; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ub[i][r] = ub[i + 1][r];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ub[NBK - 1][r] = nb[r];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NBK; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = 16 * r + m, c = 16 * b + 4 * g;
+      if (n < nrows && c < k) *reinterpret_cast<f4*>(U + (row0 + n) * k + c) = ub[b][r];
+    }
+  if (lane < nrows && sweeps_used != nullptr) sweeps_used[row0 + lane] = sweeps;
+}
+
 // One pass of the to-tolerance solve.  Sweeps run on the lanes whose row is
 // pending (relative projected-gradient norm above tol) until every row of
 // the wave has converged, spent max_sweeps, or spent this pass's budget; the
@@ -791,6 +991,15 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
     pgd_kernel<KC, W, SW><<<grid, 64, 0, s>>>(p.gp, p.gdiag, p.colsum, R, U, rows, k, mu, upper);
     DSANLS_LAUNCHED("pgd_kernel");
     return DSANLS_OK;
+  }
+  if constexpr (KC == 96 || KC == 100) {
+    if (sweeps > 0 && k % 4 == 0 && ((reinterpret_cast<uintptr_t>(U) | reinterpret_cast<uintptr_t>(p.gp)) & 15) == 0) {
+      constexpr int NM = MfmaCd<KC>::NWV;
+      prox_cd_mfma_kernel<KC><<<static_cast<unsigned>(ceil_div(nw, NM)), 64 * NM, 0, s>>>(
+          p.gp, p.inv, R, C, U, rows, k, mu, sweeps, upper, sweeps_used);
+      DSANLS_LAUNCHED("prox_cd_mfma_kernel");
+      return DSANLS_OK;
+    }
   }
   if (sweeps > 0) {
     prox_cd_lds_kernel<KC, W, SW, NWV><<<gl, 64 * NWV, 0, s>>>(p.gp, p.inv, R, C, U, rows, k, mu, sweeps, upper,
