@@ -162,6 +162,29 @@ def test_prox_cd_upper_clip_and_empty(torch_dev):
     B.nnls_prox_cd(torch.from_numpy(G).cuda(), E, E, E, 0.5)
 
 
+@pytest.mark.parametrize("k,sweeps", [(100, 2), (96, 1), (92, 3)])
+def test_prox_cd_block_coupling_kernel_clip_alias_counts(torch_dev, k, sweeps):
+    # fixed sweeps at k % 4 == 0, 64 < k <= 100 take the kernel that couples
+    # 16-coordinate blocks on the matrix cores: an upper bound that binds, a
+    # centre that is U itself over several sweeps (C is read from memory
+    # after the first), per-row sweep counts, and 133 rows (three waves: the
+    # last two-wave workgroup has one wave without rows, the third wave is
+    # ragged)
+    torch, B = torch_dev
+    rows, mu, ub = 133, 0.6, 0.3
+    G, R, U0 = _nnls_problem(rows, k, 3 * k + 5, 300 + k)
+    R = R * 20
+    U = torch.from_numpy(U0.copy()).cuda()
+    used = B.nnls_prox_cd(torch.from_numpy(G).cuda(), torch.from_numpy(R).cuda(), U, U, mu, sweeps=sweeps,
+                          upper=ub, want_sweeps=True)
+    U64 = U0.astype(np.float64)
+    ref, _ = O.prox_cd_solve(U64, U64, G.astype(np.float64), R.astype(np.float64), mu, sweeps, upper=ub)
+    Ud = U.cpu().numpy()
+    assert _rel(Ud, ref) < 1e-4
+    assert Ud.max() <= ub and Ud.min() >= 0 and np.any(Ud == np.float32(ub))
+    assert np.all(used.cpu().numpy() == sweeps)
+
+
 @pytest.mark.parametrize("k,sweeps", [(100, 1), (100, 3), (10, 1), (64, 2)])
 def test_prox_cd_centre_differs_from_start(torch_dev, k, sweeps):
     # the proximal centre C is not the starting point: every sweep must read
