@@ -105,7 +105,7 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
 
 
-@pytest.mark.parametrize("k", [1, 3, 4, 10, 16, 33, 64, 92, 96, 100, 128])
+@pytest.mark.parametrize("k", [1, 3, 4, 10, 16, 33, 64, 68, 92, 96, 100, 128])
 @pytest.mark.parametrize("sweeps", [1, 3])
 def test_prox_cd_matches_oracle(torch_dev, k, sweeps):
     torch, B = torch_dev
