@@ -594,7 +594,8 @@ __device__ __forceinline__ int cd_chunk(int n, int c) { return 16 * n + 4 * (c ^
 // cannot be waited for one at a time).
 template <int NJ, int GS, typename F4, typename QV>
 __device__ __forceinline__ void cd_block(const float* gb, const float* ib, float mu, float ubnd,
-                                         bool c_is_u, const QV& qb, const F4 (&tr)[4], F4 (&ur)[4]) {
+                                         bool c_is_u, bool act, const QV& qb, const F4 (&tr)[4],
+                                         F4 (&ur)[4]) {
   F4 gr[4], gn[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) gr[c] = *reinterpret_cast<const F4*>(gb + 4 * c);
@@ -615,10 +616,42 @@ __device__ __forceinline__ void cd_block(const float* gb, const float* ib, float
         t0 += gr[l / 4][l % 4] * ur[l / 4][l % 4];
     }
     const float q = c_is_u ? qb[jj] + mu * ur[jj / 4][jj % 4] : qb[jj];
-    ur[jj / 4][jj % 4] = fminf(fmaxf((q - (t0 + t1)) * ib[jj], 0.f), ubnd);
+    const float v = fminf(fmaxf((q - (t0 + t1)) * ib[jj], 0.f), ubnd);
+    if (act) ur[jj / 4][jj % 4] = v;
     if (jj + 1 < NJ) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) gr[c] = gn[c];
+    }
+  }
+}
+
+// Projected-gradient terms of coordinates j0 .. j0 + NJ - 1 of one lane's
+// row (the KKT test of the to-tolerance solve): g_j = T_j + the block's
+// own part of (G u)_j + (G_jj + mu) u_j - q_j, clipped at 0 from above where
+// u_j = 0; sums of g_j^2 and q_j^2 over the coordinates below k.
+template <int NJ, typename F4, typename QV>
+__device__ __forceinline__ void kkt_block(const float* gb, const float* db, int j0, int k, const QV& qb,
+                                          const F4 (&tr)[4], const F4 (&ur)[4], float& pg2, float& q2) {
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) {
+    F4 gr[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) gr[c] = *reinterpret_cast<const F4*>(gb + jj * 16 + 4 * c);
+    float t0 = tr[jj / 4][jj % 4], t1 = 0.f;
+#pragma unroll
+    for (int l = 0; l < NJ; ++l) {
+      if (l == jj) continue;
+      if (l & 1)
+        t1 += gr[l / 4][l % 4] * ur[l / 4][l % 4];
+      else
+        t0 += gr[l / 4][l % 4] * ur[l / 4][l % 4];
+    }
+    const float uj = ur[jj / 4][jj % 4];
+    float gj = (t0 + t1) + db[jj] * uj - qb[jj];
+    if (!(uj > 0.f)) gj = fminf(gj, 0.f);
+    if (j0 + jj < k) {
+      pg2 += gj * gj;
+      q2 += qb[jj] * qb[jj];
     }
   }
 }
@@ -727,9 +760,9 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_kernel(
       // not a multiple of 16 has only KC % 16 of them)
       const float* gb = sd + 256 * b;
       if (KC % 16 != 0 && b == NBK - 1)
-        cd_block<(KC % 16 != 0 ? KC % 16 : 16), 16>(gb, sinv + 16 * b, mu, ubnd, c_is_u, qb, tr, ur);
+        cd_block<(KC % 16 != 0 ? KC % 16 : 16), 16>(gb, sinv + 16 * b, mu, ubnd, c_is_u, true, qb, tr, ur);
       else
-        cd_block<16, 16>(gb, sinv + 16 * b, mu, ubnd, c_is_u, qb, tr, ur);
+        cd_block<16, 16>(gb, sinv + 16 * b, mu, ubnd, c_is_u, true, qb, tr, ur);
       // the new values back to the operand layout, then rotate
 #pragma unroll
       for (int c = 0; c < 4; ++c) *reinterpret_cast<f4*>(X + cd_chunk(lane, c)) = ur[c];
@@ -878,6 +911,251 @@ __global__ __launch_bounds__(64 * NWV) void prox_cd_tol_kernel(const float* __re
   }
 }
 
+// One pass of the to-tolerance solve in the block form of
+// prox_cd_mfma_kernel: the same passes, start choice, per-row stopping and
+// bookkeeping as prox_cd_tol_kernel, with every sweep and every KKT test
+// taking the coupling between 16-coordinate blocks on the matrix cores.  A
+// row that is done (or has no budget left) keeps its values: all rows of
+// the wave enter the products, only running rows take new values.  The
+// centre C never aliases U here (the passes copy it first), so q = r + mu c
+// is always read.
+template <int KC>
+__global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
+    const float* __restrict__ gp, const float* __restrict__ den, const float* __restrict__ inv,
+    const float* __restrict__ R, const float* C, const float* start, float* U, int64_t rows, int k,
+    float mu, float tol, int max_sweeps, float upper, TolPass pass) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int NBK = MfmaCd<KC>::NBK, KP = MfmaCd<KC>::KP, NWV = MfmaCd<KC>::NWV;
+  __shared__ __attribute__((aligned(16))) float sd[NBK * 256];
+  __shared__ float sinv[KP];
+  __shared__ float sden[KP];
+  __shared__ QPanel<16> qps[NWV];
+  __shared__ __attribute__((aligned(16))) float xs[NWV][64 * 16];
+  for (int i = threadIdx.x; i < NBK * 256; i += 64 * NWV) {
+    const int bk = i >> 8, j = 16 * bk + ((i >> 4) & 15), l = 16 * bk + (i & 15);
+    sd[i] = j < KC && l < KC ? gp[j * KC + l] : 0.f;
+  }
+  for (int i = threadIdx.x; i < KP; i += 64 * NWV) {
+    sinv[i] = i < KC ? inv[i] : 0.f;
+    sden[i] = i < KC ? den[i] : 0.f;
+  }
+  __syncthreads();
+  const int wib = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int64_t wave = blockIdx.x * static_cast<int64_t>(NWV) + wib;
+  if (wave * 64 >= rows) return;   // past the last wave (its per-wave slots do not exist)
+  const int lane = lane_id(), m = lane & 15, g = lane >> 4;
+  const int64_t row0 = wave * 64;
+  const int32_t* rmap = nullptr;
+  int nrows;
+  if (pass.list_in != nullptr) {
+    const int64_t cnt = *pass.count_in;
+    if (row0 >= cnt) {
+      if (pass.wave_cnt != nullptr && lane == 0) pass.wave_cnt[wave] = 0;
+      return;
+    }
+    nrows = static_cast<int>(cnt - row0 < 64 ? cnt - row0 : 64);
+    rmap = pass.list_in + row0;
+  } else {
+    nrows = static_cast<int>(rows - row0 < 64 ? rows - row0 : 64);
+  }
+  const bool valid = lane < nrows;
+  const int64_t myrow = valid ? (rmap != nullptr ? static_cast<int64_t>(rmap[lane]) : row0 + lane) : 0;
+  const float ubnd = upper > 0.f ? upper : INFINITY;
+  QPanel<16>& qp = qps[wib];
+  float* X = xs[wib];
+
+  f4 ub[NBK][4];
+  // rows of P into the operand layout, for the rows whose bit is set in take
+  auto load_ub = [&](const float* P, unsigned long long take) {
+#pragma unroll
+    for (int b = 0; b < NBK; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = 16 * r + m, c = 16 * b + 4 * g;
+        if ((take >> n) & 1ull) {
+          if (n < nrows && c < k) {
+            const int64_t row = rmap != nullptr ? static_cast<int64_t>(rmap[n]) : row0 + n;
+            ub[b][r] = *reinterpret_cast<const f4*>(P + row * k + c);
+          } else {
+            ub[b][r] = f4{0.f, 0.f, 0.f, 0.f};
+          }
+        }
+      }
+  };
+  f4 an[NBK - 1];
+  auto fetch_a = [&](int b) {
+#pragma unroll
+    for (int i = 1; i < NBK; ++i) {
+      const int bb = b + i < NBK ? b + i : b + i - NBK;
+      const int j = 16 * b + m, l = 16 * bb + 4 * g;
+      const bool in = j < KC && l < KC;
+      an[i - 1] = *reinterpret_cast<const f4*>(gp + (in ? j * KC + l : 0));
+      if (!in) an[i - 1] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  // T of block b (in ub[0]) from the other blocks, then block b's u and T
+  // to one lane per row, and its right-hand side
+  auto block_in = [&](int b, f4 (&ur)[4], f4 (&tr)[4], typename RowBlocks<16, 16>::vec& qb) {
+    f4 a[NBK - 1];
+#pragma unroll
+    for (int i = 0; i + 1 < NBK; ++i) a[i] = an[i];
+    f4 acc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 1; i < NBK; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i - 1][e], ub[i][r][e], acc[r], 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) *reinterpret_cast<f4*>(X + cd_chunk(16 * r + m, g)) = ub[0][r];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ur[c] = *reinterpret_cast<const f4*>(X + cd_chunk(lane, c));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) *reinterpret_cast<f4*>(X + cd_chunk(16 * r + m, g)) = acc[r];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) tr[c] = *reinterpret_cast<const f4*>(X + cd_chunk(lane, c));
+    q_read<16>(qp, mu, 16 * b, k, true, qb);
+    wait_lds_reads();
+    if (b + 1 < NBK) q_issue<16>(qp, R, C, row0, nrows, k, 16 * (b + 1), true, rmap);
+    fetch_a(b + 1 < NBK ? b + 1 : 0);
+  };
+  // rotate the blocks by one, block b's (new) values taking the last slot
+  auto block_out = [&](const f4 (&nb)[4]) {
+#pragma unroll
+    for (int i = 0; i + 1 < NBK; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ub[i][r] = ub[i + 1][r];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ub[NBK - 1][r] = nb[r];
+  };
+  auto sweep_pass = [&](bool run) {
+    wait_lds_reads();
+    q_issue<16>(qp, R, C, row0, nrows, k, 0, true, rmap);
+#pragma nounroll
+    for (int b = 0; b < NBK; ++b) {
+      f4 ur[4], tr[4];
+      typename RowBlocks<16, 16>::vec qb;
+      block_in(b, ur, tr, qb);
+      const float* gb = sd + 256 * b;
+      if (KC % 16 != 0 && b == NBK - 1)
+        cd_block<(KC % 16 != 0 ? KC % 16 : 16), 16>(gb, sinv + 16 * b, mu, ubnd, false, run, qb, tr, ur);
+      else
+        cd_block<16, 16>(gb, sinv + 16 * b, mu, ubnd, false, run, qb, tr, ur);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) *reinterpret_cast<f4*>(X + cd_chunk(lane, c)) = ur[c];
+      f4 nb[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) nb[r] = *reinterpret_cast<const f4*>(X + cd_chunk(16 * r + m, g));
+      block_out(nb);
+    }
+  };
+  auto kkt_pass = [&]() -> float {
+    float pg2 = 0.f, q2 = 0.f;
+    wait_lds_reads();
+    q_issue<16>(qp, R, C, row0, nrows, k, 0, true, rmap);
+#pragma nounroll
+    for (int b = 0; b < NBK; ++b) {
+      f4 ur[4], tr[4];
+      typename RowBlocks<16, 16>::vec qb;
+      block_in(b, ur, tr, qb);
+      const float* gb = sd + 256 * b;
+      if (KC % 16 != 0 && b == NBK - 1)
+        kkt_block<(KC % 16 != 0 ? KC % 16 : 16)>(gb, sden + 16 * b, 16 * b, k, qb, tr, ur, pg2, q2);
+      else
+        kkt_block<16>(gb, sden + 16 * b, 16 * b, k, qb, tr, ur, pg2, q2);
+      f4 nb[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) nb[r] = ub[0][r];
+      block_out(nb);
+    }
+    return sqrtf(pg2) / fmaxf(sqrtf(q2), 1e-30f);
+  };
+
+  fetch_a(0);
+  int used = 0;
+  bool fell_back = false;
+  float res = INFINITY;   // a listed row is pending
+  if (rmap == nullptr) {
+    load_ub(start != nullptr ? start : U, ~0ull);
+    bool ok = valid;
+    if (start != nullptr) {
+      // a row is finite when none of its four lanes' values is not
+      unsigned long long bad[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        bool fin = true;
+#pragma unroll
+        for (int b = 0; b < NBK; ++b)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) fin = fin && isfinite(ub[b][r][e]);
+        bad[r] = __ballot(!fin);
+      }
+      const int rr = lane >> 4, mm = lane & 15;
+      const unsigned long long br = rr == 0 ? bad[0] : rr == 1 ? bad[1] : rr == 2 ? bad[2] : bad[3];
+      const unsigned long long mine = (br >> mm) | (br >> (mm + 16)) | (br >> (mm + 32)) | (br >> (mm + 48));
+      ok = ok && !(mine & 1ull);
+    }
+    const float res_w = kkt_pass();
+    float res_c = 0.f;
+    if (start != nullptr) {
+      load_ub(C, ~0ull);
+      res_c = kkt_pass();
+    }
+    res = res_w;
+    if (start != nullptr) {
+      const bool warm = ok && res_w < res_c;
+      fell_back = valid && !warm;
+      const unsigned long long wm = __ballot(warm);
+      if (wm != 0ull) load_ub(start, wm);
+      res = warm ? res_w : res_c;
+    }
+  } else {
+    load_ub(U, ~0ull);
+    used = valid && pass.used != nullptr ? pass.used[myrow] : 0;
+  }
+  int here = 0;
+  bool pend = false;
+  for (;;) {
+    if (valid) pend = res > tol;
+    const bool run = valid && pend && used < max_sweeps && here < pass.budget;
+    if (!__any(run)) break;
+    sweep_pass(run);
+    if (run) {
+      ++used;
+      ++here;
+    }
+    res = kkt_pass();
+  }
+#pragma unroll
+  for (int b = 0; b < NBK; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = 16 * r + m, c = 16 * b + 4 * g;
+      if (n < nrows && c < k) {
+        const int64_t row = rmap != nullptr ? static_cast<int64_t>(rmap[n]) : row0 + n;
+        *reinterpret_cast<f4*>(U + row * k + c) = ub[b][r];
+      }
+    }
+  const bool keep = valid && pend && used < max_sweeps && pass.wave_cnt != nullptr;
+  if (valid) {
+    if (pass.used != nullptr) pass.used[myrow] = used;
+    if (pass.flags != nullptr) {
+      const int32_t unconv = !keep && pend ? 1 : 0;
+      if (rmap == nullptr) pass.flags[myrow] = (fell_back ? 2 : 0) | unconv;
+      else if (unconv) pass.flags[myrow] |= 1;
+    }
+  }
+  if (pass.wave_cnt != nullptr) {
+    const unsigned long long mk = __ballot(keep);
+    const int rank = __popcll(mk & ((1ull << lane) - 1ull));
+    if (keep) pass.wave_rows[wave * 64 + rank] = static_cast<int32_t>(myrow);
+    if (lane == 0) pass.wave_cnt[wave] = __popcll(mk);
+  }
+}
+
 // list[wave_off[w] + r] = wave_rows[64 w + r] for r < wave_cnt[w]: the rows
 // left pending, in wave order.
 __global__ __launch_bounds__(256) void tol_compact_kernel(const int32_t* __restrict__ wave_cnt,
@@ -1007,13 +1285,30 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
     DSANLS_LAUNCHED("prox_cd_lds_kernel");
     return DSANLS_OK;
   }
+  // one pass of the to-tolerance solve: in the block form (coupling on the
+  // matrix cores) where the fixed sweeps take it and every row source is
+  // 16-byte aligned, else one dot product per coordinate
+  auto tol_pass = [&](const TolPass& ps, const float* Cc) -> dsanls_status {
+    if constexpr (KC == 96 || KC == 100) {
+      const uintptr_t al = reinterpret_cast<uintptr_t>(U) | reinterpret_cast<uintptr_t>(Cc) |
+                           reinterpret_cast<uintptr_t>(start) | reinterpret_cast<uintptr_t>(p.gp);
+      if (k % 4 == 0 && (al & 15) == 0) {
+        constexpr int NM = MfmaCd<KC>::NWV;
+        prox_cd_mfma_tol_kernel<KC><<<static_cast<unsigned>(ceil_div(nw, NM)), 64 * NM, 0, s>>>(
+            p.gp, p.den, p.inv, R, Cc, start, U, rows, k, mu, tol, max_sweeps, upper, ps);
+        DSANLS_LAUNCHED("prox_cd_mfma_tol_kernel");
+        return DSANLS_OK;
+      }
+    }
+    prox_cd_tol_kernel<KC, W, SW, NWV><<<gl, 64 * NWV, 0, s>>>(p.gp, p.den, p.inv, R, Cc, start, U, rows, k,
+                                                               mu, tol, max_sweeps, upper, ps);
+    DSANLS_LAUNCHED("prox_cd_tol_kernel");
+    return DSANLS_OK;
+  };
   if (tw == nullptr) {
     // one pass to the end (no compaction workspace)
     const TolPass one{nullptr, nullptr, max_sweeps, sweeps_used, nullptr, nullptr, nullptr};
-    prox_cd_tol_kernel<KC, W, SW, NWV><<<gl, 64 * NWV, 0, s>>>(p.gp, p.den, p.inv, R, C, start, U, rows, k,
-                                                               mu, tol, max_sweeps, upper, one);
-    DSANLS_LAUNCHED("prox_cd_tol_kernel");
-    return DSANLS_OK;
+    return tol_pass(one, C);
   }
   // passes with budgets 16, 16, 32, 64, ... sweeps; the last pass runs to
   // max_sweeps and lists nothing.  Each pass writes U, so a centre that
@@ -1027,11 +1322,10 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
     const bool last = spent + budget >= max_sweeps;
     TolPass ps{pass_no == 0 ? nullptr : tw->list[pass_no & 1], pass_no == 0 ? nullptr : tw->wave_off + nw,
                last ? max_sweeps : budget, tw->used, tw->flags, last ? nullptr : tw->wave_cnt, tw->wave_rows};
-    prox_cd_tol_kernel<KC, W, SW, NWV><<<gl, 64 * NWV, 0, s>>>(p.gp, p.den, p.inv, R, C, start, U, rows, k,
-                                                               mu, tol, max_sweeps, upper, ps);
-    DSANLS_LAUNCHED("prox_cd_tol_kernel");
+    dsanls_status st = tol_pass(ps, C);
+    if (st != DSANLS_OK) return st;
     if (last) break;
-    dsanls_status st = launch_exclusive_scan(tw->wave_cnt, tw->wave_off, nw, tw->scan_ws, s);
+    st = launch_exclusive_scan(tw->wave_cnt, tw->wave_off, nw, tw->scan_ws, s);
     if (st != DSANLS_OK) return st;
     tol_compact_kernel<<<static_cast<unsigned>(ceil_div(nw * 64, 256)), 256, 0, s>>>(
         tw->wave_cnt, tw->wave_off, tw->wave_rows, nw, tw->list[(pass_no + 1) & 1]);

@@ -119,7 +119,7 @@ def test_prox_cd_matches_oracle(torch_dev, k, sweeps):
     assert U.min().item() >= 0
 
 
-@pytest.mark.parametrize("k", [4, 10, 64, 100])
+@pytest.mark.parametrize("k", [4, 10, 64, 92, 100])
 def test_prox_cd_to_tolerance(torch_dev, k):
     torch, B = torch_dev
     rows, mu = 513, 2.0

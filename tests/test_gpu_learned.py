@@ -156,6 +156,34 @@ def test_warm_start_reaches_the_cold_solution(env):
         Uc.copy_(Uref)
 
 
+def test_poisoned_warm_start_falls_back_at_k100(env):
+    # at k = 100 the to-tolerance passes take the block form (coupling on
+    # the matrix cores): a start that is not finite, or finite but worse
+    # than U^t, is never taken, and the update is the cold one
+    torch, Bd = env
+    m, n, k, d, h = 700, 500, 100, 80, 32
+    cold, M64, Uc, Vc, U0, V0 = _sparse_ctx(env, m, n, k, d, 9)
+    warm, _, Uw, Vw, _, _ = _sparse_ctx(env, m, n, k, d, 9, warm_hidden=h)
+    p = Bd.mlp_pack(synth.mlp_init(d, k, h, 1))
+    for poison in ("nan", "inf", "far"):
+        bad = p.clone()
+        if poison == "nan":
+            bad[:] = float("nan")
+        else:
+            bad[:] = 0.0
+            bad[-k:] = float("inf") if poison == "inf" else 1e3   # output bias
+        Uw.copy_(Uc)
+        Vw.copy_(Vc)
+        warm.set_warm_start(bad, h)
+        before = warm.stats()["warm_fallbacks"]
+        warm.update_U(0)
+        Uref = Uc.clone()
+        cold.update_U(0)
+        assert warm.stats()["warm_fallbacks"] - before == m, poison
+        assert _rel(Uw.cpu().numpy(), Uc.cpu().numpy()) < 1e-6
+        Uc.copy_(Uref)
+
+
 def test_cold_to_tolerance_update_matches_oracle(env):
     m, n, k, d = 700, 500, 10, 80
     s, M64, U, V, U0, V0 = _sparse_ctx(env, m, n, k, d, 9, tol=1e-5)
