@@ -911,15 +911,28 @@ __global__ __launch_bounds__(64 * NWV) void prox_cd_tol_kernel(const float* __re
   }
 }
 
+// Q = R + mu C over n4 float4s (16-byte aligned): the right-hand side of
+// every pass of a to-tolerance solve in the block form, formed once.
+__global__ __launch_bounds__(256) void qsum_kernel(const float4* __restrict__ R, const float4* C, float mu,
+                                                   int64_t n4, float4* __restrict__ Q) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n4; i += gridDim.x * 256ll) {
+    const float4 r = R[i], c = C[i];
+    Q[i] = make_float4(r.x + mu * c.x, r.y + mu * c.y, r.z + mu * c.z, r.w + mu * c.w);
+  }
+}
+
 // One pass of the to-tolerance solve in the block form of
 // prox_cd_mfma_kernel: the same passes, start choice, per-row stopping and
 // bookkeeping as prox_cd_tol_kernel, with every sweep and every KKT test
 // taking the coupling between 16-coordinate blocks on the matrix cores.  A
 // row that is done (or has no budget left) keeps its values: all rows of
-// the wave enter the products, only running rows take new values.  The
-// centre C never aliases U here (the passes copy it first), so q = r + mu c
-// is always read.
-template <int KC>
+// the wave enter the products, only running rows take new values.  With
+// WITHC, q = r + mu c is formed panel by panel from R and C; without, R
+// already holds q (formed once for all passes) and C is read only as the
+// cold start of the first pass, each row before its wave writes it (so C
+// may alias U).  A run-time flag in place of WITHC made the passes 25%
+// slower.
+template <int KC, bool WITHC>
 __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
     const float* __restrict__ gp, const float* __restrict__ den, const float* __restrict__ inv,
     const float* __restrict__ R, const float* C, const float* start, float* U, int64_t rows, int k,
@@ -1017,9 +1030,9 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
     for (int r = 0; r < 4; ++r) *reinterpret_cast<f4*>(X + cd_chunk(16 * r + m, g)) = acc[r];
 #pragma unroll
     for (int c = 0; c < 4; ++c) tr[c] = *reinterpret_cast<const f4*>(X + cd_chunk(lane, c));
-    q_read<16>(qp, mu, 16 * b, k, true, qb);
+    q_read<16>(qp, mu, 16 * b, k, WITHC, qb);
     wait_lds_reads();
-    if (b + 1 < NBK) q_issue<16>(qp, R, C, row0, nrows, k, 16 * (b + 1), true, rmap);
+    if (b + 1 < NBK) q_issue<16>(qp, R, C, row0, nrows, k, 16 * (b + 1), WITHC, rmap);
     fetch_a(b + 1 < NBK ? b + 1 : 0);
   };
   // rotate the blocks by one, block b's (new) values taking the last slot
@@ -1033,7 +1046,7 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
   };
   auto sweep_pass = [&](bool run) {
     wait_lds_reads();
-    q_issue<16>(qp, R, C, row0, nrows, k, 0, true, rmap);
+    q_issue<16>(qp, R, C, row0, nrows, k, 0, WITHC, rmap);
 #pragma nounroll
     for (int b = 0; b < NBK; ++b) {
       f4 ur[4], tr[4];
@@ -1055,7 +1068,7 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
   auto kkt_pass = [&]() -> float {
     float pg2 = 0.f, q2 = 0.f;
     wait_lds_reads();
-    q_issue<16>(qp, R, C, row0, nrows, k, 0, true, rmap);
+    q_issue<16>(qp, R, C, row0, nrows, k, 0, WITHC, rmap);
 #pragma nounroll
     for (int b = 0; b < NBK; ++b) {
       f4 ur[4], tr[4];
@@ -1288,14 +1301,26 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
   // one pass of the to-tolerance solve: in the block form (coupling on the
   // matrix cores) where the fixed sweeps take it and every row source is
   // 16-byte aligned, else one dot product per coordinate
+  bool block = false;
+  if constexpr (KC == 96 || KC == 100) {
+    const uintptr_t al = reinterpret_cast<uintptr_t>(U) | reinterpret_cast<uintptr_t>(C) |
+                         reinterpret_cast<uintptr_t>(start) | reinterpret_cast<uintptr_t>(p.gp) |
+                         reinterpret_cast<uintptr_t>(R) |
+                         reinterpret_cast<uintptr_t>(tw != nullptr ? tw->centre : nullptr);
+    block = k % 4 == 0 && (al & 15) == 0;
+  }
+  const float* Rq = R;
+  bool qc = true;
   auto tol_pass = [&](const TolPass& ps, const float* Cc) -> dsanls_status {
     if constexpr (KC == 96 || KC == 100) {
-      const uintptr_t al = reinterpret_cast<uintptr_t>(U) | reinterpret_cast<uintptr_t>(Cc) |
-                           reinterpret_cast<uintptr_t>(start) | reinterpret_cast<uintptr_t>(p.gp);
-      if (k % 4 == 0 && (al & 15) == 0) {
+      if (block) {
         constexpr int NM = MfmaCd<KC>::NWV;
-        prox_cd_mfma_tol_kernel<KC><<<static_cast<unsigned>(ceil_div(nw, NM)), 64 * NM, 0, s>>>(
-            p.gp, p.den, p.inv, R, Cc, start, U, rows, k, mu, tol, max_sweeps, upper, ps);
+        if (qc)
+          prox_cd_mfma_tol_kernel<KC, true><<<static_cast<unsigned>(ceil_div(nw, NM)), 64 * NM, 0, s>>>(
+              p.gp, p.den, p.inv, Rq, Cc, start, U, rows, k, mu, tol, max_sweeps, upper, ps);
+        else
+          prox_cd_mfma_tol_kernel<KC, false><<<static_cast<unsigned>(ceil_div(nw, NM)), 64 * NM, 0, s>>>(
+              p.gp, p.den, p.inv, Rq, Cc, start, U, rows, k, mu, tol, max_sweeps, upper, ps);
         DSANLS_LAUNCHED("prox_cd_mfma_tol_kernel");
         return DSANLS_OK;
       }
@@ -1313,7 +1338,17 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
   // passes with budgets 16, 16, 32, 64, ... sweeps; the last pass runs to
   // max_sweeps and lists nothing.  Each pass writes U, so a centre that
   // aliases U is copied first.
-  if (C == U) {
+  if (block) {
+    // q = r + mu c once for all passes: the passes read one panel instead of
+    // two per sweep and per KKT test (4% on the warm-start workload)
+    const int64_t n4 = rows * k / 4;
+    const unsigned qg = static_cast<unsigned>(std::min<int64_t>(ceil_div(n4, 256), 4096));
+    qsum_kernel<<<qg, 256, 0, s>>>(reinterpret_cast<const float4*>(R), reinterpret_cast<const float4*>(C), mu, n4,
+                                   reinterpret_cast<float4*>(tw->centre));
+    DSANLS_LAUNCHED("qsum_kernel");
+    Rq = tw->centre;
+    qc = false;
+  } else if (C == U) {
     DSANLS_HIP(hipMemcpyAsync(tw->centre, C, sizeof(float) * rows * k, hipMemcpyDeviceToDevice, s));
     C = tw->centre;
   }
