@@ -135,8 +135,8 @@ TRAFFIC = {
                           "sha256": "477d98a43fd4e6bed56ce09f6405edee400d8b73fe09c36268615e925d203e15",
                           "fetch_kib": 2419643.13, "write_kib": 120000.0},
     "sparse-500000x200000": {"files": ["nnls.hip", "common.hpp"],
-                             "sha256": "bfcff6f1909c5f94423a3b8535edc9fe20f5614acd3358d7651454c4631fe31c",
-                             "fetch_kib": 182233.41, "write_kib": 144056.13},
+                             "sha256": "66d0d6f9b6be75b969f6bc9eb0e6f4eb903b47627113d72f20e42aa21b47a0a4",
+                             "fetch_kib": 182695.75, "write_kib": 144235.05},
     "dense-50000x20000-bf16": {"files": ["gemm.hip", "common.hpp"],
                                "sha256": "477d98a43fd4e6bed56ce09f6405edee400d8b73fe09c36268615e925d203e15",
                                "fetch_kib": 20248669.94, "write_kib": 1120000.0},
