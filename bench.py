@@ -135,7 +135,7 @@ TRAFFIC = {
                           "sha256": "477d98a43fd4e6bed56ce09f6405edee400d8b73fe09c36268615e925d203e15",
                           "fetch_kib": 2419643.13, "write_kib": 120000.0},
     "sparse-500000x200000": {"files": ["nnls.hip", "common.hpp"],
-                             "sha256": "66d0d6f9b6be75b969f6bc9eb0e6f4eb903b47627113d72f20e42aa21b47a0a4",
+                             "sha256": "2635fe2dd953aac9dd633be9b88361725cdb69ed43d1a98dabd3a0d3a4eb3e53",
                              "fetch_kib": 182695.75, "write_kib": 144235.05},
     "dense-50000x20000-bf16": {"files": ["gemm.hip", "common.hpp"],
                                "sha256": "477d98a43fd4e6bed56ce09f6405edee400d8b73fe09c36268615e925d203e15",

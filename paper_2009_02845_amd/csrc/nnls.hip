@@ -576,7 +576,8 @@ __global__ __launch_bounds__(64 * NWV) void prox_cd_lds_kernel(const float* __re
 // layout in which the product leaves T.  A block's u and T move to one lane
 // per row, and the new u back, through a 64 x 16 LDS tile whose 4-float
 // chunks are XOR-swizzled by row.  Only for k % 4 == 0 and 16-byte aligned
-// U (rows enter and leave as float4s in the operand layout).
+// U and G (rows enter and leave as float4s in the operand layout; the
+// to-tolerance passes also need C, the warm start and R aligned).
 template <int KC>
 struct MfmaCd {
   static constexpr int NBK = (KC + 15) / 16;   // coordinate blocks
