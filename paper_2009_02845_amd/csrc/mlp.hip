@@ -59,10 +59,14 @@ P split(T* base, int d, int k, int h) {
 }
 
 // H[b, :] = ReLU(H[b, :] + sum_e val_e W1a[col_e, :] + b1), H holding
-// u_b W1u^T on entry.  One wave per batch row: the row's entries are read
-// 64 at a time (one per lane) and walked through shuffles, each lane adding
-// its hidden units h = lane + 64 q, so that a W1a row's four segments are
-// in flight together (hd <= 256; larger widths take one segment at a time).
+// u_b W1u^T on entry.  One wave per four batch rows (sketched rows hold a
+// few entries each, so a wave per row spent its time waiting on three
+// dependent loads): the four rows' H values and their entries (one range,
+// 64 at a time, one per lane, walked through shuffles) are read together,
+// each entry adding to the accumulators of its row, each lane holding the
+// hidden units h = lane + 64 q (hd <= 256; larger widths take one row and
+// one segment at a time).  Every sum runs in the row's entry order.
+constexpr int kL1Rows = 4;
 __global__ __launch_bounds__(256) void l1_sparse_kernel(const int32_t* __restrict__ rowptr,
                                                         const int32_t* __restrict__ cols,
                                                         const float* __restrict__ vals,
@@ -70,16 +74,23 @@ __global__ __launch_bounds__(256) void l1_sparse_kernel(const int32_t* __restric
                                                         const float* __restrict__ b1,
                                                         float* __restrict__ H, int64_t rows,
                                                         int hd) {
-  const int64_t r = blockIdx.x * 4ll + (threadIdx.x >> 6);
+  const int64_t r0 = (blockIdx.x * 4ll + (threadIdx.x >> 6)) * kL1Rows;
   const int lane = threadIdx.x & 63;
-  if (r >= rows) return;
-  const int beg = rowptr[r], end = rowptr[r + 1];
+  if (r0 >= rows) return;
+  const int nr = rows - r0 < kL1Rows ? static_cast<int>(rows - r0) : kL1Rows;
   if (hd <= 256) {
-    float acc[4];
+    // row boundaries; past the last row they repeat its end
+    int rp[kL1Rows + 1];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = lane + 64 * q < hd ? H[r * hd + lane + 64 * q] : 0.f;
-    for (int e0 = beg; e0 < end; e0 += 64) {
-      const int cnt = end - e0 < 64 ? end - e0 : 64;
+    for (int i = 0; i <= kL1Rows; ++i) rp[i] = rowptr[r0 + (i < nr ? i : nr)];
+    float acc[kL1Rows][4];
+#pragma unroll
+    for (int rr = 0; rr < kL1Rows; ++rr)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        acc[rr][q] = rr < nr && lane + 64 * q < hd ? H[(r0 + rr) * hd + lane + 64 * q] : 0.f;
+    for (int e0 = rp[0]; e0 < rp[kL1Rows]; e0 += 64) {
+      const int cnt = rp[kL1Rows] - e0 < 64 ? rp[kL1Rows] - e0 : 64;
       int c = 0;
       float v = 0.f;
       if (lane < cnt) {
@@ -87,22 +98,43 @@ __global__ __launch_bounds__(256) void l1_sparse_kernel(const int32_t* __restric
         v = vals[e0 + lane];
       }
       for (int i = 0; i < cnt; ++i) {
+        const int e = e0 + i;
         const float* w = W1a + static_cast<int64_t>(__shfl(c, i, 64)) * hd;
         const float vi = __shfl(v, i, 64);
+        float x[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (lane + 64 * q < hd) acc[q] += vi * w[lane + 64 * q];
+        for (int q = 0; q < 4; ++q) x[q] = lane + 64 * q < hd ? w[lane + 64 * q] : 0.f;
+        // the entry's row (wave-uniform)
+        const int rr = (e >= rp[1]) + (e >= rp[2]) + (e >= rp[3]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (rr == 0)
+            acc[0][q] += vi * x[q];
+          else if (rr == 1)
+            acc[1][q] += vi * x[q];
+          else if (rr == 2)
+            acc[2][q] += vi * x[q];
+          else
+            acc[3][q] += vi * x[q];
+        }
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (lane + 64 * q < hd) H[r * hd + lane + 64 * q] = relu(acc[q] + b1[lane + 64 * q]);
+    for (int rr = 0; rr < kL1Rows; ++rr)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (rr < nr && lane + 64 * q < hd)
+          H[(r0 + rr) * hd + lane + 64 * q] = relu(acc[rr][q] + b1[lane + 64 * q]);
     return;
   }
-  for (int h = lane; h < hd; h += 64) {
-    float acc = H[r * hd + h];
-    for (int e = beg; e < end; ++e) acc += vals[e] * W1a[static_cast<int64_t>(cols[e]) * hd + h];
-    H[r * hd + h] = relu(acc + b1[h]);
+  for (int rr = 0; rr < nr; ++rr) {
+    const int64_t r = r0 + rr;
+    const int beg = rowptr[r], end = rowptr[r + 1];
+    for (int h = lane; h < hd; h += 64) {
+      float acc = H[r * hd + h];
+      for (int e = beg; e < end; ++e) acc += vals[e] * W1a[static_cast<int64_t>(cols[e]) * hd + h];
+      H[r * hd + h] = relu(acc + b1[h]);
+    }
   }
 }
 
@@ -292,7 +324,7 @@ dsanls_status mlp_forward(int d, int k, int hd, const float* params, int64_t row
   // layer 1: H = U W1u^T (MFMA), then + sparse a W1a + b1, ReLU
   if ((st = launch_gemm_nt(U, k, p.W1u, k, w.H, hd, rows, hd, k, w.gemm_ws, w.gemm_ws_bytes, s)) != DSANLS_OK)
     return st;
-  l1_sparse_kernel<<<static_cast<unsigned>(ceil_div(rows, 4)), 256, 0, s>>>(a_rowptr, a_cols, a_vals, p.W1a,
+  l1_sparse_kernel<<<static_cast<unsigned>(ceil_div(rows, 4 * kL1Rows)), 256, 0, s>>>(a_rowptr, a_cols, a_vals, p.W1a,
                                                                             p.b1, w.H, rows, hd);
   DSANLS_LAUNCHED("l1_sparse_kernel");
   // layer 2: out = ReLU(U + H W2^T + b2)
