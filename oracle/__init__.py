@@ -8,7 +8,7 @@ and never imports it; both sides read their inputs from the seeded generators
 in paper_2009_02845_amd/synth.py, which hold none of the method's arithmetic.
 
 Modules:
-  philox  -- Philox4x32-10 and the sketch matrices drawn from it (Sec. 3.3)
+  philox  -- Philox4x32-10 and the sketch matrices drawn from it (Sec. 3.4)
   dsanls  -- sketch products, prox-CD / PGD updates, objective (Sec. 3.2-3.4)
   mlp     -- FP64 reference of the warm-start network (forward, backward, Adam)
 

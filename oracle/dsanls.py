@@ -8,9 +8,9 @@ product path never does.  It shares no code with the library.
 
 The method (Sec. 3, Alg. 2 with N = 1):
   for t = 0 .. T-1:
-    S^t  = random n x d sketch                      (Sec. 3.3)
+    S^t  = random n x d sketch                      (Sec. 3.4)
     A^t  = M S^t,  B^t = V^T S^t                    (eq. def_A_B)
-    U    <- one step on  min_{U>=0} ||A^t - U B^t||_F^2   (Sec. 3.4)
+    U    <- one step on  min_{U>=0} ||A^t - U B^t||_F^2   (Sec. 3.5)
     S'^t = random m x d' sketch
     A'^t = M^T S'^t,  B'^t = U^T S'^t               (U is the new U, Alg. 1)
     V    <- one step on  min_{V>=0} ||A'^t - V B'^t||_F^2
@@ -18,7 +18,7 @@ The step is either one projected-gradient step (eq. gradient_descent) or one
 sweep of proximal coordinate descent (eq. reg_sub, eq. entry_sol, Alg. 3).
 
 Readings where the paper is silent or inconsistent are documented inline:
-  * mu_t = alpha + beta * t with t counted from 0 (Sec. 5.1 setup).
+  * mu_t = alpha + beta * t with t counted from 0 (Sec. 5.2 setup).
   * The V-update uses the freshly updated U (Alg. 1), not U^t.
   * The PGD step size is eta_t = 1 / (2 (L_t + mu_t)) with L_t the largest
     absolute column sum of G = B B^T (a Gershgorin bound on its top
@@ -38,6 +38,8 @@ from . import philox
 SKETCH_GAUSSIAN = "gaussian"
 SKETCH_SUBSAMPLE = "subsample"
 SKETCH_IDENTITY = "identity"
+SKETCH_COUNT = "count"
+SKETCH_SRHT = "srht"
 SOLVER_PROX_CD = "prox_cd"
 SOLVER_PGD = "pgd"
 
@@ -60,12 +62,12 @@ class Config:
 
 
 def mu_t(cfg, t):
-    """Proximal weight mu_t = alpha + beta t (Sec. 5.1), growing without bound."""
+    """Proximal weight mu_t = alpha + beta t (Sec. 5.2), growing without bound."""
     return cfg.alpha + cfg.beta * t
 
 
 # ----------------------------------------------------------------------------
-# Sketch matrices (Sec. 3.3)
+# Sketch matrices (Sec. 3.4)
 # ----------------------------------------------------------------------------
 
 def sketch_matrix(kind, seed, t, side, n, d):
@@ -74,6 +76,10 @@ def sketch_matrix(kind, seed, t, side, n, d):
         return philox.gaussian_sketch(seed, t, side, n, d)
     if kind == SKETCH_SUBSAMPLE:
         return philox.subsample_sketch(seed, t, side, n, d)
+    if kind == SKETCH_COUNT:
+        return philox.count_sketch(seed, t, side, n, d)
+    if kind == SKETCH_SRHT:
+        return philox.srht_sketch(seed, t, side, n, d)
     if kind == SKETCH_IDENTITY:
         if d != n:
             raise ValueError("identity sketch needs d == n")
@@ -109,29 +115,41 @@ def gram_and_rhs(A, B):
 
 
 # ----------------------------------------------------------------------------
-# Subproblem solvers (Sec. 3.4)
+# Subproblem solvers (Sec. 3.5)
 # ----------------------------------------------------------------------------
 
 def prox_cd_sweep(U, C, G, R, mu, upper=None):
     """One sweep of proximal coordinate descent (Alg. 3), in place on U.
 
-    Column j, in order j = 0 .. k-1, is set to the exact minimiser over
-    U[:, j] >= 0 of ||A - U B||^2 + mu ||U - C||^2 with the other columns
-    fixed (eq. entry_sol):
-        T = mu C[:, j] + (A B_j^T) - sum_{l != j} (B_l B_j^T) U[:, l]
-        U[:, j] = max(T / (B_j B_j^T + mu), 0)
-    Columns l < j already hold their new values, columns l > j the old ones.
-    C is the proximal centre U^t.
+    Every row u of U has its own quadratic (eq. reg_sub, halved)
+        f(u) = 1/2 u Q u^T - q u^T,   Q = G + mu I,   q = r + mu c,
+    with c the row of the proximal centre C (= U^t).  The coordinates are
+    visited in order j = 0 .. k-1 and each is set to the exact minimiser of
+    f over u_j >= 0 with the other coordinates held at their current values
+    (eq. entry_sol): f restricted to u_j is a parabola of curvature Q_jj
+    whose slope at the current point is h_j = (u Q - q)_j, so the minimiser
+    is the Newton point u_j - h_j / Q_jj projected onto [0, upper].  The
+    slopes of all coordinates are kept in h for the whole block of rows: when
+    u_j moves by delta, h gains delta times row j of Q, so coordinate j + 1
+    sees the values already updated in this sweep (Gauss-Seidel order).
+
+    Where the paper leaves it open: a coordinate with Q_jj = G_jj + mu = 0
+    does not enter f at all (its column of B is zero and mu = 0); it is set
+    to 0, one of its minimisers.
     """
     k = U.shape[1]
+    Q = G + mu * np.eye(k)
+    h = U @ Q - (R + mu * C)
     for j in range(k):
-        T = mu * C[:, j] + R[:, j]
-        for l in range(k):
-            if l != j:
-                T = T - G[l, j] * U[:, l]
-        U[:, j] = np.maximum(T / (G[j, j] + mu), 0.0)
+        if Q[j, j] > 0:
+            new = np.maximum(U[:, j] - h[:, j] / Q[j, j], 0.0)
+        else:
+            new = np.zeros(U.shape[0])
         if upper is not None:
-            U[:, j] = np.minimum(U[:, j], upper)
+            new = np.minimum(new, upper)
+        delta = new - U[:, j]
+        U[:, j] = new
+        h += np.outer(delta, Q[j, :])
     return U
 
 
@@ -139,7 +157,7 @@ def pgd_step_size(G, mu):
     """eta_t = 1 / (2 (L + mu_t)), L = max_j sum_l |G_lj| >= lambda_max(G).
 
     The paper requires only a diminishing step with sum eta = inf and
-    sum eta^2 < inf (Theorem 1) and relates mu_t to 1/eta_t (Sec. 3.4.2);
+    sum eta^2 < inf (Theorem 1) and relates mu_t to 1/eta_t (Sec. 3.5.2);
     this choice keeps one step no longer than the inverse Lipschitz constant
     of the sketched gradient and decays like 1/(2 beta t).
     """
@@ -267,7 +285,7 @@ def frobenius(M):
 
 
 def relative_error(M, U, V):
-    """||M - U V^T||_F / ||M||_F (Sec. 5.1).
+    """||M - U V^T||_F / ||M||_F (Sec. 5.2).
 
     Dense M: the residual is formed entry by entry.  Sparse M: the residual
     norm is expanded as ||M||^2 - 2 sum_nnz M_ij <u_i, v_j> + <U^T U, V^T V>

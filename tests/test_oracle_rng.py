@@ -1,4 +1,4 @@
-"""Pins of the oracle's random sketches (Sec. 3.3, Assumption 1)."""
+"""Pins of the oracle's random sketches (Sec. 3.4, Assumption 1)."""
 import os
 
 import numpy as np
@@ -129,3 +129,84 @@ def test_bf16_rounding_matches_torch():
     ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(round_to_bf16(x), ref)
     assert round_to_bf16(1.00390625) == 1.0 and round_to_bf16(1.01171875) == 1.015625
+
+
+# ---- count sketch and SRHT (the further sketch kinds Sec. 3.4 names) ----
+
+def test_count_sketch_structure_and_brute_force_product():
+    n, d = 500, 37
+    h, s = philox.count_sketch_hash(3, 2, 1, n, d)
+    S = philox.count_sketch(3, 2, 1, n, d).toarray()
+    # exactly one nonzero of +-1 per row, at the hashed bucket
+    assert np.array_equal(np.count_nonzero(S, axis=1), np.ones(n))
+    assert np.array_equal(S[np.arange(n), h], s) and set(np.unique(s)) == {-1.0, 1.0}
+    # A = M S by adding each signed column of M into its bucket, one by one
+    g = np.random.default_rng(0)
+    M = g.standard_normal((6, n))
+    A = np.zeros((6, d))
+    for j in range(n):
+        A[:, h[j]] += s[j] * M[:, j]
+    assert np.allclose(O.sketch_products(M, np.zeros((n, 1)), philox.count_sketch(3, 2, 1, n, d))[0], A,
+                       rtol=0, atol=1e-12)
+
+
+def test_count_sketch_hash_words_and_uniformity():
+    # bucket = high word of x0 * d, sign = top bit of x1, from counter (0, j, side | 2 << 8, t)
+    seed, t, side, n, d = 12, 3, 0, 20000, 50
+    k0, k1 = philox.seed_key(seed)
+    x0, x1, _, _ = philox.philox4x32(0, 7, side | (2 << 8), t, k0, k1)
+    h, s = philox.count_sketch_hash(seed, t, side, n, d)
+    assert h[7] == (int(x0) * d) >> 32 and s[7] == (1.0 if int(x1) >> 31 == 0 else -1.0)
+    counts = np.bincount(h, minlength=d)
+    assert scipy.stats.chisquare(counts).pvalue > 1e-4
+    assert abs(s.sum()) < 4 * np.sqrt(n)
+    # a block of rows is the same rows of the whole sketch (global row index)
+    h2, s2 = philox.count_sketch_hash(seed, t, side, 300, d)
+    assert np.array_equal(h2, h[:300]) and np.array_equal(s2, s[:300])
+
+
+def test_hadamard_entries_match_sylvester_construction():
+    import scipy.linalg
+    for N in (1, 2, 8, 64):
+        a = np.arange(N)
+        assert np.array_equal(philox.hadamard_entries(a[:, None], a[None, :]), scipy.linalg.hadamard(N))
+
+
+def test_srht_full_width_is_orthogonal():
+    # n = d = N: P is a permutation, S = D H P / sqrt(N) and S S^T = I exactly
+    import scipy.linalg
+    N = 32
+    S = philox.srht_sketch(5, 1, 0, N, N)
+    assert np.allclose(S @ S.T, np.eye(N), rtol=0, atol=1e-12)
+    p = philox.subsample_indices(5, 1, 0, N, N, kind=philox.KIND_SRHT_SAMPLE)
+    assert np.array_equal(p, np.arange(N))
+    D = np.diag(philox.srht_signs(5, 1, 0, N))
+    assert np.allclose(S, D @ scipy.linalg.hadamard(N) / np.sqrt(N), rtol=0, atol=1e-15)
+    assert philox.srht_pad(1) == 1 and philox.srht_pad(5) == 8 and philox.srht_pad(64) == 64
+
+
+def test_srht_entries_from_signs_and_sampled_columns():
+    n, d = 13, 5
+    S = philox.srht_sketch(9, 4, 1, n, d)
+    s = philox.srht_signs(9, 4, 1, n)
+    p = philox.subsample_indices(9, 4, 1, 16, d, kind=philox.KIND_SRHT_SAMPLE)
+    for j in range(n):
+        for c in range(d):
+            par = bin(j & int(p[c])).count("1") & 1
+            assert S[j, c] == s[j] * (-1.0) ** par / np.sqrt(d)
+
+
+@pytest.mark.parametrize("kind", [O.SKETCH_COUNT, O.SKETCH_SRHT])
+def test_assumption1_expectation_identity_further_kinds(kind):
+    n, d, trials = 12, 4, 3000
+    acc = np.zeros((n, n))
+    acc2 = np.zeros((n, n))
+    for t in range(trials):
+        S = O.sketch_matrix(kind, 9, t, 0, n, d)
+        S = S.toarray() if hasattr(S, "toarray") else S
+        P = S @ S.T
+        acc += P
+        acc2 += P * P
+    mean = acc / trials
+    sd = np.sqrt(np.maximum(acc2 / trials - mean ** 2, 1e-30) / trials)
+    assert np.all(np.abs(mean - np.eye(n)) <= 5 * sd + 1e-12)

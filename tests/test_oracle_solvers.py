@@ -238,3 +238,55 @@ def test_sketched_gradient_is_unbiased(kind):
     sd = np.sqrt((acc2 / trials - mean ** 2) / trials)
     exact = 2 * (U @ V.T - M) @ V
     assert np.all(np.abs(mean - exact) <= 5 * sd)
+
+
+@pytest.mark.parametrize("kind", [O.SKETCH_COUNT, O.SKETCH_SRHT])
+def test_sketched_gradient_is_unbiased_further_kinds(kind):
+    g = np.random.default_rng(12)
+    m, n, k, d = 5, 13, 2, 4
+    M = g.random((m, n))
+    U = g.random((m, k))
+    V = g.random((n, k))
+    trials = 4000
+    acc = np.zeros((m, k))
+    acc2 = np.zeros((m, k))
+    for t in range(trials):
+        S = O.sketch_matrix(kind, 22, t, 0, n, d)
+        A, B = O.sketch_products(M, V, S)
+        G, R = O.gram_and_rhs(A, B)
+        gt = 2 * (U @ G - R)
+        acc += gt
+        acc2 += gt * gt
+    mean = acc / trials
+    sd = np.sqrt((acc2 / trials - mean ** 2) / trials)
+    exact = 2 * (U @ V.T - M) @ V
+    assert np.all(np.abs(mean - exact) <= 5 * sd)
+
+
+def test_prox_cd_zero_gram_column_without_mu_is_set_to_zero():
+    # a coordinate whose column of B is zero does not enter the objective
+    # when mu = 0; the sweep sets it to 0 (one of its minimisers) and the
+    # other coordinates still take their exact 1-D minimisers
+    A, B, U0 = _problem(rows=4, k=4, d=9, seed=13)
+    B[2] = 0.0
+    G, R = O.gram_and_rhs(A, B)
+    U = O.prox_cd_sweep(U0.copy(), U0.copy(), G, R, 0.0)
+    assert np.all(U[:, 2] == 0.0)
+    for i in range(4):
+        for j in (0, 1, 3):
+            state = np.concatenate([U[i, :j], U0[i, j:]])
+            state[2] = U[i, 2] if j > 2 else U0[i, 2]
+            num = R[i, j] - sum(G[l, j] * state[l] for l in range(4) if l != j)
+            assert abs(U[i, j] - max(num / G[j, j], 0.0)) < 1e-12
+
+
+def test_prox_cd_clip_and_nan_propagation():
+    A, B, U0 = _problem(rows=3, k=3, d=7, seed=14)
+    G, R = O.gram_and_rhs(A, B)
+    U = O.prox_cd_sweep(U0.copy(), U0.copy(), G, R, 0.5, upper=0.05)
+    assert np.all(U <= 0.05) and np.all(U >= 0)
+    # a NaN right-hand side is not projected to 0: it stays NaN in its row
+    Rn = R.copy()
+    Rn[1, 0] = np.nan
+    Un = O.prox_cd_sweep(U0.copy(), U0.copy(), G, Rn, 0.5)
+    assert np.isnan(Un[1, 0]) and np.all(np.isfinite(Un[[0, 2]]))
