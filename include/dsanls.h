@@ -5,12 +5,12 @@
  * Secure Distributed Nonnegative Matrix Factorization", arXiv 2009.02845) on
  * one GPU, for the problem min_{U>=0, V>=0} ||M - U V^T||_F (eq. problem):
  *
- *   update_U(t):  S^t (n x d) random sketch            (Sec. 3.3)
+ *   update_U(t):  S^t (n x d) random sketch            (Sec. 3.4)
  *                 A = M S^t,  B = V^T S^t              (eq. def_A_B)
  *                 G = B B^T,  R = A B^T                (eq. gradient_descent)
  *                 U <- prox-CD sweep(s) or PGD step    (Alg. 3 / eq. gradient_descent)
  *   update_V(t):  the same on M^T with S'^t (m x d') and the current U.
- *   objective:    ||M - U V^T||_F / ||M||_F            (Sec. 5.1)
+ *   objective:    ||M - U V^T||_F / ||M||_F            (Sec. 5.2)
  *
  * Conventions (all entry points):
  *   - Matrices are row-major.  "Device" pointers are HIP device memory owned
@@ -46,10 +46,12 @@ typedef enum {
   DSANLS_E_HIP = 4,          /* a HIP runtime call failed                      */
   DSANLS_E_NONFINITE = 5,    /* NaN/Inf found in M, U or V                     */
   DSANLS_E_STATE = 6,        /* call out of order (e.g. before init)           */
-  DSANLS_E_UNSUPPORTED = 7   /* valid request this build does not implement    */
+  DSANLS_E_UNSUPPORTED = 7,  /* valid request this build does not implement    */
+  DSANLS_E_INTERNAL = 8      /* a device-side step failed (reported later, see
+                                dsanls_objective)                              */
 } dsanls_status;
 
-/* Kind of random sketch (Sec. 3.3).  IDENTITY (S = I, needs d = n and
+/* Kind of random sketch (Sec. 3.4).  IDENTITY (S = I, needs d = n and
  * d' = m) turns the method into exact-product ANLS and is meant for tests. */
 typedef enum {
   DSANLS_SKETCH_GAUSSIAN = 0,   /* i.i.d. N(0, 1/d) entries                   */
@@ -57,7 +59,7 @@ typedef enum {
   DSANLS_SKETCH_IDENTITY = 2
 } dsanls_sketch;
 
-/* Subproblem solver (Sec. 3.4). */
+/* Subproblem solver (Sec. 3.5). */
 typedef enum {
   DSANLS_SOLVER_PROX_CD = 0,    /* proximal coordinate descent, Alg. 3        */
   DSANLS_SOLVER_PGD = 1         /* one projected-gradient step                */
@@ -76,17 +78,36 @@ typedef enum { DSANLS_DENSE = 0, DSANLS_CSR = 1 } dsanls_format;
  * Problem and method parameters.
  *   m, n       M is m x n; U is m x k and V is n x k (row-major, ld = k).
  *   d, d_prime sketch sizes of the U- and V-subproblems (eq. sketched_u/v).
- *   alpha,beta proximal weight mu_t = alpha + beta * t (Sec. 5.1), used by
+ *   alpha,beta proximal weight mu_t = alpha + beta * t (Sec. 5.2), used by
  *              prox-CD and, through the step 1/(2(L_t + mu_t)), by PGD.
  *   sweeps     prox-CD sweeps per update (the paper uses 1); 0 sweeps each
  *              row until its relative KKT residual <= tol or max_sweeps.
  *   clip_upper nonzero clips U, V to sqrt(2 ||M||_F) (eq. extra_con).
  *   seed       key of the counter-based generator: equal seeds give equal
- *              S^t on every node (Sec. 3.3).
+ *              S^t on every node (Sec. 3.4).
  *   warm_hidden hidden width of the warm-start network that
  *              dsanls_set_warm_start may install later (0: none); it sizes
  *              the workspace.  Warm starts apply to CSR input with a
  *              subsampling sketch in to-tolerance mode (sweeps = 0).
+ *   row_offset, col_offset, m_global, n_global
+ *              a node's share (Sec. 3.1, eq. u_block; Alg. 2): M is the block
+ *              [row_offset, row_offset + m) x [col_offset, col_offset + n)
+ *              of an m_global x n_global matrix (m_global = 0 or n_global = 0
+ *              mean m or n: the whole matrix, the one-node case).  U holds
+ *              the block's rows of U and V its rows of V.  The sketches are
+ *              drawn at global indices from the one shared seed (Sec. 3.4):
+ *              row j of S^t is row col_offset + j of the whole S^t, row i of
+ *              S'^t row row_offset + i of the whole S'^t, and subsampling
+ *              picks d of n_global (d' of m_global) indices with scale
+ *              sqrt(n_global / d) (sqrt(m_global / d')).  So a block that
+ *              spans all columns (col_offset = 0, n = n_global) computes node
+ *              r's U update of Alg. 2 exactly, its A = M_{I_r:} S^t being
+ *              those rows of the whole product; on a block of columns
+ *              update_U forms the node's partial products A_r = M S_{J_r} and
+ *              B_r = V^T S_{J_r}, whose sum over the column blocks is the
+ *              whole A and B (the all-reduce of Alg. 2, read back with
+ *              dsanls_debug_fetch).  Mirrored for update_V.  The identity
+ *              sketch and the warm start need the whole matrix.
  */
 typedef struct {
   int64_t m, n, k, d, d_prime;
@@ -101,6 +122,8 @@ typedef struct {
   uint64_t seed;
   int32_t warm_hidden;
   int32_t reserved;
+  int64_t row_offset, col_offset;
+  int64_t m_global, n_global;
 } dsanls_config;
 
 /*
@@ -149,10 +172,11 @@ dsanls_status dsanls_workspace_bytes(const dsanls_config* cfg, const dsanls_matr
  * ||M||_F^2, and return a context.  U (m x k) and V (n x k) are device
  * arrays holding U^0 >= 0 and V^0 >= 0; they are updated in place by the
  * update calls.  Synchronises the stream once (for ||M||_F^2).
- * Errors: INVALID_ARG (null pointers, alpha/beta < 0, mu_0 = 0 without
- * to-tol mode, bad enums), SHAPE (sizes, d > n for subsampling, d != n for
- * identity), WORKSPACE, UNSUPPORTED (Gaussian sketch on CSR input, BF16 on
- * CSR input, k > 128), HIP.
+ * Errors: INVALID_ARG (null pointers, alpha/beta < 0, alpha = mu_0 = 0
+ * outside to-tolerance mode, bad enums), SHAPE (sizes, a block outside the
+ * global matrix, d > n_global for subsampling, d != n for identity),
+ * WORKSPACE, UNSUPPORTED (Gaussian sketch on CSR input, BF16 on CSR input,
+ * k > 128), HIP.  NONFINITE: M, U or V holds NaN or Inf.
  */
 dsanls_status dsanls_init(const dsanls_config* cfg, const dsanls_matrix* M, float* U, float* V,
                           void* workspace, size_t workspace_bytes, void* hip_stream,
@@ -166,8 +190,14 @@ dsanls_status dsanls_sketch_update_U(dsanls_ctx* ctx, int64_t t);
  * (which is U^{t+1} after update_U(t), as in Alg. 1).  Asynchronous. */
 dsanls_status dsanls_sketch_update_V(dsanls_ctx* ctx, int64_t t);
 
-/* Relative error ||M - U V^T||_F / ||M||_F of the current U, V (Sec. 5.1).
- * Synchronises the stream.  Returns NONFINITE if the residual is NaN/Inf. */
+/* Relative error ||M - U V^T||_F / ||M||_F of the current U, V (Sec. 5.2).
+ * Synchronises the stream.  Returns NONFINITE if U, V or the residual hold
+ * NaN/Inf: the NNLS updates never project a non-finite value to 0 (a row
+ * whose right-hand side, centre, start or Gram is not finite comes out NaN
+ * in every entry), so a non-finite input of any update since init shows up
+ * here.  Returns INTERNAL if a subsample selection since the last objective
+ * failed (its results are then wrong).  The device flags behind both are
+ * cleared by each call. */
 dsanls_status dsanls_objective(dsanls_ctx* ctx, double* rel_err);
 
 dsanls_status dsanls_get_stats(dsanls_ctx* ctx, dsanls_stats* out);
@@ -238,13 +268,13 @@ const char* dsanls_last_error(void);
 dsanls_status dsanls_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out,
                                    int64_t count, void* hip_stream);
 
-/* Gaussian sketch S (n x d, N(0, 1/d), Sec. 3.3) written transposed: St is
+/* Gaussian sketch S (n x d, N(0, 1/d), Sec. 3.4) written transposed: St is
  * d x n with leading dimension ld_st >= n (device, FP32).  Row j of S uses
  * counters (q, j, side, t) with key = seed. */
 dsanls_status dsanls_gaussian_sketch_t(uint64_t seed, int64_t t, int32_t side, int64_t n,
                                        int64_t d, float* St, int64_t ld_st, void* hip_stream);
 
-/* Subsampling sketch (Sec. 3.3): the d indices of [0, n) with the smallest
+/* Subsampling sketch (Sec. 3.4): the d indices of [0, n) with the smallest
  * 64-bit Philox keys (ties by index), written ascending to idx[d] (device
  * int32).  workspace: device memory of dsanls_subsample_workspace_bytes(n). */
 size_t dsanls_subsample_workspace_bytes(int64_t n);
@@ -311,7 +341,10 @@ dsanls_status dsanls_mlp_train_step(int32_t d, int32_t k, int32_t hidden, float*
  * ||pg|| / ||r_i + mu c_i|| <= tol or max_sweeps.  sweeps_used (device
  * int32[rows]) may be NULL.  upper > 0 clips entries to upper.  1 <= k <= 128
  * (else UNSUPPORTED).  workspace: device memory of
- * dsanls_nnls_workspace_bytes(k) bytes for the prepared Gram. */
+ * dsanls_nnls_workspace_bytes(k) bytes for the prepared Gram.  A row whose
+ * right-hand side, centre, start or Gram entries are not finite is written
+ * as NaN in every entry (never projected to 0); the call is asynchronous and
+ * does not itself report it. */
 size_t dsanls_nnls_workspace_bytes(int32_t k);
 dsanls_status dsanls_nnls_prox_cd(const float* G, const float* R, const float* C, float* U,
                                   int64_t rows, int32_t k, float mu, int32_t sweeps, float tol,
@@ -320,7 +353,8 @@ dsanls_status dsanls_nnls_prox_cd(const float* G, const float* R, const float* C
 
 /* One projected-gradient step (eq. gradient_descent) with eta computed on
  * the device as 1 / (2 (max_j sum_l |G_lj| + mu)):
- * U <- max(U - 2 eta (U G - R), 0), in place.  Workspace as above. */
+ * U <- max(U - 2 eta (U G - R), 0), in place.  Workspace as above.  The
+ * projection keeps a NaN (and turns -Inf into NaN) instead of returning 0. */
 dsanls_status dsanls_pgd_step(const float* G, const float* R, float* U, int64_t rows, int32_t k,
                               float mu, float upper, void* workspace, size_t workspace_bytes,
                               void* hip_stream);

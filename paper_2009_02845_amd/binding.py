@@ -16,7 +16,7 @@ SOLVER = {"prox_cd": 0, "pgd": 1}
 PRECISION = {"fp32": 0, "bf16": 1}
 DENSE, CSR = 0, 1
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "SHAPE", 3: "WORKSPACE", 4: "HIP", 5: "NONFINITE",
-          6: "STATE", 7: "UNSUPPORTED"}
+          6: "STATE", 7: "UNSUPPORTED", 8: "INTERNAL"}
 
 c_int32, c_int64, c_uint64, c_double, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                               ctypes.c_double, ctypes.c_void_p)
@@ -28,7 +28,8 @@ class Config(ctypes.Structure):
                 ("d_prime", c_int64), ("sketch", c_int32), ("solver", c_int32),
                 ("precision", c_int32), ("sweeps", c_int32), ("max_sweeps", c_int32),
                 ("clip_upper", c_int32), ("tol", c_double), ("alpha", c_double),
-                ("beta", c_double), ("seed", c_uint64), ("warm_hidden", c_int32), ("reserved", c_int32)]
+                ("beta", c_double), ("seed", c_uint64), ("warm_hidden", c_int32), ("reserved", c_int32),
+                ("row_offset", c_int64), ("col_offset", c_int64), ("m_global", c_int64), ("n_global", c_int64)]
 
 
 class Matrix(ctypes.Structure):
@@ -140,11 +141,12 @@ def _stream(stream=None):
 
 def make_config(m, n, k, d, d_prime=None, sketch="gaussian", solver="prox_cd", precision="fp32",
                 sweeps=1, max_sweeps=100, tol=1e-4, alpha=1.0, beta=1.0, clip_upper=False, seed=0,
-                warm_hidden=0):
+                warm_hidden=0, row_offset=0, col_offset=0, m_global=0, n_global=0):
     return Config(m=m, n=n, k=k, d=d, d_prime=d if d_prime is None else d_prime,
                   sketch=SKETCH[sketch], solver=SOLVER[solver], precision=PRECISION[precision],
                   sweeps=sweeps, max_sweeps=max_sweeps, clip_upper=int(bool(clip_upper)), tol=tol,
-                  alpha=alpha, beta=beta, seed=seed, warm_hidden=warm_hidden)
+                  alpha=alpha, beta=beta, seed=seed, warm_hidden=warm_hidden, row_offset=row_offset,
+                  col_offset=col_offset, m_global=m_global, n_global=n_global)
 
 
 def dense_matrix(M, Mt=None):

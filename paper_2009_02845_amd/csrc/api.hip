@@ -53,7 +53,8 @@ struct Layout {
   size_t gemm_ws_bytes = 0;
   void* nnls_ws = nullptr;
   size_t nnls_ws_bytes = 0;
-  int32_t* idx[2] = {nullptr, nullptr};    // per side: subsample indices (d) ...
+  int32_t* idx[2] = {nullptr, nullptr};    // per side: subsample indices (d, global) ...
+  int32_t* idx_win[2] = {nullptr, nullptr};  // ... the same seen by this block (-1: outside), shares only
   int32_t* slot[2] = {nullptr, nullptr};   // ... and slot map (lng); one set per side so that the
                                            // next side's selection can run ahead on the side stream
   // sketched rows of A (CSR input, subsampling): counts, offsets, entries
@@ -86,6 +87,16 @@ struct Layout {
 
 bool dense(const dsanls_matrix* M) { return M->format == DSANLS_DENSE; }
 
+// The whole matrix of which this context holds the block: m_global x
+// n_global (0 means the block's own size), the block starting at
+// (row_offset, col_offset).  Side 0's long dimension is the columns, side
+// 1's the rows.
+int64_t m_glob(const dsanls_config& c) { return c.m_global > 0 ? c.m_global : c.m; }
+int64_t n_glob(const dsanls_config& c) { return c.n_global > 0 ? c.n_global : c.n; }
+bool is_share(const dsanls_config& c) {
+  return c.row_offset != 0 || c.col_offset != 0 || m_glob(c) != c.m || n_glob(c) != c.n;
+}
+
 Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
   Layout L;
   size_t off = 0;
@@ -96,6 +107,7 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
   };
   const int64_t m = c.m, n = c.n, k = c.k;
   const int64_t lngmax = std::max(m, n), rowsmax = std::max(m, n), dmax = std::max(c.d, c.d_prime);
+  const int64_t lngglob = std::max(m_glob(c), n_glob(c));
   const bool is_dense = dense(&M);
   const bool gauss = c.sketch == DSANLS_SKETCH_GAUSSIAN;
   const bool sub = c.sketch == DSANLS_SKETCH_SUBSAMPLE;
@@ -138,10 +150,12 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
   L.nnls_ws_bytes = align_up(nnls_ws_bytes(static_cast<int>(std::min<int64_t>(k, kMaxRank))), 256);
   L.nnls_ws = take(L.nnls_ws_bytes);
   if (sub) {
-    L.sub_ws_bytes = subsample_ws_bytes(lngmax);
+    // the selection runs over the whole long dimension (global indices)
+    L.sub_ws_bytes = subsample_ws_bytes(lngglob);
     for (int sd = 0; sd < 2; ++sd) {
       L.idx[sd] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * dmax));
-      L.slot[sd] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * lngmax));
+      if (is_share(c)) L.idx_win[sd] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * dmax));
+      L.slot[sd] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * lngglob));
       L.sub_ws[sd] = take(L.sub_ws_bytes);
     }
   }
@@ -212,15 +226,23 @@ dsanls_status validate(const dsanls_config* c, const dsanls_matrix* M) {
   if (c->sketch < 0 || c->sketch > 2) return fail(DSANLS_E_INVALID_ARG, "bad sketch kind");
   if (c->solver < 0 || c->solver > 1) return fail(DSANLS_E_INVALID_ARG, "bad solver");
   if (c->precision < 0 || c->precision > 1) return fail(DSANLS_E_INVALID_ARG, "bad precision");
-  if (c->sketch == DSANLS_SKETCH_SUBSAMPLE && (c->d > c->n || c->d_prime > c->m))
-    return fail(DSANLS_E_SHAPE, "subsampling needs d <= n and d_prime <= m");
+  if (c->row_offset < 0 || c->col_offset < 0 || c->m_global < 0 || c->n_global < 0)
+    return fail(DSANLS_E_SHAPE, "row_offset, col_offset, m_global and n_global must be >= 0");
+  if (c->row_offset + c->m > m_glob(*c) || c->col_offset + c->n > n_glob(*c))
+    return fail(DSANLS_E_SHAPE, "the block [row_offset, +m) x [col_offset, +n) must lie inside m_global x n_global");
+  if (m_glob(*c) > INT32_MAX || n_glob(*c) > INT32_MAX) return fail(DSANLS_E_SHAPE, "m_global and n_global must fit int32");
+  if (c->sketch == DSANLS_SKETCH_SUBSAMPLE && (c->d > n_glob(*c) || c->d_prime > m_glob(*c)))
+    return fail(DSANLS_E_SHAPE, "subsampling needs d <= n_global and d_prime <= m_global");
   if (c->sketch == DSANLS_SKETCH_IDENTITY && (c->d != c->n || c->d_prime != c->m))
     return fail(DSANLS_E_SHAPE, "identity sketch needs d == n and d_prime == m");
+  if (c->sketch == DSANLS_SKETCH_IDENTITY && is_share(*c))
+    return fail(DSANLS_E_UNSUPPORTED, "identity sketch applies to the whole matrix only");
   if (c->sketch == DSANLS_SKETCH_GAUSSIAN && std::max(c->d, c->d_prime) > 4 * 65535)
     return fail(DSANLS_E_SHAPE, "Gaussian sketch supports d <= 262140");
   if (c->warm_hidden < 0 || c->warm_hidden > 4096) return fail(DSANLS_E_INVALID_ARG, "warm_hidden out of range");
   if (c->warm_hidden > 0 && (c->d != c->d_prime || M->format != DSANLS_CSR || c->sketch != DSANLS_SKETCH_SUBSAMPLE))
     return fail(DSANLS_E_UNSUPPORTED, "warm start needs CSR input, a subsampling sketch and d == d_prime");
+  if (c->warm_hidden > 0 && is_share(*c)) return fail(DSANLS_E_UNSUPPORTED, "warm start applies to the whole matrix only");
   if (!(c->alpha >= 0.0) || !(c->beta >= 0.0) || !std::isfinite(c->alpha) || !std::isfinite(c->beta))
     return fail(DSANLS_E_INVALID_ARG, "alpha and beta must be finite and >= 0");
   if (c->solver == DSANLS_SOLVER_PROX_CD) {
@@ -228,6 +250,12 @@ dsanls_status validate(const dsanls_config* c, const dsanls_matrix* M) {
     if (c->sweeps == 0 && (c->max_sweeps < 1 || !(c->tol >= 0.0)))
       return fail(DSANLS_E_INVALID_ARG, "to-tolerance mode needs max_sweeps >= 1 and tol >= 0");
   }
+  // mu_0 = alpha must be positive for the one-step updates: a coordinate
+  // with G_jj = 0 would have no defined step (fixed sweeps) and the PGD step
+  // 1 / (2 (L + mu)) no bound; only the exact (to-tolerance) solve, which
+  // then solves plain NNLS, may run with alpha = 0
+  if (!(c->alpha > 0.0) && !(c->solver == DSANLS_SOLVER_PROX_CD && c->sweeps == 0))
+    return fail(DSANLS_E_INVALID_ARG, "alpha (mu_0) must be > 0 outside to-tolerance mode");
   if (M->format == DSANLS_DENSE) {
     if (!M->dense || M->ld < c->n) return fail(DSANLS_E_INVALID_ARG, "dense M: NULL or ld < n");
     if (M->dense_t && M->ld_t < c->m) return fail(DSANLS_E_INVALID_ARG, "dense M^T: ld_t < m");
@@ -359,11 +387,25 @@ dsanls_status mark(dsanls_ctx* ctx, int phase) {
   return DSANLS_OK;
 }
 
+// Device flag words: err[0] non-finite values met by the checks of init and
+// objective, err[1] and err[2] a subsample selection that failed (its
+// boundary bucket over capacity) on the caller's stream and on the side
+// stream.  read_scalars copies the first three back; objective clears them
+// after reading, so each objective reports what happened since the last.
 dsanls_status read_scalars(dsanls_ctx* ctx, float* host_red, int n_red, int* host_err) {
   hipStream_t s = ctx->stream;
   DSANLS_HIP(hipMemcpyAsync(host_red, ctx->L.red, sizeof(float) * n_red, hipMemcpyDeviceToHost, s));
-  DSANLS_HIP(hipMemcpyAsync(host_err, ctx->L.err, sizeof(int), hipMemcpyDeviceToHost, s));
+  DSANLS_HIP(hipMemcpyAsync(host_err, ctx->L.err, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
   DSANLS_HIP(hipStreamSynchronize(s));
+  return DSANLS_OK;
+}
+
+// Status of the flag words read by read_scalars, then cleared on the stream.
+dsanls_status report_flags(dsanls_ctx* ctx, const int* err, const char* where) {
+  DSANLS_HIP(hipMemsetAsync(ctx->L.err, 0, 3 * sizeof(int), ctx->stream));
+  if (err[0]) return fail(DSANLS_E_NONFINITE, std::string(where) + ": non-finite values in U, V or the residual");
+  if (err[1] | err[2])
+    return fail(DSANLS_E_INTERNAL, std::string(where) + ": a subsample selection failed (boundary bucket over capacity)");
   return DSANLS_OK;
 }
 
@@ -389,6 +431,11 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
   const uint32_t tt = static_cast<uint32_t>(t);
   const double mu = c.alpha + c.beta * static_cast<double>(t);
   const int64_t lds = r4(lng), lda = r4(d), ldb = r4(d), ldw = r4(lng);
+  // the long dimension of the whole matrix and where this block starts in
+  // it: rows of the sketch (and the subsample) are drawn at global indices
+  const int64_t lng_g = side == 0 ? n_glob(c) : m_glob(c);
+  const int64_t off = side == 0 ? c.col_offset : c.row_offset;
+  const bool share = is_share(c);
   dsanls_status st = DSANLS_OK;
 #define CHECK(x)                      \
   do {                                \
@@ -410,7 +457,8 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
       CHECK(mark(ctx, kPhSketch));
       for (int sd = both ? 0 : 1; sd < 2; ++sd) {
         const int64_t lng_s = sd == 0 ? c.n : c.m, d_s = sd == 0 ? c.d : c.d_prime;
-        CHECK(launch_gaussian_sketch_t(c.seed, tt, sd, lng_s, d_s, L.St[sd], r4(lng_s),
+        const int64_t off_s = sd == 0 ? c.col_offset : c.row_offset;
+        CHECK(launch_gaussian_sketch_t(c.seed, tt, sd, off_s, lng_s, d_s, L.St[sd], r4(lng_s),
                                        bf16 ? L.Sb[sd] : nullptr, r32(lng_s), s));
       }
       CHECK(mark(ctx, kPhSketch));
@@ -442,20 +490,23 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     if (ctx->ahead_pending[side]) DSANLS_HIP(hipStreamWaitEvent(s, ctx->ev_sel[side], 0));
     ctx->ahead_pending[side] = false;
     if (ctx->sel_t[side] != t)
-      CHECK(launch_subsample(c.seed, tt, side, lng, d, L.idx[side], is_dense ? nullptr : L.slot[side],
-                             L.sub_ws[side], L.sub_ws_bytes, L.err, s));
+      CHECK(launch_subsample(c.seed, tt, side, lng_g, d, L.idx[side], is_dense ? nullptr : L.slot[side],
+                             L.sub_ws[side], L.sub_ws_bytes, L.err + 1, s, off, lng, L.idx_win[side]));
     else
       gathered = ctx->gathered_ahead[side];
     ctx->sel_t[side] = -1;
     CHECK(mark(ctx, kPhSketch));
-    const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
+    // d of the lng_g columns, each scaled by sqrt(lng_g / d); a block sees
+    // the sampled columns inside it (idx_win, -1 elsewhere)
+    const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng_g) / static_cast<double>(d)));
+    const int32_t* idx_b = share ? L.idx_win[side] : L.idx[side];
     if (is_dense) {
       CHECK(mark(ctx, kPhProduct));
-      CHECK(launch_gather_cols(X, ldx, L.idx[side], rows, d, scale, L.A[side], lda, s));
+      CHECK(launch_gather_cols(X, ldx, idx_b, rows, d, scale, L.A[side], lda, s));
       CHECK(mark(ctx, kPhProduct));
     }
     CHECK(mark(ctx, kPhSmall));
-    CHECK(launch_gather_rows_t(Wother, k, L.idx[side], d, scale, L.B, ldb, s));
+    CHECK(launch_gather_rows_t(Wother, k, idx_b, d, scale, L.B, ldb, s));
   } else {
     // identity: A = X, B = W^T
     CHECK(mark(ctx, kPhSmall));
@@ -482,21 +533,24 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
       const int64_t* xt_rowptr = side == 0 ? ctx->mat.t_rowptr : ctx->mat.rowptr;
       const int32_t* xt_colidx = side == 0 ? ctx->mat.t_colidx : ctx->mat.colidx;
       const float* xt_vals = side == 0 ? ctx->mat.t_vals : ctx->mat.vals;
-      const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
+      const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng_g) / static_cast<double>(d)));
+      const int32_t* idx_b = share ? L.idx_win[side] : L.idx[side];
       if (!gathered)
-        CHECK(launch_sampled_rows(xt_rowptr, xt_colidx, xt_vals, rows, L.idx[side], d, scale, L.a_cnt[side],
+        CHECK(launch_sampled_rows(xt_rowptr, xt_colidx, xt_vals, rows, idx_b, d, scale, L.a_cnt[side],
                                   L.a_pos[side], L.scan_ws[side], L.a_rowptr[side], L.a_cols[side],
                                   L.a_vals[side], L.long_rows[side], L.nlong[side], s));
-      CHECK(launch_a_rhs(L.a_rowptr[side], L.a_cols[side], L.a_vals[side], rows, L.idx[side], Wother, k, scale,
+      CHECK(launch_a_rhs(L.a_rowptr[side], L.a_cols[side], L.a_vals[side], rows, idx_b, Wother, k, scale,
                          L.long_rows[side], L.nlong[side], L.R,
                          s));
       ctx->rows_kept = rows;
     } else {
       // the CSR stream: every nnz of X, the sampled ones (or all, identity)
       // folded into R
-      const float scale = sub ? static_cast<float>(static_cast<double>(lng) / static_cast<double>(d)) : 1.0f;
-      CHECK(launch_csr_rhs_seg(rowptr, colidx, vals, L.seg[side], sub ? L.slot[side] : nullptr, Wother, k, scale,
-                               L.R, L.seg_partials, s));
+      // (the slot map covers the whole long dimension: this block's columns
+      // start at off)
+      const float scale = sub ? static_cast<float>(static_cast<double>(lng_g) / static_cast<double>(d)) : 1.0f;
+      CHECK(launch_csr_rhs_seg(rowptr, colidx, vals, L.seg[side], sub ? L.slot[side] + off : nullptr, Wother, k,
+                               scale, L.R, L.seg_partials, s));
     }
     CHECK(mark(ctx, kPhProduct));
   }
@@ -507,8 +561,8 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
   if (!is_dense && c.sketch == DSANLS_SKETCH_SUBSAMPLE && (warm || ctx->keep_rows) && ctx->rows_kept < 0) {
     // sketched rows from the CSR stream (d too large for the gather)
     CHECK(mark(ctx, kPhProduct));
-    const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng) / static_cast<double>(d)));
-    CHECK(launch_sketched_rows(rowptr, colidx, vals, rows, L.seg[side], L.slot[side], scale, L.a_cnt[side],
+    const float scale = static_cast<float>(std::sqrt(static_cast<double>(lng_g) / static_cast<double>(d)));
+    CHECK(launch_sketched_rows(rowptr, colidx, vals, rows, L.seg[side], L.slot[side] + off, scale, L.a_cnt[side],
                                L.a_pos[side], L.scan_ws[side], L.a_rowptr[side], L.a_cols[side], L.a_vals[side],
                                s));
     CHECK(mark(ctx, kPhProduct));
@@ -537,19 +591,21 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     const int64_t nt = side == 0 ? t : t + 1;
     if (nt <= UINT32_MAX) {
       const int64_t nlng = ns == 0 ? c.n : c.m, nd = ns == 0 ? c.d : c.d_prime;
+      const int64_t nlng_g = ns == 0 ? n_glob(c) : m_glob(c), noff = ns == 0 ? c.col_offset : c.row_offset;
       if (ctx->ahead_pending[ns]) DSANLS_HIP(hipStreamWaitEvent(ctx->side_stream, ctx->ev_sel[ns], 0));
       if (ctx->used_recorded[ns]) DSANLS_HIP(hipStreamWaitEvent(ctx->side_stream, ctx->ev_used[ns], 0));
-      dsanls_status ast = launch_subsample(c.seed, static_cast<uint32_t>(nt), ns, nlng, nd, L.idx[ns],
+      dsanls_status ast = launch_subsample(c.seed, static_cast<uint32_t>(nt), ns, nlng_g, nd, L.idx[ns],
                                            is_dense ? nullptr : L.slot[ns], L.sub_ws[ns], L.sub_ws_bytes,
-                                           L.err, ctx->side_stream);
+                                           L.err + 2, ctx->side_stream, noff, nlng, L.idx_win[ns]);
       // the sketched rows of that side need only M and the indices
       const bool gather = !is_dense && nd <= kGatherMaxD && ctx->mat.nnz < (int64_t{1} << 31);
       if (ast == DSANLS_OK && gather) {
         const int64_t nrows = ns == 0 ? c.m : c.n;
-        const float nscale = static_cast<float>(std::sqrt(static_cast<double>(nlng) / static_cast<double>(nd)));
+        const float nscale = static_cast<float>(std::sqrt(static_cast<double>(nlng_g) / static_cast<double>(nd)));
         ast = launch_sampled_rows(ns == 0 ? ctx->mat.t_rowptr : ctx->mat.rowptr,
                                   ns == 0 ? ctx->mat.t_colidx : ctx->mat.colidx,
-                                  ns == 0 ? ctx->mat.t_vals : ctx->mat.vals, nrows, L.idx[ns], nd, nscale,
+                                  ns == 0 ? ctx->mat.t_vals : ctx->mat.vals, nrows,
+                                  share ? L.idx_win[ns] : L.idx[ns], nd, nscale,
                                   L.a_cnt[ns], L.a_pos[ns], L.scan_ws[ns], L.a_rowptr[ns], L.a_cols[ns],
                                   L.a_vals[ns], L.long_rows[ns], L.nlong[ns], ctx->side_stream);
       }
@@ -591,6 +647,7 @@ const char* dsanls_status_string(dsanls_status s) {
     case DSANLS_E_NONFINITE: return "non-finite value";
     case DSANLS_E_STATE: return "call out of order";
     case DSANLS_E_UNSUPPORTED: return "unsupported";
+    case DSANLS_E_INTERNAL: return "internal failure";
   }
   return "unknown status";
 }
@@ -687,9 +744,9 @@ dsanls_status dsanls_init(const dsanls_config* cfg, const dsanls_matrix* M, floa
   if ((st = launch_check_finite(U, c.m * c.k, L.err, s)) != DSANLS_OK) return bail(st);
   if ((st = launch_check_finite(V, c.n * c.k, L.err, s)) != DSANLS_OK) return bail(st);
   float red[2];
-  int err = 0;
-  if ((st = read_scalars(ctx, red, 2, &err)) != DSANLS_OK) return bail(st);
-  if (err) return bail(fail(DSANLS_E_NONFINITE, "init: M, U or V holds NaN/Inf"));
+  int err[3] = {0, 0, 0};
+  if ((st = read_scalars(ctx, red, 2, err)) != DSANLS_OK) return bail(st);
+  if (err[0]) return bail(fail(DSANLS_E_NONFINITE, "init: M, U or V holds NaN/Inf"));
   ctx->normM2 = static_cast<double>(red[0]) + static_cast<double>(red[1]);
   ctx->upper = c.clip_upper ? static_cast<float>(std::sqrt(2.0 * std::sqrt(ctx->normM2))) : 0.0f;
   *out = ctx;
@@ -715,6 +772,9 @@ dsanls_status dsanls_objective(dsanls_ctx* ctx, double* rel_err) {
   const Layout& L = ctx->L;
   hipStream_t s = ctx->stream;
   dsanls_status st;
+  // the side stream's selections report into err[2]: they end before it is read
+  for (int sd = 0; sd < 2; ++sd)
+    if (ctx->ahead_pending[sd]) DSANLS_HIP(hipStreamWaitEvent(s, ctx->ev_sel[sd], 0));
   if ((st = launch_check_finite(ctx->U, c.m * c.k, L.err, s)) != DSANLS_OK) return st;
   if ((st = launch_check_finite(ctx->V, c.n * c.k, L.err, s)) != DSANLS_OK) return st;
   double resid = 0.0;
@@ -724,9 +784,9 @@ dsanls_status dsanls_objective(dsanls_ctx* ctx, double* rel_err) {
     if ((st = launch_combine_partials(L.partials, residual_partials(c.m, c.n), 2, L.red, L.err, s)) != DSANLS_OK)
       return st;
     float red[2];
-    int err = 0;
-    if ((st = read_scalars(ctx, red, 2, &err)) != DSANLS_OK) return st;
-    if (err) return fail(DSANLS_E_NONFINITE, "objective: non-finite values in U, V or the residual");
+    int err[3] = {0, 0, 0};
+    if ((st = read_scalars(ctx, red, 2, err)) != DSANLS_OK) return st;
+    if ((st = report_flags(ctx, err, "objective")) != DSANLS_OK) return st;
     resid = static_cast<double>(red[0]) + static_cast<double>(red[1]);
   } else {
     // ||M||^2 - 2 sum_nnz M_ij <u_i, v_j> + <U^T U, V^T V>
@@ -744,9 +804,9 @@ dsanls_status dsanls_objective(dsanls_ctx* ctx, double* rel_err) {
     if ((st = launch_gram(L.Wt, r4(c.n), k, c.n, GV, s)) != DSANLS_OK) return st;
     if ((st = launch_frob_dot(GU, GV, k * k, L.red + 4, s)) != DSANLS_OK) return st;
     float red[6];
-    int err = 0;
-    if ((st = read_scalars(ctx, red, 6, &err)) != DSANLS_OK) return st;
-    if (err) return fail(DSANLS_E_NONFINITE, "objective: non-finite values in U, V or the residual");
+    int err[3] = {0, 0, 0};
+    if ((st = read_scalars(ctx, red, 6, err)) != DSANLS_OK) return st;
+    if ((st = report_flags(ctx, err, "objective")) != DSANLS_OK) return st;
     const double cross = static_cast<double>(red[0]) + static_cast<double>(red[1]);
     const double gg = static_cast<double>(red[4]) + static_cast<double>(red[5]);
     resid = std::max(0.0, ctx->normM2 - 2.0 * cross + gg);

@@ -38,15 +38,20 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 constexpr int kNumXcd = 8;
 
 // ---------------------------------------------------------------- philox.hip
-dsanls_status launch_gaussian_sketch_t(uint64_t seed, uint32_t t, int side, int64_t n, int64_t d,
+// S^T (d x n) of rows j0 .. j0 + n - 1 of the Gaussian sketch (and its
+// BF16 rounding when St_bf16 is not null).
+dsanls_status launch_gaussian_sketch_t(uint64_t seed, uint32_t t, int side, int64_t j0, int64_t n, int64_t d,
                                        float* St, int64_t ld, __hip_bfloat16* St_bf16, int64_t ld_bf16,
                                        hipStream_t s);
 // Workspace layout of the subsample selection.
 size_t subsample_ws_bytes(int64_t n);
 // idx[d] ascending; slot (may be null) gets slot[j] = column of index j or -1.
+// idx_win (may be null): idx[c] - win_off where that lies in [0, win_len),
+// else -1 (the sampled columns seen by a block of the long dimension).
 dsanls_status launch_subsample(uint64_t seed, uint32_t t, int side, int64_t n, int64_t d,
                                int32_t* idx, int32_t* slot, void* ws, size_t ws_bytes,
-                               int* err_flag, hipStream_t s);
+                               int* err_flag, hipStream_t s, int64_t win_off = 0, int64_t win_len = 0,
+                               int32_t* idx_win = nullptr);
 
 // ---------------------------------------------------------------- gemm.hip
 // C[rows x cols] = X[rows x K] * Y[cols x K]^T, FP32 MFMA.
@@ -96,10 +101,10 @@ dsanls_status launch_combine_partials(const float* partials, int64_t npart, int6
 // out[0..1] = compensated sum of X[i] * Y[i] over count entries (one block).
 dsanls_status launch_frob_dot(const float* X, const float* Y, int64_t count, float* out,
                               hipStream_t s);
-// A[i, c] = scale * X[i, idx[c]] (rows x d), gathered columns.
+// A[i, c] = scale * X[i, idx[c]] (rows x d), gathered columns (0 where idx[c] < 0).
 dsanls_status launch_gather_cols(const float* X, int64_t ldx, const int32_t* idx, int64_t rows,
                                  int64_t d, float scale, float* A, int64_t lda, hipStream_t s);
-// B[l, c] = scale * W[idx[c], l] (k x d) from W (rows x k).
+// B[l, c] = scale * W[idx[c], l] (k x d) from W (rows x k); 0 where idx[c] < 0.
 dsanls_status launch_gather_rows_t(const float* W, int64_t k, const int32_t* idx, int64_t d,
                                    float scale, float* B, int64_t ldb, hipStream_t s);
 dsanls_status launch_check_finite(const float* X, int64_t count, int* err_flag, hipStream_t s);

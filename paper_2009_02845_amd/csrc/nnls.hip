@@ -1,4 +1,4 @@
-// Batched row-wise NNLS updates of the sketched subproblem (Sec. 3.4).
+// Batched row-wise NNLS updates of the sketched subproblem (Sec. 3.5).
 //
 // Every row i of U solves its own k-dimensional problem (the subproblem is
 // row-independent, eq. u_block), all sharing G = B B^T.  Layout: one lane
@@ -336,8 +336,31 @@ __device__ __forceinline__ void q_read(const QPanel<SW>& qp, float mu, int c0, i
     x[e] = qp.r[SW * lane + (e ^ f)];
     y[e] = with_c ? qp.c[SW * lane + (e ^ f)] : 0.f;
   }
+  if (c0 + SW > k) {
+    // the last panel of a rank that is not a multiple of SW: its columns
+    // past k hold the corner's value (see q_issue); they read as exact
+    // zeros, so that the padding coordinates see finite values
+#pragma unroll
+    for (int e = 0; e < SW; ++e)
+      if (c0 + e >= k) x[e] = y[e] = 0.f;
+  }
 #pragma unroll
   for (int e = 0; e < SW; ++e) q[e] = x[e] + mu * y[e];
+}
+
+// Non-finite guard of a row: g = fma(x, 0, g) stays +0 while every x folded
+// in is finite and becomes NaN as soon as one is NaN or +-Inf (x * 0 is NaN
+// for those).  The projection max(x, 0) would map a NaN to 0; instead a row
+// whose guard is NaN is written out as NaN in every entry, so a non-finite
+// right-hand side, centre, start or Gram never turns into a silent zero.
+__device__ __forceinline__ void guard(float& g, float x) { g = __builtin_fmaf(x, 0.f, g); }
+
+// A lane's row with a NaN guard becomes NaN in every entry.
+template <int KC, int W>
+__device__ __forceinline__ void poison_row(RowBlocks<KC, W>& u, float gd) {
+  const bool bad = gd != gd;
+#pragma unroll
+  for (int l = 0; l < RowBlocks<KC, W>::NB * W; ++l) u.b[l / W][l % W] = bad ? __builtin_nanf("") : u.b[l / W][l % W];
 }
 
 // u <- this lane's row of P on the lanes where take holds.  A first load
@@ -447,7 +470,7 @@ __device__ __forceinline__ void sweep(QPanel<SW>& qp, const float* __restrict__ 
                                       const float* __restrict__ inv, const float* __restrict__ R,
                                       const float* __restrict__ C, int64_t row0, int nrows, int k,
                                       float mu, float ub, bool act, bool c_is_u,
-                                      RowBlocks<KC, W>& u, const int32_t* rmap = nullptr) {
+                                      RowBlocks<KC, W>& u, float& gd, const int32_t* rmap = nullptr) {
   // c_is_u: the centre is the iterate this sweep starts from, so c_j is
   // u_j as it stands when coordinate j is reached, and C is not read
   constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
@@ -469,7 +492,9 @@ __device__ __forceinline__ void sweep(QPanel<SW>& qp, const float* __restrict__ 
           const int j = jb * W + je;
           const float q = c_is_u ? qb[b * W + je] + mu * u.b[jb][je] : qb[b * W + je];
           const float t = GLDS ? dot_row_lds<KC, W>(gp + j * KC, u) : dot_row<KC, W>(gp + j * KC, u);
-          const float v = fminf(fmaxf((q - t) * inv[j], 0.f), ub);
+          const float x = (q - t) * inv[j];
+          guard(gd, x);
+          const float v = fminf(fmaxf(x, 0.f), ub);
           if (act) u.b[jb][je] = v;
         }
       }
@@ -484,7 +509,8 @@ template <int KC, int W, int SW, bool GLDS = false>
 __device__ __forceinline__ float kkt(QPanel<SW>& qp, const float* __restrict__ gp,
                                      const float* __restrict__ den, const float* __restrict__ R,
                                      const float* __restrict__ C, int64_t row0, int nrows, int k,
-                                     float mu, const RowBlocks<KC, W>& u, const int32_t* rmap = nullptr) {
+                                     float mu, const RowBlocks<KC, W>& u, float& gd,
+                                     const int32_t* rmap = nullptr) {
   constexpr int NB = RowBlocks<KC, W>::NB, BPP = SW / W, NP = (KC + SW - 1) / SW;
   float pg2 = 0.f, q2 = 0.f;
   wait_lds_reads();
@@ -506,6 +532,7 @@ __device__ __forceinline__ float kkt(QPanel<SW>& qp, const float* __restrict__ g
           const float q = qb[b * W + le];
           const float ul = u.b[lb][le];
           float g = (GLDS ? dot_row_lds<KC, W>(gp + l * KC, u) : dot_row<KC, W>(gp + l * KC, u)) + den[l] * ul - q;
+          guard(gd, g);
           if (!(ul > 0.f)) g = fminf(g, 0.f);
           if (l < k) {
             pg2 += g * g;
@@ -548,9 +575,11 @@ __global__ __launch_bounds__(64 * NWV) void prox_cd_lds_kernel(const float* __re
   const bool valid = lane_id() < nrows;
   const float ub = upper > 0.f ? upper : INFINITY;
   RowBlocks<KC, W> u;
+  float gd = 0.f;
   load_rows<KC, W, SW>(panel, U, row0, nrows, k, true, u);
   for (int s = 0; s < sweeps; ++s)
-    sweep<KC, W, SW, true>(qp, sg, inv, R, C, row0, nrows, k, mu, ub, true, s == 0 && C == U, u);
+    sweep<KC, W, SW, true>(qp, sg, inv, R, C, row0, nrows, k, mu, ub, true, s == 0 && C == U, u, gd);
+  poison_row(u, gd);
   store_rows<KC, W, SW>(panel, U, row0, nrows, k, u);
   if (valid && sweeps_used != nullptr) sweeps_used[row0 + lane_id()] = sweeps;
 }
@@ -596,7 +625,7 @@ __device__ __forceinline__ int cd_chunk(int n, int c) { return 16 * n + 4 * (c ^
 template <int NJ, int GS, typename F4, typename QV>
 __device__ __forceinline__ void cd_block(const float* gb, const float* ib, float mu, float ubnd,
                                          bool c_is_u, bool act, const QV& qb, const F4 (&tr)[4],
-                                         F4 (&ur)[4]) {
+                                         F4 (&ur)[4], float& gd) {
   F4 gr[4], gn[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) gr[c] = *reinterpret_cast<const F4*>(gb + 4 * c);
@@ -617,7 +646,9 @@ __device__ __forceinline__ void cd_block(const float* gb, const float* ib, float
         t0 += gr[l / 4][l % 4] * ur[l / 4][l % 4];
     }
     const float q = c_is_u ? qb[jj] + mu * ur[jj / 4][jj % 4] : qb[jj];
-    const float v = fminf(fmaxf((q - (t0 + t1)) * ib[jj], 0.f), ubnd);
+    const float x = (q - (t0 + t1)) * ib[jj];
+    guard(gd, x);
+    const float v = fminf(fmaxf(x, 0.f), ubnd);
     if (act) ur[jj / 4][jj % 4] = v;
     if (jj + 1 < NJ) {
 #pragma unroll
@@ -632,7 +663,8 @@ __device__ __forceinline__ void cd_block(const float* gb, const float* ib, float
 // u_j = 0; sums of g_j^2 and q_j^2 over the coordinates below k.
 template <int NJ, typename F4, typename QV>
 __device__ __forceinline__ void kkt_block(const float* gb, const float* db, int j0, int k, const QV& qb,
-                                          const F4 (&tr)[4], const F4 (&ur)[4], float& pg2, float& q2) {
+                                          const F4 (&tr)[4], const F4 (&ur)[4], float& pg2, float& q2,
+                                          float& gd) {
 #pragma unroll
   for (int jj = 0; jj < NJ; ++jj) {
     F4 gr[4];
@@ -649,6 +681,7 @@ __device__ __forceinline__ void kkt_block(const float* gb, const float* db, int 
     }
     const float uj = ur[jj / 4][jj % 4];
     float gj = (t0 + t1) + db[jj] * uj - qb[jj];
+    guard(gd, gj);
     if (!(uj > 0.f)) gj = fminf(gj, 0.f);
     if (j0 + jj < k) {
       pg2 += gj * gj;
@@ -717,6 +750,7 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_kernel(
     }
   };
   fetch_a(0);
+  float gd = 0.f;   // non-finite guard of this lane's row (one lane per row in cd_block)
   for (int s = 0; s < sweeps; ++s) {
     const bool c_is_u = s == 0 && C == U;
     wait_lds_reads();
@@ -761,9 +795,9 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_kernel(
       // not a multiple of 16 has only KC % 16 of them)
       const float* gb = sd + 256 * b;
       if (KC % 16 != 0 && b == NBK - 1)
-        cd_block<(KC % 16 != 0 ? KC % 16 : 16), 16>(gb, sinv + 16 * b, mu, ubnd, c_is_u, true, qb, tr, ur);
+        cd_block<(KC % 16 != 0 ? KC % 16 : 16), 16>(gb, sinv + 16 * b, mu, ubnd, c_is_u, true, qb, tr, ur, gd);
       else
-        cd_block<16, 16>(gb, sinv + 16 * b, mu, ubnd, c_is_u, true, qb, tr, ur);
+        cd_block<16, 16>(gb, sinv + 16 * b, mu, ubnd, c_is_u, true, qb, tr, ur, gd);
       // the new values back to the operand layout, then rotate
 #pragma unroll
       for (int c = 0; c < 4; ++c) *reinterpret_cast<f4*>(X + cd_chunk(lane, c)) = ur[c];
@@ -778,12 +812,15 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_kernel(
       for (int r = 0; r < 4; ++r) ub[NBK - 1][r] = nb[r];
     }
   }
+  // rows whose guard is NaN leave as NaN (bit n of badm: row n)
+  const unsigned long long badm = __ballot(gd != gd);
+  const f4 nanv = f4{__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
 #pragma unroll
   for (int b = 0; b < NBK; ++b)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int n = 16 * r + m, c = 16 * b + 4 * g;
-      if (n < nrows && c < k) *reinterpret_cast<f4*>(U + (row0 + n) * k + c) = ub[b][r];
+      if (n < nrows && c < k) *reinterpret_cast<f4*>(U + (row0 + n) * k + c) = (badm >> n) & 1ull ? nanv : ub[b][r];
     }
   if (lane < nrows && sweeps_used != nullptr) sweeps_used[row0 + lane] = sweeps;
 }
@@ -854,6 +891,7 @@ __global__ __launch_bounds__(64 * NWV) void prox_cd_tol_kernel(const float* __re
   int used = 0;
   bool fell_back = false;
   float res = INFINITY;   // a listed row is pending
+  float gd = 0.f;         // non-finite guard (a warm start's own values are not folded in)
   if (rmap == nullptr) {
     load_rows<KC, W, SW>(panel, start != nullptr ? start : U, row0, nrows, k, true, u);
     bool ok = valid;
@@ -866,7 +904,9 @@ __global__ __launch_bounds__(64 * NWV) void prox_cd_tol_kernel(const float* __re
 #pragma nounroll
     for (int c = 0; c < ncand; ++c) {
       if (c == 1) load_rows<KC, W, SW, true>(panel, C, row0, nrows, k, true, u);
-      const float r = kkt<KC, W, SW, true>(qp, sg, den, R, C, row0, nrows, k, mu, u);
+      float gc = 0.f;
+      const float r = kkt<KC, W, SW, true>(qp, sg, den, R, C, row0, nrows, k, mu, u, gc);
+      if (c + 1 == ncand) gd += gc;   // the cold start (or the only start)
       if (c == 0) res_w = r;
       else res_c = r;
     }
@@ -887,13 +927,14 @@ __global__ __launch_bounds__(64 * NWV) void prox_cd_tol_kernel(const float* __re
     if (valid) pend = res > tol;
     const bool run = valid && pend && used < max_sweeps && here < pass.budget;
     if (!__any(run)) break;
-    sweep<KC, W, SW, true>(qp, sg, inv, R, C, row0, nrows, k, mu, ub, run, false, u, rmap);
+    sweep<KC, W, SW, true>(qp, sg, inv, R, C, row0, nrows, k, mu, ub, run, false, u, gd, rmap);
     if (run) {
       ++used;
       ++here;
     }
-    res = kkt<KC, W, SW, true>(qp, sg, den, R, C, row0, nrows, k, mu, u, rmap);
+    res = kkt<KC, W, SW, true>(qp, sg, den, R, C, row0, nrows, k, mu, u, gd, rmap);
   }
+  poison_row(u, gd);
   store_rows<KC, W, SW>(panel, U, row0, nrows, k, u, rmap);
   const bool keep = valid && pend && used < max_sweeps && pass.wave_cnt != nullptr;
   if (valid) {
@@ -1045,6 +1086,7 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
 #pragma unroll
     for (int r = 0; r < 4; ++r) ub[NBK - 1][r] = nb[r];
   };
+  float gd = 0.f;   // non-finite guard of this lane's row (a warm start's own values are not folded in)
   auto sweep_pass = [&](bool run) {
     wait_lds_reads();
     q_issue<16>(qp, R, C, row0, nrows, k, 0, WITHC, rmap);
@@ -1055,9 +1097,9 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
       block_in(b, ur, tr, qb);
       const float* gb = sd + 256 * b;
       if (KC % 16 != 0 && b == NBK - 1)
-        cd_block<(KC % 16 != 0 ? KC % 16 : 16), 16>(gb, sinv + 16 * b, mu, ubnd, false, run, qb, tr, ur);
+        cd_block<(KC % 16 != 0 ? KC % 16 : 16), 16>(gb, sinv + 16 * b, mu, ubnd, false, run, qb, tr, ur, gd);
       else
-        cd_block<16, 16>(gb, sinv + 16 * b, mu, ubnd, false, run, qb, tr, ur);
+        cd_block<16, 16>(gb, sinv + 16 * b, mu, ubnd, false, run, qb, tr, ur, gd);
 #pragma unroll
       for (int c = 0; c < 4; ++c) *reinterpret_cast<f4*>(X + cd_chunk(lane, c)) = ur[c];
       f4 nb[4];
@@ -1066,7 +1108,7 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
       block_out(nb);
     }
   };
-  auto kkt_pass = [&]() -> float {
+  auto kkt_pass = [&](float& gk) -> float {
     float pg2 = 0.f, q2 = 0.f;
     wait_lds_reads();
     q_issue<16>(qp, R, C, row0, nrows, k, 0, WITHC, rmap);
@@ -1077,9 +1119,9 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
       block_in(b, ur, tr, qb);
       const float* gb = sd + 256 * b;
       if (KC % 16 != 0 && b == NBK - 1)
-        kkt_block<(KC % 16 != 0 ? KC % 16 : 16)>(gb, sden + 16 * b, 16 * b, k, qb, tr, ur, pg2, q2);
+        kkt_block<(KC % 16 != 0 ? KC % 16 : 16)>(gb, sden + 16 * b, 16 * b, k, qb, tr, ur, pg2, q2, gk);
       else
-        kkt_block<16>(gb, sden + 16 * b, 16 * b, k, qb, tr, ur, pg2, q2);
+        kkt_block<16>(gb, sden + 16 * b, 16 * b, k, qb, tr, ur, pg2, q2, gk);
       f4 nb[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) nb[r] = ub[0][r];
@@ -1112,11 +1154,12 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
       const unsigned long long mine = (br >> mm) | (br >> (mm + 16)) | (br >> (mm + 32)) | (br >> (mm + 48));
       ok = ok && !(mine & 1ull);
     }
-    const float res_w = kkt_pass();
+    float gw = 0.f;
+    const float res_w = kkt_pass(start != nullptr ? gw : gd);
     float res_c = 0.f;
     if (start != nullptr) {
       load_ub(C, ~0ull);
-      res_c = kkt_pass();
+      res_c = kkt_pass(gd);
     }
     res = res_w;
     if (start != nullptr) {
@@ -1141,8 +1184,10 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
       ++used;
       ++here;
     }
-    res = kkt_pass();
+    res = kkt_pass(gd);
   }
+  const unsigned long long badm = __ballot(gd != gd);
+  const f4 nanv = f4{__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
 #pragma unroll
   for (int b = 0; b < NBK; ++b)
 #pragma unroll
@@ -1150,7 +1195,7 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
       const int n = 16 * r + m, c = 16 * b + 4 * g;
       if (n < nrows && c < k) {
         const int64_t row = rmap != nullptr ? static_cast<int64_t>(rmap[n]) : row0 + n;
-        *reinterpret_cast<f4*>(U + row * k + c) = ub[b][r];
+        *reinterpret_cast<f4*>(U + row * k + c) = (badm >> n) & 1ull ? nanv : ub[b][r];
       }
     }
   const bool keep = valid && pend && used < max_sweeps && pass.wave_cnt != nullptr;
@@ -1251,7 +1296,10 @@ __global__ __launch_bounds__(64) void pgd_kernel(const float* __restrict__ gp,
           const int j = jb * W + je;
           const float uj = u.b[jb][je];
           const float g = dot_row<KC, W>(gp + j * KC, u) + gdiag[j] * uj - mine[b * W + je];
-          mine[b * W + je] = fminf(fmaxf(uj - two_eta * g, 0.f), ub);
+          // max(x, 0) that keeps a NaN (and makes -Inf a NaN): x - x is 0
+          // for finite x and NaN otherwise
+          const float x = uj - two_eta * g;
+          mine[b * W + je] = x > 0.f ? fminf(x, ub) : x - x;
         }
       }
     }

@@ -1,4 +1,4 @@
-// Random sketch matrices (Sec. 3.3) from a counter-based generator.
+// Random sketch matrices (Sec. 3.4) from a counter-based generator.
 //
 // All nodes must draw the same S^t from one shared seed; a counter-based
 // generator makes S^t a pure function of (seed, t, side, row, column), so
@@ -63,13 +63,15 @@ __global__ void philox_kernel(const uint32_t* __restrict__ ctr, const uint32_t* 
 // (x0, x1) to columns 4q, 4q+1 and (x2, x3) to 4q+2, 4q+3.  S is stored
 // transposed (St[c * ld + j]) so that it is the K-contiguous operand of the
 // sketch GEMM; consecutive threads write consecutive j (coalesced).
+// Row j of the block is row j0 + j of the whole sketch (a node's share of the
+// long dimension draws the same values as the one-node sketch).
 __global__ void gaussian_t_kernel(uint32_t k0, uint32_t k1, uint32_t t, uint32_t side_word,
-                                  int64_t n, int64_t d, float scale, float* __restrict__ St,
+                                  int64_t j0, int64_t n, int64_t d, float scale, float* __restrict__ St,
                                   int64_t ld, __hip_bfloat16* __restrict__ Sb, int64_t ldb) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const uint32_t q = blockIdx.y;
   if (j >= n) return;
-  const Words w = philox10(q, static_cast<uint32_t>(j), side_word, t, k0, k1);
+  const Words w = philox10(q, static_cast<uint32_t>(j0 + j), side_word, t, k0, k1);
   float z[4];
   {
     const float rad = sqrtf(-2.0f * logf(open01(w.x0)));
@@ -351,7 +353,7 @@ SubWs carve_sub(void* base, int64_t n) {
 
 }  // namespace
 
-dsanls_status launch_gaussian_sketch_t(uint64_t seed, uint32_t t, int side, int64_t n, int64_t d,
+dsanls_status launch_gaussian_sketch_t(uint64_t seed, uint32_t t, int side, int64_t j0, int64_t n, int64_t d,
                                        float* St, int64_t ld, __hip_bfloat16* St_bf16, int64_t ld_bf16,
                                        hipStream_t s) {
   if (n <= 0 || d <= 0) return DSANLS_OK;
@@ -360,8 +362,8 @@ dsanls_status launch_gaussian_sketch_t(uint64_t seed, uint32_t t, int side, int6
   const float scale = static_cast<float>(1.0 / std::sqrt(static_cast<double>(d)));
   dim3 grid(static_cast<unsigned>(ceil_div(n, 256)), static_cast<unsigned>(nq));
   gaussian_t_kernel<<<grid, 256, 0, s>>>(static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), t,
-                                         (static_cast<uint32_t>(side) & 0xFFu) | (kKindGaussian << 8), n,
-                                         d, scale, St, ld, St_bf16, ld_bf16);
+                                         (static_cast<uint32_t>(side) & 0xFFu) | (kKindGaussian << 8), j0,
+                                         n, d, scale, St, ld, St_bf16, ld_bf16);
   DSANLS_LAUNCHED("gaussian_t_kernel");
   return DSANLS_OK;
 }
@@ -370,9 +372,21 @@ size_t subsample_ws_bytes(int64_t n) {
   return carve_sub(nullptr, n).bytes;
 }
 
+// idx_win[c] = idx[c] - off for the sampled indices inside [off, off + len),
+// -1 for the others: the sampled columns as seen by a block of the long
+// dimension (a node's share).
+__global__ void sub_window_kernel(const int32_t* __restrict__ idx, int64_t d, int64_t off, int64_t len,
+                                  int32_t* __restrict__ idx_win) {
+  const int64_t c = blockIdx.x * 256ll + threadIdx.x;
+  if (c >= d) return;
+  const int64_t j = static_cast<int64_t>(idx[c]) - off;
+  idx_win[c] = j >= 0 && j < len ? static_cast<int32_t>(j) : -1;
+}
+
 dsanls_status launch_subsample(uint64_t seed, uint32_t t, int side, int64_t n, int64_t d,
                                int32_t* idx, int32_t* slot, void* ws, size_t ws_bytes,
-                               int* err_flag, hipStream_t s) {
+                               int* err_flag, hipStream_t s, int64_t win_off, int64_t win_len,
+                               int32_t* idx_win) {
   if (d < 1 || d > n) return fail(DSANLS_E_SHAPE, "subsampling needs 1 <= d <= n");
   if (n > (int64_t(1) << 27)) return fail(DSANLS_E_UNSUPPORTED, "subsampling supports n <= 2^27");
   SubWs w = carve_sub(ws, n);
@@ -397,6 +411,10 @@ dsanls_status launch_subsample(uint64_t seed, uint32_t t, int side, int64_t n, i
   sub_write_kernel<<<static_cast<unsigned>(nblk), kScanBlock, 0, s>>>(w.keys, n, w.st, w.blk, idx,
                                                                       slot);
   DSANLS_LAUNCHED("sub_write_kernel");
+  if (idx_win != nullptr) {
+    sub_window_kernel<<<static_cast<unsigned>(ceil_div(d, 256)), 256, 0, s>>>(idx, d, win_off, win_len, idx_win);
+    DSANLS_LAUNCHED("sub_window_kernel");
+  }
   return DSANLS_OK;
 }
 
@@ -421,7 +439,7 @@ extern "C" dsanls_status dsanls_gaussian_sketch_t(uint64_t seed, int64_t t, int3
                                                   void* hip_stream) {
   if (!St || n < 1 || d < 1 || ld_st < n || t < 0 || side < 0 || side > 255)
     return fail(DSANLS_E_INVALID_ARG, "gaussian_sketch_t: bad arguments");
-  return launch_gaussian_sketch_t(seed, static_cast<uint32_t>(t), side, n, d, St, ld_st, nullptr, 0,
+  return launch_gaussian_sketch_t(seed, static_cast<uint32_t>(t), side, 0, n, d, St, ld_st, nullptr, 0,
                                   static_cast<hipStream_t>(hip_stream));
 }
 

@@ -159,7 +159,8 @@ __global__ __launch_bounds__(256) void gather_cols_kernel(const float* __restric
   const int64_t total = rows * d;
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
     const int64_t r = i / d, c = i % d;
-    A[r * lda + c] = scale * X[r * ldx + idx[c]];
+    const int32_t j = idx[c];
+    A[r * lda + c] = j >= 0 ? scale * X[r * ldx + j] : 0.f;
   }
 }
 
@@ -170,7 +171,8 @@ __global__ __launch_bounds__(256) void gather_rows_t_kernel(const float* __restr
   const int64_t c = blockIdx.x * 256ll + threadIdx.x;
   const int64_t l = blockIdx.y;
   if (c >= d) return;
-  B[l * ldb + c] = scale * W[(int64_t)idx[c] * k + l];
+  const int32_t j = idx[c];
+  B[l * ldb + c] = j >= 0 ? scale * W[(int64_t)j * k + l] : 0.f;
 }
 
 __global__ __launch_bounds__(256) void finite_kernel(const float* __restrict__ X, int64_t count,

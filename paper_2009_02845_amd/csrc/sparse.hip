@@ -4,7 +4,7 @@
 // With S = sqrt(n/d) [e_{j_1} .. e_{j_d}], A = M S keeps only the sampled
 // columns of M and B = V^T S the sampled rows of V, so
 //     R[i, :] = (A B^T)[i, :] = (n/d) * sum_{j sampled, M_ij != 0} M_ij V[j, :]
-// (Sec. 3.3: subsampling keeps the sparsity of M).  One wave streams the
+// (Sec. 3.4: subsampling keeps the sparsity of M).  One wave streams the
 // nnz of a row in coalesced 64-entry chunks, tests each column against the
 // sampled-slot map, and folds the hits, in ascending column order, into a
 // k-vector held across the lanes (two components per lane for k <= 128).
@@ -374,7 +374,8 @@ __global__ __launch_bounds__(256) void gather_len_kernel(const int64_t* __restri
                                                          const int32_t* __restrict__ idx, int d,
                                                          int32_t* __restrict__ len) {
   const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c < d) len[c] = static_cast<int32_t>(t_rowptr[idx[c] + 1] - t_rowptr[idx[c]]);
+  // a sampled column outside this block (idx[c] < 0) has no entries here
+  if (c < d) len[c] = idx[c] >= 0 ? static_cast<int32_t>(t_rowptr[idx[c] + 1] - t_rowptr[idx[c]]) : 0;
 }
 
 __global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {

@@ -79,3 +79,28 @@ def test_workspace_grows_with_problem():
     small = _ws(B.make_config(m=100, n=80, k=8, d=20), _dense(80))
     big = _ws(B.make_config(m=1000, n=800, k=8, d=200), _dense(800))
     assert small[0] == 0 and big[0] == 0 and big[1] > small[1] > 0
+
+
+@pytest.mark.parametrize("kw,status", [
+    # mu_0 = alpha = 0 only in to-tolerance mode
+    (dict(m=5, n=5, k=2, d=3, alpha=0.0, beta=1.0), 1),
+    (dict(m=5, n=5, k=2, d=3, alpha=0.0, solver="pgd"), 1),
+    (dict(m=5, n=5, k=2, d=3, alpha=0.0, beta=0.0, sweeps=0, max_sweeps=10), 0),
+    # a node's share must lie inside the whole matrix
+    (dict(m=5, n=5, k=2, d=3, row_offset=3, m_global=7), 2),
+    (dict(m=5, n=5, k=2, d=3, row_offset=2, m_global=7), 0),
+    (dict(m=5, n=5, k=2, d=3, col_offset=-1), 2),
+    (dict(m=5, n=5, k=2, d=3, m_global=4), 2),
+    # subsampling draws d of n_global columns; identity needs the whole matrix
+    (dict(m=5, n=5, k=2, d=8, d_prime=3, sketch="subsample", col_offset=5, n_global=10), 0),
+    (dict(m=5, n=5, k=2, d=11, d_prime=3, sketch="subsample", col_offset=5, n_global=10), 2),
+    (dict(m=5, n=5, k=2, d=5, sketch="identity", n_global=10), 7),
+])
+def test_validation_node_share_and_alpha(kw, status):
+    cfg = B.make_config(**kw)
+    st, _ = _ws(cfg, _dense(kw["n"]))
+    assert st == status, B.load().dsanls_last_error()
+
+
+def test_status_string_internal():
+    assert B.load().dsanls_status_string(8) == b"internal failure"

@@ -213,3 +213,53 @@ def test_to_tolerance_passes_match_oracle(env, k):
                      tol=1e-12, max_sweeps=20000, seed=7)
     assert _rel(Ug, O.update_U(M64, U0.astype(np.float64), V0.astype(np.float64), 0, exact)) < 1e-3
     assert np.isfinite(Ug).all() and Ug.min() >= 0
+
+
+def _shift_net(d, k, h, shift):
+    """A network whose output is ReLU(u + shift) for every row: zero first
+    layer with unit hidden biases, W2 spreading the shift over the hidden
+    units (so the warm start differs from u_i^t by a fixed vector)."""
+    return {"W1a": np.zeros((d, h)), "W1u": np.zeros((h, k)), "b1": np.ones(h),
+            "W2": np.repeat((shift / h)[:, None], h, axis=1), "b2": np.zeros(k)}
+
+
+@pytest.mark.parametrize("k,d", [(68, 80), (96, 60), (100, 80)])
+def test_warm_start_taken_in_block_form(env, k, d):
+    # k = 68..100: the to-tolerance passes run in the block form (coupling on
+    # the matrix cores).  The warm start is u_i^t shifted by the mean
+    # correction towards the exact solutions, so it wins on some rows and not
+    # on others; the oracle predicts which from the same KKT test, the waves
+    # mix warm and cold rows, and every row still reaches the unique
+    # minimiser of its regularised problem (mu > 0).
+    torch, Bd = env
+    m, n, h, t = 700, 500, 32, 0
+    warm, M64, Uw, Vw, U0, V0 = _sparse_ctx(env, m, n, k, d, 9, warm_hidden=h, tol=1e-5)
+    U64, V64 = U0.astype(np.float64), V0.astype(np.float64)
+    S = P.subsample_sketch(7, t, 0, n, d)
+    A, Bm = O.sketch_products(M64, V64, S)
+    G, R = O.gram_and_rhs(A, Bm)
+    mu = 1.0 + 1.0 * t
+    exact, _ = O.prox_cd_solve(U64, U64, G, R, mu, 0, tol=1e-12, max_sweeps=20000)
+    p = _shift_net(d, k, h, np.mean(exact - U64, axis=0))
+    p = {nm: v.astype(np.float32).astype(np.float64) for nm, v in p.items()}
+    y = N.forward(p, sp.csr_matrix(A), U64)[3]
+    res_w = O.kkt_residual(y, U64, G, R, mu)
+    res_c = O.kkt_residual(U64, U64, G, R, mu)
+    take = res_w < res_c
+    assert 0.05 * m < take.sum() < 0.95 * m          # the construction mixes the rows
+    warm.set_warm_start(Bd.mlp_pack(p), h)
+    before = warm.stats()
+    warm.update_U(t)
+    st = warm.stats()
+    fb = st["warm_fallbacks"] - before["warm_fallbacks"]
+    assert 0 < fb < m
+    assert abs(fb - (m - take.sum())) <= max(3, m // 100)
+    Ug = Uw.cpu().numpy().astype(np.float64)
+    # the same rule from the same starts, and the exact minimiser
+    start = np.where(take[:, None], y, U64)
+    same, _ = O.prox_cd_solve(start, U64, G, R, mu, 0, tol=1e-5, max_sweeps=400)
+    assert _rel(Ug, same) < 1e-4
+    assert _rel(Ug, exact) < 1e-3
+    # per row too: no row far from its minimiser
+    rowerr = np.linalg.norm(Ug - exact, axis=1) / np.maximum(np.linalg.norm(exact, axis=1), 1e-12)
+    assert rowerr.max() < 1e-2

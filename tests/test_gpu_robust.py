@@ -1,0 +1,160 @@
+"""Non-finite inputs on the GPU path: never projected to a silent zero, and
+reported as NONFINITE by the objective (the projection max(x, 0) of Alg. 3
+and eq. gradient_descent is not allowed to swallow a NaN)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import dsanls as O
+from paper_2009_02845_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_02845_amd import binding
+    binding.load()
+    return torch, binding
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def _gram_rhs(k, d, rows, seed):
+    g = np.random.default_rng(seed)
+    B = g.standard_normal((k, d))
+    A = g.standard_normal((rows, d)) + 0.3
+    G, R = O.gram_and_rhs(A, B)
+    U0 = g.random((rows, k))
+    f32 = lambda x: x.astype(np.float32).astype(np.float64)
+    return f32(G), f32(R), f32(U0)
+
+
+@pytest.mark.parametrize("k", [10, 33, 64, 100])
+@pytest.mark.parametrize("sweeps", [1, 3, 0])
+def test_nonfinite_rows_of_R_come_out_nan(env, k, sweeps):
+    # rows with +Inf, -Inf or NaN in R: all their entries NaN; every other
+    # row matches the oracle (k = 100 runs the block kernels, k = 33 has
+    # padding coordinates, sweeps = 0 is the to-tolerance solve)
+    torch, Bd = env
+    rows, mu = 300, 0.8
+    G, R, U0 = _gram_rhs(k, 3 * k // 2 + 7, rows, k + sweeps)
+    bad = {5: np.inf, 77: -np.inf, 130: np.nan, 299: np.nan}
+    Rb = R.copy()
+    for i, v in bad.items():
+        Rb[i, (i * 7) % k] = v
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(np.float32))).cuda()
+    Gd, Rd, Ud = t(G), t(Rb), t(U0)
+    Bd.nnls_prox_cd(Gd, Rd, Ud, Ud, mu, sweeps=sweeps, tol=1e-5, max_sweeps=300)
+    Ug = Ud.cpu().numpy().astype(np.float64)
+    badrows = sorted(bad)
+    assert np.isnan(Ug[badrows]).all()
+    ok = np.setdiff1d(np.arange(rows), badrows)
+    assert np.isfinite(Ug[ok]).all()
+    Uo, _ = O.prox_cd_solve(U0[ok], U0[ok], G, R[ok], mu, sweeps, tol=1e-5 if sweeps == 0 else 1e-4,
+                            max_sweeps=300)
+    assert _rel(Ug[ok], Uo) < (1e-3 if sweeps == 0 else 1e-4)
+
+
+def test_nonfinite_gram_poisons_every_row(env):
+    torch, Bd = env
+    k, rows = 64, 200
+    G, R, U0 = _gram_rhs(k, 90, rows, 3)
+    G[3, 40] = G[40, 3] = np.inf
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(np.float32))).cuda()
+    Ud = t(U0)
+    Bd.nnls_prox_cd(t(G), t(R), Ud, Ud, 1.0, sweeps=1)
+    assert np.isnan(Ud.cpu().numpy()).all()
+
+
+def test_pgd_keeps_nan(env):
+    torch, Bd = env
+    k, rows = 10, 100
+    G, R, U0 = _gram_rhs(k, 30, rows, 4)
+    R[9, 2] = np.nan
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(np.float32))).cuda()
+    Ud = t(U0)
+    Bd.pgd_step(t(G), t(R), Ud, 0.5)
+    Ug = Ud.cpu().numpy()
+    assert np.isnan(Ug[9, 2]) and np.isfinite(np.delete(Ug, 9, axis=0)).all()
+
+
+def _dense_solver(env, sketch="gaussian", k=10, **kw):
+    torch, Bd = env
+    m, n, d = 200, 150, 40
+    M = synth.dense_uniform(m, n, 0)
+    U0, V0 = synth.init_factors(m, n, k, 0)
+    Md = torch.from_numpy(M).cuda()
+    U, V = torch.from_numpy(U0).cuda(), torch.from_numpy(V0).cuda()
+    cfg = Bd.make_config(m, n, k, d, d, sketch=sketch, solver="prox_cd", seed=0, **kw)
+    return Bd.Solver(cfg, Bd.dense_matrix(Md), U, V, tensors=[Md]), M, U, V, U0, V0
+
+
+def test_nan_in_M_at_init(env):
+    torch, Bd = env
+    M = synth.dense_uniform(50, 40, 0)
+    M[7, 3] = np.nan
+    U0, V0 = synth.init_factors(50, 40, 4, 0)
+    Md = torch.from_numpy(M).cuda()
+    cfg = Bd.make_config(50, 40, 4, 10, 10, seed=0)
+    with pytest.raises(Bd.DsanlsError) as e:
+        Bd.Solver(cfg, Bd.dense_matrix(Md), torch.from_numpy(U0).cuda(), torch.from_numpy(V0).cuda(),
+                  tensors=[Md])
+    assert e.value.status_name == "NONFINITE"
+
+
+@pytest.mark.parametrize("sketch,kw", [("gaussian", {}), ("subsample", {}),
+                                       ("gaussian", dict(sweeps=0, tol=1e-5, max_sweeps=200))])
+def test_nan_injected_into_V_before_update(env, sketch, kw):
+    # the update runs (asynchronously); U is not silently zeroed where the
+    # NaN reaches it, and the objective reports NONFINITE once, then, with
+    # finite factors restored, the flags are clear again
+    torch, Bd = env
+    s, M, U, V, U0, V0 = _dense_solver(env, sketch, **kw)
+    s.iteration(0)
+    V[11, 2] = float("nan")
+    s.update_U(1)
+    Ug = U.cpu().numpy()
+    if sketch == "gaussian":
+        assert np.isnan(Ug).all()            # B = V^T S: every entry sees the NaN row
+    with pytest.raises(Bd.DsanlsError) as e:
+        s.objective()
+    assert e.value.status_name == "NONFINITE"
+    U.copy_(torch.from_numpy(U0))
+    V.copy_(torch.from_numpy(V0))
+    assert np.isfinite(s.objective())
+
+
+def test_nan_in_U_centre_fixed_sweeps_block_kernel(env):
+    # sparse path at k = 100 (the block-coupling kernel): a NaN in one row of
+    # U (the start and proximal centre) comes out as a NaN row
+    torch, Bd = env
+    m, n, k, d = 400, 300, 100, 60
+    g = np.random.default_rng(5)
+    Ms = sp.random(m, n, density=0.05, format="csr", random_state=5, dtype=np.float64)
+    Ms.data = g.lognormal(0, 1, Ms.nnz)
+    Ms = Ms.astype(np.float32).tocsr()
+    Ms.sort_indices()
+    Mt = Ms.T.tocsr()
+    Mt.sort_indices()
+    U0, V0 = synth.init_factors(m, n, k, 5)
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a.astype(dt))).cuda()
+    arrs = [t(Ms.indptr, np.int64), t(Ms.indices, np.int32), t(Ms.data, np.float32),
+            t(Mt.indptr, np.int64), t(Mt.indices, np.int32), t(Mt.data, np.float32)]
+    U, V = torch.from_numpy(U0).cuda(), torch.from_numpy(V0).cuda()
+    cfg = Bd.make_config(m, n, k, d, d, sketch="subsample", solver="prox_cd", sweeps=1, seed=2)
+    s = Bd.Solver(cfg, Bd.csr_matrix(*arrs), U, V, tensors=arrs)
+    U[123, 50] = float("nan")
+    s.update_U(0)
+    Ug = U.cpu().numpy()
+    assert np.isnan(Ug[123]).all()
+    assert np.isfinite(np.delete(Ug, 123, axis=0)).all()
+    ocfg = O.Config(k=k, d=d, d_prime=d, sketch=O.SKETCH_SUBSAMPLE, solver=O.SOLVER_PROX_CD, seed=2)
+    ok = np.setdiff1d(np.arange(m), [123])
+    Uo = O.update_U(Ms.astype(np.float64), U0.astype(np.float64), V0.astype(np.float64), 0, ocfg, rows=ok)
+    assert _rel(Ug[ok].astype(np.float64), Uo) < 1e-4
