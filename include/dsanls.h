@@ -351,6 +351,23 @@ dsanls_status dsanls_nnls_prox_cd(const float* G, const float* R, const float* C
                                   int32_t max_sweeps, float upper, int32_t* sweeps_used,
                                   void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* The same batched NNLS update as dsanls_nnls_prox_cd, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops
+ * that forbid allocation): no workspace argument and no allocation of any
+ * kind.  The prepared Gram lives in a static device array of
+ * dsanls_nnls_noalloc_scratch_bytes() bytes, one copy on each GPU the
+ * library runs on, held until the process ends; its device address is
+ * looked up on the first call on each device (the stream must belong to the
+ * current device).  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (other streams, other threads) race and give wrong
+ * results.  Arguments, layout and results as dsanls_nnls_prox_cd;
+ * UNSUPPORTED if k > 128 or the prepared Gram would not fit the array. */
+size_t dsanls_nnls_noalloc_scratch_bytes(void);
+dsanls_status dsanls_nnls_prox_cd_noalloc(const float* G, const float* R, const float* C, float* U,
+                                          int64_t rows, int32_t k, float mu, int32_t sweeps, float tol,
+                                          int32_t max_sweeps, float upper, int32_t* sweeps_used,
+                                          void* hip_stream);
+
 /* One projected-gradient step (eq. gradient_descent) with eta computed on
  * the device as 1 / (2 (max_j sum_l |G_lj| + mu)):
  * U <- max(U - 2 eta (U G - R), 0), in place.  Workspace as above.  The

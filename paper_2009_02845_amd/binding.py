@@ -99,6 +99,9 @@ _SIGS = {
     "dsanls_nnls_prox_cd": (c_int32, [c_vp, c_vp, c_vp, c_vp, c_int64, c_int32, c_float, c_int32, c_float,
                                       c_int32, c_float, c_vp, c_vp, c_size_t, c_vp]),
     "dsanls_pgd_step": (c_int32, [c_vp, c_vp, c_vp, c_int64, c_int32, c_float, c_float, c_vp, c_size_t, c_vp]),
+    "dsanls_nnls_noalloc_scratch_bytes": (c_size_t, []),
+    "dsanls_nnls_prox_cd_noalloc": (c_int32, [c_vp, c_vp, c_vp, c_vp, c_int64, c_int32, c_float, c_int32, c_float,
+                                              c_int32, c_float, c_vp, c_vp]),
 }
 
 
@@ -334,6 +337,20 @@ def nnls_prox_cd(G, R, C, U, mu, sweeps=1, tol=1e-4, max_sweeps=100, upper=0.0, 
     _check("dsanls_nnls_prox_cd", lib.dsanls_nnls_prox_cd(_ptr(G), _ptr(R), _ptr(C), _ptr(U), rows, k, mu,
                                                           sweeps, tol, max_sweeps, upper, _ptr(used),
                                                           _ptr(ws), nb, _stream(stream)))
+    return used
+
+
+def nnls_prox_cd_noalloc(G, R, C, U, mu, sweeps=1, tol=1e-4, max_sweeps=100, upper=0.0, want_sweeps=False,
+                         stream=None):
+    """nnls_prox_cd through the allocation-free entry point (the library's
+    static device scratch instead of a workspace)."""
+    import torch
+    lib = load()
+    rows, k = U.shape
+    used = torch.empty(rows, dtype=torch.int32, device=U.device) if want_sweeps else None
+    _check("dsanls_nnls_prox_cd_noalloc", lib.dsanls_nnls_prox_cd_noalloc(
+        _ptr(G), _ptr(R), _ptr(C), _ptr(U), rows, k, mu, sweeps, tol, max_sweeps, upper, _ptr(used),
+        _stream(stream)))
     return used
 
 

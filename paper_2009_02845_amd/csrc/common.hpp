@@ -115,6 +115,10 @@ dsanls_status launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, 
                                     hipStream_t s);
 
 // ---------------------------------------------------------------- nnls.hip
+// Largest rank of the NNLS kernels, and the floats of the prepared Gram for
+// a padded rank KC (KC x KC, four vectors of KC, 64 spare).
+constexpr int kNnlsMaxRank = 128;
+constexpr size_t nnls_prep_floats(int KC) { return static_cast<size_t>(KC) * KC + 4 * static_cast<size_t>(KC) + 64; }
 size_t nnls_ws_bytes(int k);
 // Workspace of the to-tolerance mode's compacted passes (rows = the most
 // rows of any update; nw = ceil(rows / 64)): per-row sweep counts and flags,

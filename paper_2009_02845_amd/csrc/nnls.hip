@@ -38,7 +38,7 @@ constexpr int kMaxKC = 128;
 // Lane within the wave (a workgroup is one wave of 64 rows).
 __device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x & 63); }
 
-size_t prep_floats(int KC) { return static_cast<size_t>(KC) * KC + 4 * KC + 64; }
+size_t prep_floats(int KC) { return nnls_prep_floats(KC); }
 
 Prep carve_prep(void* ws, int KC) {
   float* p = static_cast<float*>(ws);
@@ -1438,7 +1438,7 @@ int nnls_kc(int k) {
 
 }  // namespace
 
-constexpr int kMaxK = 128;
+constexpr int kMaxK = kNnlsMaxRank;
 
 size_t nnls_ws_bytes(int k) {
   const int kc = nnls_kc(k < 1 ? 1 : k);
