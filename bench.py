@@ -4,14 +4,24 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
 A step is one outer iteration of the method (update_U then update_V, Alg. 2
-with one node) on synthetic data already resident in HBM.  The default
-workload is the dense 20000 x 10000 planted matrix, k = 64, Gaussian sketch
-d = d' = 1024, one prox-CD sweep per update, in FP32.  W warm-up iterations
-run first, then U and V are reset to U^0, V^0 and exactly K iterations
-t = 0 .. K-1 are timed between two device synchronisations.  One JSON line
-is printed: the throughput, the roofline of the dominant kernel (its
-duration taken from HIP events recorded around it in the timed region), the
-relative objective reached, and the CPU oracle timed on a bounded sample.
+with one node) on synthetic data already resident in HBM.
+
+The default workload measures the metric to a fixed relative objective: the
+dense 50000 x 20000 planted rank-128 matrix with 1% noise, k = 128, Gaussian
+sketch d = d' = 4096, one prox-CD sweep per update, run as plain FP32 and as
+the BF16 form (sketch GEMM in BF16 on the matrix cores, FP32 accumulation).
+For each of three data seeds the plain FP32 run takes K iterations
+(K = --steps, default 30) and its final relative objective is that seed's
+eps*; the BF16 form then runs until its objective is <= eps* (1 + 1e-3).
+Every iteration is timed on its own between device synchronisations (the
+objective, evaluated after it, is outside the timed region).  value is the
+BF16 form's iterations/s over its runs to eps*; the line also carries each
+form's iterations and time to eps*, the speed-up, the per-update error of
+both forms against the plain FP64 oracle on sampled rows, the roofline of
+the BF16 sketch GEMM, and the CPU oracle timed on a bounded sample.
+
+Other workloads (--workload) time K iterations at a fixed count.  W warm-up
+iterations run first, then U and V are reset to U^0, V^0.
 """
 import argparse
 import json
@@ -51,10 +61,21 @@ WORKLOADS = {
                                       pairs=1_000_000, runs=5, run_iters=20, label_tol=1e-6, tol=1e-4,
                                       max_sweeps=200, epochs=6, batch=4096, lr=1e-4),
 }
-DEFAULT = "dense-20000x10000"
+DEFAULT = "dense-50000x20000"
+# the precision form measured to a fixed relative objective (the default)
+TO_EPS = {"dense-50000x20000": dict(kind="to_eps", m=50000, n=20000, k=128, d=4096, iters=30,
+                                    solver="prox_cd", gen="planted", noise=0.01, noise_relative=True,
+                                    seeds=(0, 1, 2), max_factor=3, sample_rows=256)}
+WORKLOADS.update(TO_EPS)
 
 
-def describe(name, w):
+def describe(name, w, K=None):
+    iters = K if K is not None else w["iters"]
+    if w["kind"] == "to_eps":
+        return (f"dense {w['m']}x{w['n']} planted rank-{w['k']} |N(0,1)| factors + {w['noise']:.0%} noise, "
+                f"k={w['k']}, Gaussian sketch d=d'={w['d']}, prox-CD 1 sweep; plain FP32 for {iters} iterations "
+                f"sets eps* per data seed, the BF16 sketch-GEMM form runs to eps*(1+1e-3); "
+                f"{len(w['seeds'])} data seeds")
     if w["kind"] == "warm":
         return (f"CSR {w['m']}x{w['n']}, {w['nnz']:.0e} nnz text-shaped, k={w['k']}, subsampling d=d'={w['d']}, "
                 f"prox-CD to tolerance {w['tol']}, MLP warm start [a_i (d); u_i (k)] -> {w['hidden']} -> k "
@@ -62,13 +83,13 @@ def describe(name, w):
     if w["kind"] == "sparse":
         return (f"CSR {w['m']}x{w['n']}, {w['nnz']:.0e} nnz, power-law rows (alpha=1.5), Zipf(1.1) "
                 f"columns, lognormal values, k={w['k']}, subsampling sketch d=d'={w['d']}, "
-                f"prox-CD 1 sweep, FP32, {w['iters']} iterations")
+                f"prox-CD 1 sweep, FP32, {iters} iterations")
     if w["kind"] == "dense":
         gen = ("uniform[0,1)" if w["gen"] == "uniform" else
                f"planted rank-{w['k']} |N(0,1)| factors + noise")
         return (f"dense {w['m']}x{w['n']} {gen}, k={w['k']}, Gaussian sketch d=d'={w['d']}, "
                 f"{'prox-CD 1 sweep' if w['solver'] == 'prox_cd' else 'PGD'}, "
-                f"sketch GEMM {w['precision'].upper()}, {w['iters']} iterations")
+                f"sketch GEMM {w['precision'].upper()}, {iters} iterations")
     return name
 
 
@@ -95,8 +116,10 @@ def make_sparse(w, seed=0):
     return M, Mt, U0, V0
 
 
-def cpu_baseline(w, M, U0, V0, budget_s=12.0, max_iters=5, Mt=None):
-    """The FP64 oracle, untuned, timed on the host's cores over whole iterations."""
+def cpu_baseline(w, M, U0, V0, budget_s=12.0, max_iters=5, Mt=None, half=False):
+    """The FP64 oracle, untuned, timed on the host's cores over whole
+    iterations (half=True: one U half-iteration, counted as half an
+    iteration, for the workloads where a whole one takes about a minute)."""
     from oracle import dsanls as O
     try:
         import threadpoolctl
@@ -109,6 +132,13 @@ def cpu_baseline(w, M, U0, V0, budget_s=12.0, max_iters=5, Mt=None):
     M64 = M.astype(np.float64)
     Mt64 = Mt.astype(np.float64) if Mt is not None else None
     U, V = U0.astype(np.float64), V0.astype(np.float64)
+    if half:
+        t0 = time.perf_counter()
+        O.update_U(M64, U, V, 0, cfg)
+        el = time.perf_counter() - t0
+        return {"value": 0.5 / el, "unit": "iterations/s", "cores": int(cores), "kind": "oracle",
+                "sample": f"one U half-iteration (t=0) of the same workload in FP64 numpy, {el:.1f} s, "
+                          f"counted as half an iteration"}
     done, t0 = 0, time.perf_counter()
     while done < max_iters:
         U = O.update_U(M64, U, V, done, cfg)
@@ -323,6 +353,145 @@ def run_warm(args, w, torch, B):
     }
 
 
+def _timed_run(solver, U, V, U0d, V0d, torch, iters, stop_at=None):
+    """Reset U, V and run up to iters iterations, each timed on its own
+    between device synchronisations; the objective after each one is outside
+    the timed region.  With stop_at, stop at the first iteration whose
+    objective is <= stop_at.  Returns (times_s, objectives)."""
+    U.copy_(U0d)
+    V.copy_(V0d)
+    torch.cuda.synchronize()
+    times, objs = [], []
+    for t in range(iters):
+        t0 = time.perf_counter()
+        solver.iteration(t)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        if stop_at is not None or t == iters - 1:
+            objs.append(solver.objective())
+            if stop_at is not None and objs[-1] <= stop_at:
+                break
+    return times, objs
+
+
+def _per_update_error(M, U0, V0, Ug, sel, w, seed_sketch=0):
+    """Relative Frobenius error of one GPU U update on the rows sel against
+    the plain FP64 oracle (same U^0, V^0, same S^0), and against the oracle
+    of the BF16 form (M and S rounded to bfloat16, products exact)."""
+    from oracle import dsanls as O
+    k, d = w["k"], w["d"]
+    ocfg = O.Config(k=k, d=d, d_prime=d, sketch=O.SKETCH_GAUSSIAN, solver=O.SOLVER_PROX_CD, seed=seed_sketch)
+    U64, V64 = U0.astype(np.float64), V0.astype(np.float64)
+    plain = O.update_U(M, U64, V64, 0, ocfg, rows=sel)
+    ocfg.precision = "bf16"
+    rounded = O.update_U(M, U64, V64, 0, ocfg, rows=sel)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    return rel(Ug, plain), rel(Ug, rounded)
+
+
+def run_to_eps(args, w, torch, B, K, W):
+    """Plain FP32 and the BF16 form to a fixed relative objective (the
+    metric), on several data seeds."""
+    m, n, k, d = w["m"], w["n"], w["k"], w["d"]
+    dev = torch.device("cuda", 0)
+    seeds = w["seeds"] if args.seeds is None else tuple(range(args.seeds))
+    per_seed, bf16_times, bf16_iters = [], [], 0
+    errors, roof, prod_ms = None, None, {}
+    for si, seed in enumerate(seeds):
+        print(f"[bench] seed {seed}: generating data", file=sys.stderr, flush=True)
+        M, U0, V0 = make_dense(w, seed)
+        Md = torch.from_numpy(M).to(dev)
+        U0d, V0d = torch.from_numpy(U0).to(dev), torch.from_numpy(V0).to(dev)
+        res = {}
+        for form in ("fp32", "bf16"):
+            U, V = U0d.clone(), V0d.clone()
+            cfg = B.make_config(m, n, k, d, d, sketch="gaussian", solver="prox_cd", precision=form, sweeps=1,
+                                alpha=1.0, beta=1.0, seed=0)
+            solver = B.Solver(cfg, B.dense_matrix(Md), U, V, tensors=[Md])
+            if si == 0:
+                # one U update from U^0, V^0 against the FP64 oracle on sampled rows
+                solver.update_U(0)
+                torch.cuda.synchronize()
+                g = np.random.default_rng(11)
+                sel = np.unique(np.concatenate([g.choice(m, w["sample_rows"], replace=False), [0, m - 1]]))
+                Ug = U.cpu().numpy().astype(np.float64)[sel]
+                print(f"[bench] {form}: per-update error against the FP64 oracle", file=sys.stderr, flush=True)
+                e_plain, e_rounded = _per_update_error(M, U0, V0, Ug, sel, w)
+                errors = errors or {}
+                errors[form] = {"vs_fp64_oracle": e_plain, "vs_fp64_oracle_of_bf16_inputs": e_rounded,
+                                "rows": int(len(sel)), "update": "U at t=0 from U^0, V^0"}
+            for t in range(W):
+                solver.iteration(t)
+            torch.cuda.synchronize()
+            print(f"[bench] seed {seed} {form}: timing", file=sys.stderr, flush=True)
+            solver.set_timing(True)
+            if form == "fp32":
+                times, objs = _timed_run(solver, U, V, U0d, V0d, torch, K)
+                eps = objs[-1]
+                res[form] = {"iterations": K, "time_s": sum(times), "rel_objective": eps}
+            else:
+                target = res["fp32"]["rel_objective"] * (1 + 1e-3)
+                times, objs = _timed_run(solver, U, V, U0d, V0d, torch, w["max_factor"] * K, stop_at=target)
+                reached = objs[-1] <= target
+                res[form] = {"iterations": len(times), "time_s": sum(times), "rel_objective": objs[-1],
+                             "reached": bool(reached)}
+                bf16_times += times
+                bf16_iters += len(times)
+            solver.set_timing(False)
+            tm = solver.timing()
+            res[form]["iterations_per_s"] = res[form]["iterations"] / res[form]["time_s"]
+            res[form]["phase_ms_per_step"] = {p: tm[p + "_ms"] / max(tm["launches"] / 2, 1)
+                                              for p in ("sketch", "product", "small", "nnls")}
+            prod_ms.setdefault(form, []).append(tm["product_ms"] / max(tm["launches"] / 2, 1))
+            solver.close()
+            del solver, U, V
+        res["eps_star"] = res["fp32"]["rel_objective"]
+        res["speedup_time_to_eps"] = res["fp32"]["time_s"] / res["bf16"]["time_s"]
+        res["seed"] = seed
+        per_seed.append(res)
+        del Md, U0d, V0d
+        torch.cuda.empty_cache()
+        if si == 0:
+            keepM = (M, U0, V0)
+    med = lambda xs: float(np.median(xs))
+    # roofline of the dominant kernel of the BF16 form: one grouped launch per
+    # iteration computes A = M S and A' = M^T S' (the V side reuses A')
+    flops = 2.0 * m * n * d + 2.0 * n * m * d
+    avg_s = med(prod_ms["bf16"]) / 1e3
+    ach = flops / avg_s / 1e12
+    roof = {"kernel": "BF16 sketch GEMMs A = M S, A' = M^T S' (gemm_nt_bf16_dma_kernel, one launch per iteration)",
+            "bound": "mfma", "achieved": ach, "peak": PEAK["bf16_mfma_tflops"], "unit": "TFLOP/s",
+            "frac": ach / PEAK["bf16_mfma_tflops"], "traffic": traffic_bytes("dense-50000x20000-bf16"),
+            "flops_per_launch": flops, "avg_launch_ms": avg_s * 1e3}
+    f_avg = med(prod_ms["fp32"]) / 1e3
+    roof_fp32 = {"kernel": "FP32 sketch GEMMs (gemm_nt_f32_dma_kernel)", "bound": "mfma",
+                 "achieved": flops / f_avg / 1e12, "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
+                 "frac": flops / f_avg / 1e12 / PEAK["fp32_mfma_tflops"], "avg_launch_ms": f_avg * 1e3}
+    value = bf16_iters / sum(bf16_times)
+    out = {
+        "value": value, "ms_per_step": 1e3 * sum(bf16_times) / bf16_iters,
+        "rel_objective": med([r["bf16"]["rel_objective"] for r in per_seed]),
+        "nnls_rows_per_s": (m + n) / (med([r["bf16"]["phase_ms_per_step"]["nnls"] for r in per_seed]) / 1e3),
+        "to_eps": {
+            "eps_star_median": med([r["eps_star"] for r in per_seed]),
+            "definition": "eps* = plain-FP32 relative objective after K iterations, per data seed; "
+                          "a form reaches it at rel <= eps* (1 + 1e-3)",
+            "fp32": {"iterations_to_eps": med([r["fp32"]["iterations"] for r in per_seed]),
+                     "time_to_eps_s": med([r["fp32"]["time_s"] for r in per_seed]),
+                     "iterations_per_s": med([r["fp32"]["iterations_per_s"] for r in per_seed])},
+            "bf16": {"iterations_to_eps": med([r["bf16"]["iterations"] for r in per_seed]),
+                     "time_to_eps_s": med([r["bf16"]["time_s"] for r in per_seed]),
+                     "iterations_per_s": med([r["bf16"]["iterations_per_s"] for r in per_seed]),
+                     "all_reached": all(r["bf16"]["reached"] for r in per_seed)},
+            "speedup_bf16_vs_fp32_time_to_eps": med([r["speedup_time_to_eps"] for r in per_seed]),
+            "per_seed": per_seed},
+        "error_vs_fp64_oracle": errors,
+        "roofline": roof,
+        "roofline_fp32_form": roof_fp32,
+    }
+    return out, keepM
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,6 +500,8 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seeds", type=int, default=None,
+                    help="data seeds of the to-eps* workload (default: the workload's three)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES bytes device-to-device three times (calibrates the HBM "
                          "traffic counters against a transfer of known size) and exit")
@@ -357,6 +528,21 @@ def main():
     w = WORKLOADS[args.workload]
     K = args.steps if args.steps is not None else w["iters"]
     W = args.warmup
+    if w["kind"] == "to_eps":
+        r, (M, U0, V0) = run_to_eps(args, w, torch, B, K, W)
+        out = {"metric": "sketched-ANLS iterations/s (and NNLS rows/s) to a fixed relative objective, "
+                         "BF16 form vs plain FP32",
+               "unit": "iterations/s", "n_gpus": 1, "steps": K, "warmup": W,
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16-sketch/f32",
+               "data": "synthetic",
+               "config": {"workload": describe(args.workload, w, K), "m": w["m"], "n": w["n"], "k": w["k"],
+                          "d": w["d"], "iterations": K, "parallelism": "single GPU"}}
+        out.update(r)
+        if not args.no_cpu_baseline:
+            print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+            out["cpu_baseline"] = cpu_baseline(w, M, U0, V0, half=True)
+        print(json.dumps(out), flush=True)
+        return
     if w["kind"] == "warm":
         r = run_warm(args, w, torch, B)
         out = {"metric": "sketched-ANLS iterations/s (and NNLS rows/s) to a fixed relative objective",
@@ -439,7 +625,7 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16-sketch/f32" if w["precision"] == "bf16" else "f32",
         "data": "synthetic",
-        "config": {"workload": describe(args.workload, w), "m": m, "n": n, "k": k, "d": d,
+        "config": {"workload": describe(args.workload, w, K), "m": m, "n": n, "k": k, "d": d,
                    "iterations": K, "parallelism": "single GPU"},
         "rel_objective": rel,
         "nnls_rows_per_s": (m + n) * K / (tm["nnls_ms"] / 1e3) if tm["nnls_ms"] > 0 else None,

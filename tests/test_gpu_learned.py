@@ -215,22 +215,30 @@ def test_to_tolerance_passes_match_oracle(env, k):
     assert np.isfinite(Ug).all() and Ug.min() >= 0
 
 
-def _shift_net(d, k, h, shift):
-    """A network whose output is ReLU(u + shift) for every row: zero first
-    layer with unit hidden biases, W2 spreading the shift over the hidden
-    units (so the warm start differs from u_i^t by a fixed vector)."""
-    return {"W1a": np.zeros((d, h)), "W1u": np.zeros((h, k)), "b1": np.ones(h),
-            "W2": np.repeat((shift / h)[:, None], h, axis=1), "b2": np.zeros(k)}
+def _mixed_net(d, k, h, shift):
+    """A network whose output is u + shift on rows with u_0 >= 0.3 and is
+    pushed far off (by up to 15 in every coordinate) on rows with u_0 < 0.3:
+    hidden unit 0 is the constant 1 carrying the shift, hidden unit 1 is
+    ReLU(3 - 10 u_0) with output weights 5; the rest are zero."""
+    W1u = np.zeros((h, k))
+    W1u[1, 0] = -10.0
+    b1 = np.zeros(h)
+    b1[0], b1[1] = 1.0, 3.0
+    W2 = np.zeros((k, h))
+    W2[:, 0] = shift
+    W2[:, 1] = 5.0
+    return {"W1a": np.zeros((d, h)), "W1u": W1u, "b1": b1, "W2": W2, "b2": np.zeros(k)}
 
 
 @pytest.mark.parametrize("k,d", [(68, 80), (96, 60), (100, 80)])
 def test_warm_start_taken_in_block_form(env, k, d):
     # k = 68..100: the to-tolerance passes run in the block form (coupling on
     # the matrix cores).  The warm start is u_i^t shifted by the mean
-    # correction towards the exact solutions, so it wins on some rows and not
-    # on others; the oracle predicts which from the same KKT test, the waves
-    # mix warm and cold rows, and every row still reaches the unique
-    # minimiser of its regularised problem (mu > 0).
+    # correction towards the exact solutions on about 70% of the rows and
+    # pushed far off on the others, so it wins on some rows and not on
+    # others; the oracle predicts which from the same KKT test, the waves mix
+    # warm and cold rows, and every row still reaches the unique minimiser
+    # of its regularised problem (mu > 0).
     torch, Bd = env
     m, n, h, t = 700, 500, 32, 0
     warm, M64, Uw, Vw, U0, V0 = _sparse_ctx(env, m, n, k, d, 9, warm_hidden=h, tol=1e-5)
@@ -240,7 +248,7 @@ def test_warm_start_taken_in_block_form(env, k, d):
     G, R = O.gram_and_rhs(A, Bm)
     mu = 1.0 + 1.0 * t
     exact, _ = O.prox_cd_solve(U64, U64, G, R, mu, 0, tol=1e-12, max_sweeps=20000)
-    p = _shift_net(d, k, h, np.mean(exact - U64, axis=0))
+    p = _mixed_net(d, k, h, np.mean(exact - U64, axis=0))
     p = {nm: v.astype(np.float32).astype(np.float64) for nm, v in p.items()}
     y = N.forward(p, sp.csr_matrix(A), U64)[3]
     res_w = O.kkt_residual(y, U64, G, R, mu)
