@@ -166,8 +166,11 @@ def count_sketch(seed, t, side, n, d):
 
 
 def srht_pad(n):
-    """Length of the Hadamard transform of an n-long vector: 2^ceil(log2 n)."""
-    return 1 << max(0, int(n - 1).bit_length())
+    """Length N of the Hadamard transform of an n-long vector: the smallest
+    power of two >= n, and at least 1024.  Any N >= n gives E[S S^T] = I;
+    the paper does not fix it, and the floor keeps one transform size class
+    for all short rows."""
+    return max(1024, 1 << max(0, int(n - 1).bit_length()))
 
 
 def srht_signs(seed, t, side, n):

@@ -175,21 +175,21 @@ def test_hadamard_entries_match_sylvester_construction():
 def test_srht_full_width_is_orthogonal():
     # n = d = N: P is a permutation, S = D H P / sqrt(N) and S S^T = I exactly
     import scipy.linalg
-    N = 32
+    N = 1024
     S = philox.srht_sketch(5, 1, 0, N, N)
     assert np.allclose(S @ S.T, np.eye(N), rtol=0, atol=1e-12)
     p = philox.subsample_indices(5, 1, 0, N, N, kind=philox.KIND_SRHT_SAMPLE)
     assert np.array_equal(p, np.arange(N))
     D = np.diag(philox.srht_signs(5, 1, 0, N))
     assert np.allclose(S, D @ scipy.linalg.hadamard(N) / np.sqrt(N), rtol=0, atol=1e-15)
-    assert philox.srht_pad(1) == 1 and philox.srht_pad(5) == 8 and philox.srht_pad(64) == 64
+    assert philox.srht_pad(1) == 1024 and philox.srht_pad(1025) == 2048 and philox.srht_pad(4096) == 4096
 
 
 def test_srht_entries_from_signs_and_sampled_columns():
     n, d = 13, 5
     S = philox.srht_sketch(9, 4, 1, n, d)
     s = philox.srht_signs(9, 4, 1, n)
-    p = philox.subsample_indices(9, 4, 1, 16, d, kind=philox.KIND_SRHT_SAMPLE)
+    p = philox.subsample_indices(9, 4, 1, philox.srht_pad(n), d, kind=philox.KIND_SRHT_SAMPLE)
     for j in range(n):
         for c in range(d):
             par = bin(j & int(p[c])).count("1") & 1
