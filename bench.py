@@ -61,6 +61,18 @@ WORKLOADS = {
                                       pairs=1_000_000, runs=5, run_iters=20, label_tol=1e-6, tol=1e-4,
                                       max_sweeps=200, epochs=6, batch=4096, lr=1e-4),
 }
+# the further sketch kinds of Sec. 3.4 on the same data shapes
+WORKLOADS["dense-20000x10000-count"] = dict(WORKLOADS["dense-20000x10000"], sketch="count")
+WORKLOADS["dense-20000x10000-srht"] = dict(WORKLOADS["dense-20000x10000"], sketch="srht")
+WORKLOADS["sparse-500000x200000-count"] = dict(WORKLOADS["sparse-500000x200000"], sketch="count")
+# synthetic analogues of the paper's rank sweep and solver comparison
+# (Sec. 5.3): relative objective and time per iteration
+WORKLOADS["sparse-500000x200000-ksweep"] = dict(WORKLOADS["sparse-500000x200000"], kind="ksweep",
+                                                ks=(20, 50, 100, 200, 500), iters=10)
+WORKLOADS["pgd-vs-cd"] = dict(kind="pgd_vs_cd", iters=20,
+                              cases=(dict(name="dense-200x150", m=200, n=150, k=10, d=40, gen="uniform", iters=20),
+                                     dict(name="dense-20000x10000", m=20000, n=10000, k=64, d=1024, gen="planted",
+                                          noise=0.01, noise_relative=False, iters=50)))
 DEFAULT = "dense-50000x20000"
 # the precision form measured to a fixed relative objective (the default)
 TO_EPS = {"dense-50000x20000": dict(kind="to_eps", m=50000, n=20000, k=128, d=4096, iters=30,
@@ -71,6 +83,12 @@ WORKLOADS.update(TO_EPS)
 
 def describe(name, w, K=None):
     iters = K if K is not None else w["iters"]
+    if w["kind"] == "ksweep":
+        return (f"CSR {w['m']}x{w['n']}, {w['nnz']:.0e} nnz text-shaped, subsampling d=d'={w['d']}, prox-CD 1 sweep, "
+                f"k in {list(w['ks'])}, {iters} iterations each")
+    if w["kind"] == "pgd_vs_cd":
+        return "PGD vs prox-CD, relative objective per iteration: " + ", ".join(
+            f"{c['name']} k={c['k']} d={c['d']} ({c['iters']} iterations)" for c in w["cases"])
     if w["kind"] == "to_eps":
         return (f"dense {w['m']}x{w['n']} planted rank-{w['k']} |N(0,1)| factors + {w['noise']:.0%} noise, "
                 f"k={w['k']}, Gaussian sketch d=d'={w['d']}, prox-CD 1 sweep; plain FP32 for {iters} iterations "
@@ -81,13 +99,15 @@ def describe(name, w, K=None):
                 f"prox-CD to tolerance {w['tol']}, MLP warm start [a_i (d); u_i (k)] -> {w['hidden']} -> k "
                 f"trained on {w['pairs']:.0e} pairs from {w['runs']} plain runs, {w['iters']} iterations")
     if w["kind"] == "sparse":
+        kind = "count sketch" if w.get("sketch") == "count" else "subsampling sketch"
         return (f"CSR {w['m']}x{w['n']}, {w['nnz']:.0e} nnz, power-law rows (alpha=1.5), Zipf(1.1) "
-                f"columns, lognormal values, k={w['k']}, subsampling sketch d=d'={w['d']}, "
+                f"columns, lognormal values, k={w['k']}, {kind} d=d'={w['d']}, "
                 f"prox-CD 1 sweep, FP32, {iters} iterations")
     if w["kind"] == "dense":
         gen = ("uniform[0,1)" if w["gen"] == "uniform" else
                f"planted rank-{w['k']} |N(0,1)| factors + noise")
-        return (f"dense {w['m']}x{w['n']} {gen}, k={w['k']}, Gaussian sketch d=d'={w['d']}, "
+        kind = {"count": "count sketch", "srht": "SRHT"}.get(w.get("sketch"), "Gaussian sketch")
+        return (f"dense {w['m']}x{w['n']} {gen}, k={w['k']}, {kind} d=d'={w['d']}, "
                 f"{'prox-CD 1 sweep' if w['solver'] == 'prox_cd' else 'PGD'}, "
                 f"sketch GEMM {w['precision'].upper()}, {iters} iterations")
     return name
@@ -128,6 +148,7 @@ def cpu_baseline(w, M, U0, V0, budget_s=12.0, max_iters=5, Mt=None, half=False):
     except Exception:
         cores = os.cpu_count() or 1
     sketch = O.SKETCH_SUBSAMPLE if w["kind"] == "sparse" else O.SKETCH_GAUSSIAN
+    sketch = {"count": O.SKETCH_COUNT, "srht": O.SKETCH_SRHT}.get(w.get("sketch"), sketch)
     cfg = O.Config(k=w["k"], d=w["d"], d_prime=w["d"], sketch=sketch, solver=w["solver"])
     M64 = M.astype(np.float64)
     Mt64 = Mt.astype(np.float64) if Mt is not None else None
@@ -492,6 +513,96 @@ def run_to_eps(args, w, torch, B, K, W):
     return out, keepM
 
 
+def run_ksweep(args, w, torch, B, K, W):
+    """Rank sweep on the text-shaped CSR workload (the synthetic analogue of
+    the paper's k sweep): per k, iterations/s, NNLS rows/s, the relative
+    objective after each iteration and its cumulative time."""
+    m, n, d = w["m"], w["n"], w["d"]
+    dev = torch.device("cuda", 0)
+    print("[bench] generating data", file=sys.stderr, flush=True)
+    M, Mt, _, _ = make_sparse(dict(w, k=1), args.seed)
+    to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a.astype(dt))).to(dev)
+    keep = [to(M.indptr, np.int64), to(M.indices, np.int32), to(M.data, np.float32),
+            to(Mt.indptr, np.int64), to(Mt.indices, np.int32), to(Mt.data, np.float32)]
+    mat = B.csr_matrix(*keep)
+    from paper_2009_02845_amd import synth
+    res = []
+    for k in w["ks"]:
+        U0, V0 = synth.init_factors(m, n, k, args.seed)
+        U0d, V0d = torch.from_numpy(U0).to(dev), torch.from_numpy(V0).to(dev)
+        U, V = U0d.clone(), V0d.clone()
+        cfg = B.make_config(m, n, k, d, d, sketch="subsample", solver="prox_cd", sweeps=1, alpha=1.0, beta=1.0,
+                            seed=0)
+        solver = B.Solver(cfg, mat, U, V, tensors=keep)
+        for t in range(W):
+            solver.iteration(t)
+        torch.cuda.synchronize()
+        solver.set_timing(True)
+        times, objs = [], []
+        U.copy_(U0d)
+        V.copy_(V0d)
+        torch.cuda.synchronize()
+        for t in range(K):
+            t0 = time.perf_counter()
+            solver.iteration(t)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            objs.append(solver.objective())
+        solver.set_timing(False)
+        tm = solver.timing()
+        nnls_s = tm["nnls_ms"] / 1e3
+        # the NNLS sweep: 12 k bytes and 2 k^2 flop per row
+        nnls_avg = nnls_s / tm["launches"]
+        flops = 2.0 * k * k * (m + n) / 2
+        nbytes = 12.0 * k * (m + n) / 2
+        block = k > 128 or (k % 4 == 0 and 64 < k <= 100)
+        kern = "prox_cd_wide_kernel" if k > 128 else ("prox_cd_mfma_kernel" if block else "prox_cd_lds_kernel")
+        peak_f = PEAK["fp32_mfma_tflops"] if block else PEAK["fp32_valu_tflops"]
+        res.append({"k": k, "iterations_per_s": K / sum(times), "ms_per_step": 1e3 * sum(times) / K,
+                    "nnls_rows_per_s": (m + n) * K / nnls_s,
+                    "phase_ms_per_step": {p: tm[p + "_ms"] / K for p in ("sketch", "product", "small", "nnls")},
+                    "rel_objective": objs, "cumulative_time_s": [float(x) for x in np.cumsum(times)],
+                    "nnls_kernel": kern, "nnls_avg_launch_ms": nnls_avg * 1e3,
+                    "nnls_tflops": flops / nnls_avg / 1e12, "nnls_frac_of_peak": flops / nnls_avg / 1e12 / peak_f,
+                    "nnls_peak": "fp32 mfma" if block else "fp32 valu",
+                    "nnls_gbs": nbytes / nnls_avg / 1e9})
+        print(f"[bench] k={k}: {res[-1]['iterations_per_s']:.1f} it/s, objective {objs[-1]:.4f}", file=sys.stderr,
+              flush=True)
+        solver.close()
+        del solver, U, V, U0d, V0d
+    main_k = [r for r in res if r["k"] == 100] or res
+    return {"value": main_k[0]["iterations_per_s"], "ms_per_step": main_k[0]["ms_per_step"], "k_sweep": res}
+
+
+def run_pgd_vs_cd(args, w, torch, B, W):
+    """PGD and prox-CD on the same data, seeds and sketches: relative
+    objective after every iteration (the synthetic analogue of the paper's
+    solver comparison)."""
+    dev = torch.device("cuda", 0)
+    out = []
+    for c in w["cases"]:
+        m, n, k, d = c["m"], c["n"], c["k"], c["d"]
+        M, U0, V0 = make_dense(dict(c, kind="dense"), args.seed)
+        Md = torch.from_numpy(M).to(dev)
+        U0d, V0d = torch.from_numpy(U0).to(dev), torch.from_numpy(V0).to(dev)
+        entry = {"case": c["name"], "m": m, "n": n, "k": k, "d": d}
+        for solver_name in ("pgd", "prox_cd"):
+            U, V = U0d.clone(), V0d.clone()
+            cfg = B.make_config(m, n, k, d, d, sketch="gaussian", solver=solver_name, sweeps=1, alpha=1.0, beta=1.0,
+                                seed=0)
+            solver = B.Solver(cfg, B.dense_matrix(Md), U, V, tensors=[Md])
+            for t in range(W):
+                solver.iteration(t)
+            times, objs = _timed_run(solver, U, V, U0d, V0d, torch, c["iters"], stop_at=-1.0)
+            entry[solver_name] = {"rel_objective": objs, "cumulative_time_s": [float(x) for x in np.cumsum(times)],
+                                  "iterations_per_s": len(times) / sum(times)}
+            solver.close()
+        print(f"[bench] {c['name']}: PGD {entry['pgd']['rel_objective'][-1]:.4f}, prox-CD "
+              f"{entry['prox_cd']['rel_objective'][-1]:.4f}", file=sys.stderr, flush=True)
+        out.append(entry)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -528,6 +639,25 @@ def main():
     w = WORKLOADS[args.workload]
     K = args.steps if args.steps is not None else w["iters"]
     W = args.warmup
+    if w["kind"] == "ksweep":
+        r = run_ksweep(args, w, torch, B, K, W)
+        out = {"metric": "sketched-ANLS iterations/s across ranks k (relative objective per iteration)",
+               "unit": "iterations/s", "n_gpus": 1, "steps": K, "warmup": W, "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": describe(args.workload, w, K), "m": w["m"], "n": w["n"], "d": w["d"],
+                          "iterations": K, "parallelism": "single GPU"}}
+        out.update(r)
+        print(json.dumps(out), flush=True)
+        return
+    if w["kind"] == "pgd_vs_cd":
+        r = run_pgd_vs_cd(args, w, torch, B, W)
+        out = {"metric": "relative objective per iteration, PGD vs prox-CD", "unit": "relative error",
+               "n_gpus": 1, "steps": None, "warmup": W, "higher_is_better": False, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": describe(args.workload, w), "parallelism": "single GPU"},
+               "value": r[-1]["prox_cd"]["rel_objective"][-1], "cases": r}
+        print(json.dumps(out), flush=True)
+        return
     if w["kind"] == "to_eps":
         r, (M, U0, V0) = run_to_eps(args, w, torch, B, K, W)
         out = {"metric": "sketched-ANLS iterations/s (and NNLS rows/s) to a fixed relative objective, "
@@ -562,14 +692,14 @@ def main():
         Md = torch.from_numpy(M).to(dev)
         keep = [Md]
         mat = B.dense_matrix(Md)
-        sketch = "gaussian"
+        sketch = w.get("sketch", "gaussian")
     else:
         M, Mt, U0, V0 = make_sparse(w, args.seed)
         to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a.astype(dt))).to(dev)
         keep = [to(M.indptr, np.int64), to(M.indices, np.int32), to(M.data, np.float32),
                 to(Mt.indptr, np.int64), to(Mt.indices, np.int32), to(Mt.data, np.float32)]
         mat = B.csr_matrix(*keep)
-        sketch = "subsample"
+        sketch = w.get("sketch", "subsample")
     U0d, V0d = torch.from_numpy(U0).to(dev), torch.from_numpy(V0).to(dev)
     U, V = U0d.clone(), V0d.clone()
     cfg = B.make_config(m, n, k, d, d, sketch=sketch, solver=w["solver"], precision=w["precision"],
@@ -595,7 +725,22 @@ def main():
     rel = solver.objective()
     its = K / el
     launches = 2 * K
-    if w["kind"] == "dense":
+    if w["kind"] == "dense" and w.get("sketch") in ("count", "srht"):
+        # HBM-bound sketch products, one per half-iteration: the count sketch
+        # reads X^T once and writes A^T, then transposes it (A read and
+        # written); the SRHT reads X once and writes A
+        prod_avg_s = tm["product_ms"] / 1e3 / launches
+        per_side = []
+        for rows, lng in ((m, n), (n, m)):
+            extra = 3 if w["sketch"] == "count" else 1
+            per_side.append(4.0 * rows * lng + extra * 4.0 * rows * d)
+        nbytes = sum(per_side) / 2
+        achieved = nbytes / prod_avg_s / 1e9
+        name = ("cs_rows_kernel + transpose_kernel" if w["sketch"] == "count" else "srht_rows_kernel")
+        roof = {"kernel": f"sketch product A = X S ({name}, one per half-iteration)", "bound": "hbm",
+                "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": achieved / PEAK["hbm_gbs"],
+                "traffic": None, "bytes_per_launch": nbytes, "avg_launch_ms": prod_avg_s * 1e3}
+    elif w["kind"] == "dense":
         # one grouped launch per iteration computes A = M S (m x n x d) and
         # A' = M^T S' (n x m x d'); the V side reuses A'
         prod_avg_s = tm["product_ms"] / 1e3 / K

@@ -52,11 +52,24 @@ typedef enum {
 } dsanls_status;
 
 /* Kind of random sketch (Sec. 3.4).  IDENTITY (S = I, needs d = n and
- * d' = m) turns the method into exact-product ANLS and is meant for tests. */
+ * d' = m) turns the method into exact-product ANLS and is meant for tests.
+ * COUNT and SRHT are the further kinds the last paragraph of Sec. 3.4 names
+ * (both satisfy Assumption 1, E[S S^T] = I):
+ *   COUNT: row j of S has one nonzero s_j = +-1 in column h_j (uniform over
+ *          d); A = M S costs one pass over M (dense or CSR).  Needs
+ *          d >= n_global / 1024 (and d' >= m_global / 1024).
+ *   SRHT:  S[j, c] = s_j H[j, p_c] / sqrt(d), H the Sylvester Hadamard matrix
+ *          of order N = max(1024, 2^ceil(log2 n_global)), p the d sampled
+ *          columns of H (without replacement).  Dense input, N <= 32768.
+ * Signs, buckets and sampled columns come from Philox counters
+ * (0, j, side | kind << 8, t) with kind 2 (count), 3 (SRHT signs) and 4
+ * (SRHT columns, the subsampling rule over N). */
 typedef enum {
   DSANLS_SKETCH_GAUSSIAN = 0,   /* i.i.d. N(0, 1/d) entries                   */
   DSANLS_SKETCH_SUBSAMPLE = 1,  /* d columns e_j without replacement, x sqrt(n/d) */
-  DSANLS_SKETCH_IDENTITY = 2
+  DSANLS_SKETCH_IDENTITY = 2,
+  DSANLS_SKETCH_COUNT = 3,      /* count sketch                               */
+  DSANLS_SKETCH_SRHT = 4        /* subsampled randomised Hadamard transform   */
 } dsanls_sketch;
 
 /* Subproblem solver (Sec. 3.5). */
@@ -175,8 +188,10 @@ dsanls_status dsanls_workspace_bytes(const dsanls_config* cfg, const dsanls_matr
  * Errors: INVALID_ARG (null pointers, alpha/beta < 0, alpha = mu_0 = 0
  * outside to-tolerance mode, bad enums), SHAPE (sizes, a block outside the
  * global matrix, d > n_global for subsampling, d != n for identity),
- * WORKSPACE, UNSUPPORTED (Gaussian sketch on CSR input, BF16 on CSR input,
- * k > 128), HIP.  NONFINITE: M, U or V holds NaN or Inf.
+ * WORKSPACE, UNSUPPORTED (Gaussian or SRHT sketch on CSR input, BF16 on
+ * CSR input or with a sketch other than Gaussian, the size limits of COUNT
+ * and SRHT above, k > 512, k > 128 with PGD, to-tolerance sweeps or a warm
+ * start), HIP.  NONFINITE: M, U or V holds NaN or Inf.
  */
 dsanls_status dsanls_init(const dsanls_config* cfg, const dsanls_matrix* M, float* U, float* V,
                           void* workspace, size_t workspace_bytes, void* hip_stream,
@@ -339,8 +354,9 @@ dsanls_status dsanls_mlp_train_step(int32_t d, int32_t k, int32_t hidden, float*
  * of G is used for coordinate j) and R (rows x k).  sweeps >= 1: exactly
  * that many; sweeps = 0: until the relative KKT residual
  * ||pg|| / ||r_i + mu c_i|| <= tol or max_sweeps.  sweeps_used (device
- * int32[rows]) may be NULL.  upper > 0 clips entries to upper.  1 <= k <= 128
- * (else UNSUPPORTED).  workspace: device memory of
+ * int32[rows]) may be NULL.  upper > 0 clips entries to upper.  1 <= k <= 512
+ * (else UNSUPPORTED); above 128 only fixed sweeps (sweeps >= 1), in blocks
+ * of 16 coordinates coupled on the matrix cores.  workspace: device memory of
  * dsanls_nnls_workspace_bytes(k) bytes for the prepared Gram.  A row whose
  * right-hand side, centre, start or Gram entries are not finite is written
  * as NaN in every entry (never projected to 0); the call is asynchronous and

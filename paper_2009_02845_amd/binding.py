@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdsanls.so")
 
-SKETCH = {"gaussian": 0, "subsample": 1, "identity": 2}
+SKETCH = {"gaussian": 0, "subsample": 1, "identity": 2, "count": 3, "srht": 4}
 SOLVER = {"prox_cd": 0, "pgd": 1}
 PRECISION = {"fp32": 0, "bf16": 1}
 DENSE, CSR = 0, 1

@@ -26,7 +26,9 @@ dsanls_status hip_fail(hipError_t e, const char* what) {
 
 namespace {
 
-constexpr int64_t kMaxRank = 128;
+// Largest rank: 512 (ranks above 128 take the wide NNLS kernel, fixed
+// prox-CD sweeps only)
+constexpr int64_t kMaxRank = kNnlsMaxRankWide;
 
 int64_t r4(int64_t x) { return (x + 3) / 4 * 4; }
 int64_t r8(int64_t x) { return (x + 7) / 8 * 8; }
@@ -69,6 +71,16 @@ struct Layout {
   float* a_vals[2] = {nullptr, nullptr};
   int32_t* scan_ws[2] = {nullptr, nullptr};
   float* ustart = nullptr;          // warm start, rows x k
+  // count sketch: per side the hash and bucket lists; At (d x rows, the
+  // product before its transpose) and Bt (d x k) shared by the sides
+  CountSketch cs[2];
+  float* At = nullptr;
+  int64_t ldat = 0;
+  float* Bt = nullptr;
+  // SRHT: per side the signs and the sampled Hadamard columns
+  float* hsign[2] = {nullptr, nullptr};
+  int32_t* hcol[2] = {nullptr, nullptr};
+  int64_t hlen[2] = {0, 0};          // transform length N of each side
   // segment tables of CSR(M) (side 0) and CSR(M^T) (side 1), partial sums
   CsrSegments seg[2];
   int64_t seg_cap[2] = {0, 0}, multi_cap[2] = {0, 0};
@@ -111,6 +123,8 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
   const bool is_dense = dense(&M);
   const bool gauss = c.sketch == DSANLS_SKETCH_GAUSSIAN;
   const bool sub = c.sketch == DSANLS_SKETCH_SUBSAMPLE;
+  const bool count = c.sketch == DSANLS_SKETCH_COUNT;
+  const bool srht = c.sketch == DSANLS_SKETCH_SRHT;
   const bool bf16 = c.precision == DSANLS_PREC_BF16_SKETCH;
   if (is_dense && M.dense_t == nullptr) {
     L.ldmt = r4(m);
@@ -129,8 +143,34 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
       L.St[sd] = reinterpret_cast<float*>(take(sizeof(float) * side_d[sd] * r4(side_lng[sd])));
       if (bf16) L.Sb[sd] = reinterpret_cast<__hip_bfloat16*>(take(2 * side_d[sd] * r32(side_lng[sd])));
     }
-    if (is_dense && (gauss || sub))
+    if (is_dense && (gauss || sub || count || srht))
       L.A[sd] = reinterpret_cast<float*>(take(sizeof(float) * side_rows[sd] * r4(side_d[sd])));
+    if (count) {
+      const int64_t lng = side_lng[sd], dd = side_d[sd];
+      CountSketch& q = L.cs[sd];
+      q.bucket = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * lng));
+      q.sign = reinterpret_cast<float*>(take(sizeof(float) * lng));
+      q.cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2 * (dd + 1)));
+      q.off = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (dd + 1)));
+      q.scan_ws = reinterpret_cast<int32_t*>(take(scan_ws_bytes(dd)));
+      q.tmp = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * lng));
+      q.list = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * lng));
+    }
+    if (srht) {
+      L.hsign[sd] = reinterpret_cast<float*>(take(sizeof(float) * side_lng[sd]));
+      L.hcol[sd] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * side_d[sd]));
+    }
+  }
+  if (count) {
+    L.ldat = r4(rowsmax);
+    if (is_dense) L.At = reinterpret_cast<float*>(take(sizeof(float) * dmax * L.ldat));
+    L.Bt = reinterpret_cast<float*>(take(sizeof(float) * dmax * k));
+  }
+  if (srht) {
+    L.hlen[0] = srht_length(n_glob(c));
+    L.hlen[1] = srht_length(m_glob(c));
+    L.sub_ws_bytes = subsample_ws_bytes(std::max(L.hlen[0], L.hlen[1]));
+    for (int sd = 0; sd < 2; ++sd) L.sub_ws[sd] = take(L.sub_ws_bytes);
   }
   L.Wt = reinterpret_cast<float*>(take(sizeof(float) * k * r4(lngmax)));
   L.B = reinterpret_cast<float*>(take(sizeof(float) * k * r4(dmax)));
@@ -199,6 +239,7 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
   L.partials = reinterpret_cast<float*>(take(sizeof(float) * 4 * np));
   L.red = reinterpret_cast<float*>(take(sizeof(float) * 64));
   L.err = reinterpret_cast<int*>(take(sizeof(int) * 16));
+  for (int sd = 0; sd < 2; ++sd) L.cs[sd].err = L.err + 1;
   L.counters = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * 8));
   L.tol.counters = L.counters;
   if (c.solver == DSANLS_SOLVER_PROX_CD && c.sweeps == 0) {
@@ -221,9 +262,13 @@ dsanls_status validate(const dsanls_config* c, const dsanls_matrix* M) {
   if (!c || !M) return fail(DSANLS_E_INVALID_ARG, "config or matrix is NULL");
   if (c->m < 1 || c->n < 1 || c->k < 1 || c->d < 1 || c->d_prime < 1)
     return fail(DSANLS_E_SHAPE, "m, n, k, d, d_prime must be >= 1");
-  if (c->k > kMaxRank) return fail(DSANLS_E_UNSUPPORTED, "k > 128 is not supported");
+  if (c->k > kMaxRank) return fail(DSANLS_E_UNSUPPORTED, "k > 512 is not supported");
+  if (c->k > kNnlsMaxRank && !(c->solver == DSANLS_SOLVER_PROX_CD && c->sweeps >= 1))
+    return fail(DSANLS_E_UNSUPPORTED, "ranks above 128 support prox-CD with a fixed number of sweeps only");
+  if (c->k > kNnlsMaxRank && c->warm_hidden > 0)
+    return fail(DSANLS_E_UNSUPPORTED, "the warm start supports ranks up to 128");
   if (c->m > INT32_MAX || c->n > INT32_MAX) return fail(DSANLS_E_SHAPE, "m and n must fit int32");
-  if (c->sketch < 0 || c->sketch > 2) return fail(DSANLS_E_INVALID_ARG, "bad sketch kind");
+  if (c->sketch < 0 || c->sketch > 4) return fail(DSANLS_E_INVALID_ARG, "bad sketch kind");
   if (c->solver < 0 || c->solver > 1) return fail(DSANLS_E_INVALID_ARG, "bad solver");
   if (c->precision < 0 || c->precision > 1) return fail(DSANLS_E_INVALID_ARG, "bad precision");
   if (c->row_offset < 0 || c->col_offset < 0 || c->m_global < 0 || c->n_global < 0)
@@ -237,6 +282,18 @@ dsanls_status validate(const dsanls_config* c, const dsanls_matrix* M) {
     return fail(DSANLS_E_SHAPE, "identity sketch needs d == n and d_prime == m");
   if (c->sketch == DSANLS_SKETCH_IDENTITY && is_share(*c))
     return fail(DSANLS_E_UNSUPPORTED, "identity sketch applies to the whole matrix only");
+  if (c->sketch == DSANLS_SKETCH_COUNT && (c->d * 1024 < n_glob(*c) || c->d_prime * 1024 < m_glob(*c)))
+    return fail(DSANLS_E_UNSUPPORTED, "count sketch needs d >= n_global / 1024 and d_prime >= m_global / 1024 "
+                                      "(bucket lists of at most a few thousand rows)");
+  if (c->sketch == DSANLS_SKETCH_SRHT) {
+    if (M->format != DSANLS_DENSE) return fail(DSANLS_E_UNSUPPORTED, "SRHT applies to dense input only");
+    if (srht_length(n_glob(*c)) > 32768 || srht_length(m_glob(*c)) > 32768)
+      return fail(DSANLS_E_UNSUPPORTED, "SRHT supports m_global, n_global <= 32768 (the transform runs in LDS)");
+    if (c->d > srht_length(n_glob(*c)) || c->d_prime > srht_length(m_glob(*c)))
+      return fail(DSANLS_E_SHAPE, "SRHT needs d <= N = max(1024, 2^ceil(log2 n_global)), and d_prime likewise");
+  }
+  if ((c->sketch == DSANLS_SKETCH_COUNT || c->sketch == DSANLS_SKETCH_SRHT) && c->precision != DSANLS_PREC_FP32)
+    return fail(DSANLS_E_UNSUPPORTED, "the BF16 form applies to the Gaussian sketch GEMM only");
   if (c->sketch == DSANLS_SKETCH_GAUSSIAN && std::max(c->d, c->d_prime) > 4 * 65535)
     return fail(DSANLS_E_SHAPE, "Gaussian sketch supports d <= 262140");
   if (c->warm_hidden < 0 || c->warm_hidden > 4096) return fail(DSANLS_E_INVALID_ARG, "warm_hidden out of range");
@@ -262,8 +319,8 @@ dsanls_status validate(const dsanls_config* c, const dsanls_matrix* M) {
   } else if (M->format == DSANLS_CSR) {
     if (!M->rowptr || !M->t_rowptr || M->nnz < 0 || (M->nnz > 0 && (!M->colidx || !M->vals || !M->t_colidx || !M->t_vals)))
       return fail(DSANLS_E_INVALID_ARG, "CSR M: CSR(M) and CSR(M^T) arrays are required");
-    if (c->sketch == DSANLS_SKETCH_GAUSSIAN)
-      return fail(DSANLS_E_UNSUPPORTED, "Gaussian sketch on CSR input is not supported");
+    if (c->sketch == DSANLS_SKETCH_GAUSSIAN || c->sketch == DSANLS_SKETCH_SRHT)
+      return fail(DSANLS_E_UNSUPPORTED, "Gaussian and SRHT sketches on CSR input are not supported");
     if (c->precision != DSANLS_PREC_FP32)
       return fail(DSANLS_E_UNSUPPORTED, "BF16 sketch applies to dense input only");
   } else {
@@ -405,7 +462,8 @@ dsanls_status report_flags(dsanls_ctx* ctx, const int* err, const char* where) {
   DSANLS_HIP(hipMemsetAsync(ctx->L.err, 0, 3 * sizeof(int), ctx->stream));
   if (err[0]) return fail(DSANLS_E_NONFINITE, std::string(where) + ": non-finite values in U, V or the residual");
   if (err[1] | err[2])
-    return fail(DSANLS_E_INTERNAL, std::string(where) + ": a subsample selection failed (boundary bucket over capacity)");
+    return fail(DSANLS_E_INTERNAL, std::string(where) + ": a subsample selection or a count-sketch bucket list "
+                                                        "exceeded its capacity");
   return DSANLS_OK;
 }
 
@@ -507,6 +565,39 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
     }
     CHECK(mark(ctx, kPhSmall));
     CHECK(launch_gather_rows_t(Wother, k, idx_b, d, scale, L.B, ldb, s));
+  } else if (c.sketch == DSANLS_SKETCH_COUNT) {
+    // hash and bucket lists of this side's rows of S (global row indices),
+    // then A^T = S^T X^T bucket by bucket (reads X once) and B^T = S^T W
+    const CountSketch& q = L.cs[side];
+    CHECK(mark(ctx, kPhSketch));
+    CHECK(launch_count_sketch_hash(c.seed, tt, side, off, lng, d, L.cs[side], s));
+    CHECK(mark(ctx, kPhSketch));
+    if (is_dense) {
+      const float* Xt = side == 0 ? ctx->Mt : ctx->mat.dense;
+      const int64_t ldxt = side == 0 ? ctx->ldmt : ctx->mat.ld;
+      CHECK(mark(ctx, kPhProduct));
+      CHECK(launch_count_sketch_rows(Xt, ldxt, rows, d, q, L.At, L.ldat, s));
+      CHECK(launch_transpose(L.At, L.ldat, L.A[side], lda, d, rows, s));
+      CHECK(mark(ctx, kPhProduct));
+    }
+    CHECK(mark(ctx, kPhSmall));
+    CHECK(launch_count_sketch_rows(Wother, k, k, d, q, L.Bt, k, s));
+    CHECK(launch_transpose(L.Bt, k, L.B, ldb, d, k, s));
+  } else if (c.sketch == DSANLS_SKETCH_SRHT) {
+    // signs of this side's rows and the d sampled Hadamard columns, then
+    // A = X S and B = W^T S by one transform per row
+    const int64_t N = L.hlen[side];
+    CHECK(mark(ctx, kPhSketch));
+    CHECK(launch_srht_signs(c.seed, tt, side, off, lng, L.hsign[side], s));
+    CHECK(launch_subsample(c.seed, tt, side, N, d, L.hcol[side], nullptr, L.sub_ws[side], L.sub_ws_bytes, L.err + 1,
+                           s, 0, 0, nullptr, kSrhtSampleKind));
+    CHECK(mark(ctx, kPhSketch));
+    CHECK(mark(ctx, kPhProduct));
+    CHECK(launch_srht_rows(X, ldx, rows, lng, off, N, L.hsign[side], L.hcol[side], d, L.A[side], lda, s));
+    CHECK(mark(ctx, kPhProduct));
+    CHECK(mark(ctx, kPhSmall));
+    CHECK(launch_transpose(Wother, k, L.Wt, ldw, lng, k, s));
+    CHECK(launch_srht_rows(L.Wt, ldw, k, lng, off, N, L.hsign[side], L.hcol[side], d, L.B, ldb, s));
   } else {
     // identity: A = X, B = W^T
     CHECK(mark(ctx, kPhSmall));
@@ -543,6 +634,10 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
                          L.long_rows[side], L.nlong[side], L.R,
                          s));
       ctx->rows_kept = rows;
+    } else if (c.sketch == DSANLS_SKETCH_COUNT) {
+      // the CSR stream, each entry (i, j) adding M_ij s_j B^T[h_j, :]
+      CHECK(launch_csr_rhs_seg(rowptr, colidx, vals, L.seg[side], nullptr, L.Bt, k, 1.0f, L.R, L.seg_partials, s,
+                               L.cs[side].bucket, L.cs[side].sign));
     } else {
       // the CSR stream: every nnz of X, the sampled ones (or all, identity)
       // folded into R
@@ -924,7 +1019,7 @@ dsanls_status dsanls_debug_fetch(dsanls_ctx* ctx, int32_t which, void* dst, size
       if (c.sketch == DSANLS_SKETCH_GAUSSIAN)
         return copy2d(ctx->L.St[ctx->last_side], ctx->last_lds, d, lng, sizeof(float));
       if (c.sketch == DSANLS_SKETCH_SUBSAMPLE) return copy2d(ctx->L.idx[ctx->last_side], d, 1, d, sizeof(int32_t));
-      return fail(DSANLS_E_UNSUPPORTED, "debug_fetch: identity sketch has no stored S");
+      return fail(DSANLS_E_UNSUPPORTED, "debug_fetch: S is stored for the Gaussian and subsampling sketches only");
     case 1:
       if (!ctx->last_A) return fail(DSANLS_E_UNSUPPORTED, "debug_fetch: A is not formed on the CSR path");
       return copy2d(ctx->last_A, ctx->last_lda, rows, d, sizeof(float));

@@ -48,10 +48,45 @@ size_t subsample_ws_bytes(int64_t n);
 // idx[d] ascending; slot (may be null) gets slot[j] = column of index j or -1.
 // idx_win (may be null): idx[c] - win_off where that lies in [0, win_len),
 // else -1 (the sampled columns seen by a block of the long dimension).
+// kind selects the counter stream (1: the subsampling sketch, 4: the SRHT's
+// sampled Hadamard columns).
+constexpr uint32_t kSrhtSampleKind = 4;
 dsanls_status launch_subsample(uint64_t seed, uint32_t t, int side, int64_t n, int64_t d,
                                int32_t* idx, int32_t* slot, void* ws, size_t ws_bytes,
                                int* err_flag, hipStream_t s, int64_t win_off = 0, int64_t win_len = 0,
-                               int32_t* idx_win = nullptr);
+                               int32_t* idx_win = nullptr, uint32_t kind = 1);
+
+// ---------------------------------------------------------------- sketches.hip
+// Count sketch of one side: bucket h_j and sign s_j of each row j of S (n
+// rows, global index j0 + j), bucket offsets off[d + 1] and the rows of
+// each bucket in ascending order (list); cnt holds 2 (d + 1) ints (counts,
+// cursors), tmp n ints, scan_ws scan_ws_bytes(d); a bucket over the
+// ordering kernel's capacity sets bit 4 of *err.
+struct CountSketch {
+  int32_t* bucket = nullptr;
+  float* sign = nullptr;
+  int32_t* cnt = nullptr;
+  int32_t* off = nullptr;
+  int32_t* scan_ws = nullptr;
+  int32_t* tmp = nullptr;
+  int32_t* list = nullptr;
+  int* err = nullptr;
+};
+dsanls_status launch_count_sketch_hash(uint64_t seed, uint32_t t, int side, int64_t j0, int64_t n, int64_t d,
+                                       const CountSketch& cs, hipStream_t s);
+// Out (d x cols, ldo) = S^T X^T for X^T (n x cols, ldx): bucket sums of the
+// signed rows of X^T.
+dsanls_status launch_count_sketch_rows(const float* Xt, int64_t ldx, int64_t cols, int64_t d, const CountSketch& cs,
+                                       float* Out, int64_t ldo, hipStream_t s);
+// SRHT: transform length N = max(1024, 2^ceil(log2 n)); signs of rows
+// j0 .. j0 + n - 1; Out (rows x d) = X S for the rows of X (rows x lng, a
+// block starting at global column j0), p the d sampled Hadamard columns.
+int64_t srht_length(int64_t n);
+dsanls_status launch_srht_signs(uint64_t seed, uint32_t t, int side, int64_t j0, int64_t n, float* sign,
+                                hipStream_t s);
+dsanls_status launch_srht_rows(const float* X, int64_t ldx, int64_t rows, int64_t lng, int64_t j0, int64_t N,
+                               const float* sign, const int32_t* p, int64_t d, float* Out, int64_t ldo,
+                               hipStream_t s);
 
 // ---------------------------------------------------------------- gemm.hip
 // C[rows x cols] = X[rows x K] * Y[cols x K]^T, FP32 MFMA.
@@ -120,6 +155,14 @@ dsanls_status launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, 
 constexpr int kNnlsMaxRank = 128;
 constexpr size_t nnls_prep_floats(int KC) { return static_cast<size_t>(KC) * KC + 4 * static_cast<size_t>(KC) + 64; }
 size_t nnls_ws_bytes(int k);
+// Ranks 129 .. 512 (fixed prox-CD sweeps): the wide kernel's padded rank
+// (0 past the largest) and its launch on the prepared Gram gp (KC x KC, row j
+// = column j of G, zero diagonal) and inv (1 / (G_jj + mu), zero padding).
+constexpr int kNnlsMaxRankWide = 512;
+int nnls_kc_wide(int k);
+dsanls_status launch_prox_cd_wide(const float* gp, const float* inv, int KC, const float* R, const float* C, float* U,
+                                  int64_t rows, int k, float mu, int sweeps, float upper, int32_t* sweeps_used,
+                                  hipStream_t s);
 // Workspace of the to-tolerance mode's compacted passes (rows = the most
 // rows of any update; nw = ceil(rows / 64)): per-row sweep counts and flags,
 // per-wave pending counts (nw), their scan (nw + 1), pending rows per wave
@@ -191,9 +234,12 @@ dsanls_status launch_sketched_rows(const int64_t* rowptr, const int32_t* colidx,
                                    int64_t rows, const CsrSegments& sg, const int32_t* slot, float scale,
                                    int32_t* seg_cnt, int32_t* seg_pos, int32_t* scan_ws,
                                    int32_t* a_rowptr, int32_t* a_cols, float* a_vals, hipStream_t s);
+// hbucket/hsign (count sketch): W is then B^T (d x k), read at the bucket of
+// each entry's column, the entry scaled by the column's sign.
 dsanls_status launch_csr_rhs_seg(const int64_t* rowptr, const int32_t* colidx, const float* vals,
                                  const CsrSegments& sg, const int32_t* slot, const float* W, int64_t k,
-                                 float scale, float* R, float* P, hipStream_t s);
+                                 float scale, float* R, float* P, hipStream_t s,
+                                 const int32_t* hbucket = nullptr, const float* hsign = nullptr);
 // R[i, :] = scale * sum_{e in row i, slot[col_e] >= 0} val_e * W[col_e, :]
 // (slot == nullptr: every column).  CSR rows x ncols, W is ncols x k.
 dsanls_status launch_csr_sketch_rhs(const int64_t* rowptr, const int32_t* colidx,

@@ -1441,16 +1441,34 @@ int nnls_kc(int k) {
 constexpr int kMaxK = kNnlsMaxRank;
 
 size_t nnls_ws_bytes(int k) {
-  const int kc = nnls_kc(k < 1 ? 1 : k);
+  const int kc = k > kMaxK ? nnls_kc_wide(k) : nnls_kc(k < 1 ? 1 : k);
   return sizeof(float) * prep_floats(kc > 0 ? kc : kMaxKC);
 }
+
+namespace {
+
+// Ranks 129 .. kNnlsMaxRankWide: the Gram prepared at the padded rank of the
+// wide kernel (fixed sweeps of prox-CD only).
+dsanls_status run_wide(bool pgd, const float* G, const float* R, const float* C, float* U, int64_t rows, int k,
+                       float mu, int sweeps, float upper, int32_t* sweeps_used, void* ws, hipStream_t s) {
+  if (pgd || sweeps < 1)
+    return fail(DSANLS_E_UNSUPPORTED, "ranks above 128 support prox-CD with a fixed number of sweeps only");
+  const int KC = nnls_kc_wide(k);
+  Prep p = carve_prep(ws, KC);
+  prep_kernel<<<KC, 64, 0, s>>>(G, k, KC, mu, p.gp, p.gdiag, p.den, p.inv, p.colsum);
+  DSANLS_LAUNCHED("prep_kernel");
+  return launch_prox_cd_wide(p.gp, p.inv, KC, R, C, U, rows, k, mu, sweeps, upper, sweeps_used, s);
+}
+
+}  // namespace
 
 dsanls_status launch_nnls(bool pgd, const float* G, const float* R, const float* C, float* U,
                           int64_t rows, int k, float mu, int sweeps, float tol, int max_sweeps,
                           float upper, int32_t* sweeps_used, const TolWork* tw, void* ws,
                           size_t ws_bytes, hipStream_t s, const float* start) {
-  if (k < 1 || k > kMaxK) return fail(DSANLS_E_UNSUPPORTED, "NNLS supports 1 <= k <= 128");
+  if (k < 1 || k > kNnlsMaxRankWide) return fail(DSANLS_E_UNSUPPORTED, "NNLS supports 1 <= k <= 512");
   if (ws_bytes < nnls_ws_bytes(k)) return fail(DSANLS_E_WORKSPACE, "NNLS workspace too small");
+  if (k > kMaxK) return run_wide(pgd, G, R, C, U, rows, k, mu, sweeps, upper, sweeps_used, ws, s);
   switch (nnls_kc(k)) {
 #define DSANLS_KC(KC, W, SW)                                                                         \
   case KC:                                                                                           \
@@ -1476,7 +1494,7 @@ dsanls_status launch_nnls(bool pgd, const float* G, const float* R, const float*
 using namespace dsanls;
 
 extern "C" size_t dsanls_nnls_workspace_bytes(int32_t k) {
-  return k < 1 || k > kMaxK ? 0 : align_up(nnls_ws_bytes(k), 256);
+  return k < 1 || k > kNnlsMaxRankWide ? 0 : align_up(nnls_ws_bytes(k), 256);
 }
 
 extern "C" dsanls_status dsanls_nnls_prox_cd(const float* G, const float* R, const float* C,

@@ -386,13 +386,13 @@ __global__ void sub_window_kernel(const int32_t* __restrict__ idx, int64_t d, in
 dsanls_status launch_subsample(uint64_t seed, uint32_t t, int side, int64_t n, int64_t d,
                                int32_t* idx, int32_t* slot, void* ws, size_t ws_bytes,
                                int* err_flag, hipStream_t s, int64_t win_off, int64_t win_len,
-                               int32_t* idx_win) {
+                               int32_t* idx_win, uint32_t kind) {
   if (d < 1 || d > n) return fail(DSANLS_E_SHAPE, "subsampling needs 1 <= d <= n");
   if (n > (int64_t(1) << 27)) return fail(DSANLS_E_UNSUPPORTED, "subsampling supports n <= 2^27");
   SubWs w = carve_sub(ws, n);
   if (ws_bytes < w.bytes) return fail(DSANLS_E_WORKSPACE, "subsample workspace too small");
   const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
-  const uint32_t side_word = (static_cast<uint32_t>(side) & 0xFFu) | (kKindSubsample << 8);
+  const uint32_t side_word = (static_cast<uint32_t>(side) & 0xFFu) | (kind << 8);
   DSANLS_HIP(hipMemsetAsync(w.hist, 0, sizeof(uint32_t) * kHistBins + sizeof(SelectState), s));
   const unsigned g = static_cast<unsigned>(ceil_div(n, 256));
   sub_keys_kernel<<<g, 256, 0, s>>>(k0, k1, t, side_word, n, w.keys, w.hist);

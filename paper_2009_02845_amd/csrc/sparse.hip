@@ -65,6 +65,10 @@ __global__ __launch_bounds__(256) void csr_rhs_kernel(const int64_t* __restrict_
 // entries) is shared by many waves instead of serialising one.  A segment
 // of a single-segment row writes R directly; the segments of a longer row
 // write partial k-vectors that a fixup sums in segment order.
+// HASHED (count sketch): every entry counts, and entry (i, j) adds
+// M_ij s_j T[h_j, :] with T = B^T (d x k) read at the bucket h_j of its
+// column, instead of M_ij W[j, :] over the sampled columns.
+template <bool HASHED>
 __global__ __launch_bounds__(256) void csr_rhs_seg_kernel(const int64_t* __restrict__ rowptr,
                                                           const int32_t* __restrict__ colidx,
                                                           const float* __restrict__ vals,
@@ -73,9 +77,11 @@ __global__ __launch_bounds__(256) void csr_rhs_seg_kernel(const int64_t* __restr
                                                           const int32_t* __restrict__ seg_part,
                                                           int64_t nseg,
                                                           const int32_t* __restrict__ slot,
-                                                          const float* __restrict__ W, int k,
-                                                          float scale, float* __restrict__ R,
-                                                          float* __restrict__ P) {
+                                                          const float* __restrict__ W, int k, int64_t ldw,
+                                                          float scale, float* __restrict__ R, int64_t ldr,
+                                                          float* __restrict__ P,
+                                                          const int32_t* __restrict__ hbucket,
+                                                          const float* __restrict__ hsign) {
   const int64_t sg = blockIdx.x * 4ll + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (sg >= nseg) return;
@@ -90,8 +96,13 @@ __global__ __launch_bounds__(256) void csr_rhs_seg_kernel(const int64_t* __restr
     float v = 0.f;
     if (e < end) {
       col = colidx[e];
-      if (slot != nullptr && slot[col] < 0) col = -1;
-      if (col >= 0) v = vals[e];
+      if (HASHED) {
+        v = vals[e] * hsign[col];
+        col = hbucket[col];
+      } else {
+        if (slot != nullptr && slot[col] < 0) col = -1;
+        if (col >= 0) v = vals[e];
+      }
     }
     unsigned long long mask = __ballot(col >= 0);
     while (mask != 0ull) {
@@ -99,13 +110,13 @@ __global__ __launch_bounds__(256) void csr_rhs_seg_kernel(const int64_t* __restr
       mask &= mask - 1ull;
       const int32_t c = __shfl(col, b, 64);
       const float x = __shfl(v, b, 64);
-      const float* w = W + (int64_t)c * k;
+      const float* w = W + (int64_t)c * ldw;
       if (lane < k) a0 += x * w[lane];
       if (lane + 64 < k) a1 += x * w[lane + 64];
     }
   }
   const int32_t part = seg_part[sg];
-  float* out = part < 0 ? R + row * k : P + (int64_t)part * k;
+  float* out = part < 0 ? R + row * ldr : P + (int64_t)part * k;
   const float sc = part < 0 ? scale : 1.0f;
   if (lane < k) out[lane] = sc * a0;
   if (lane + 64 < k) out[lane + 64] = sc * a1;
@@ -116,7 +127,7 @@ __global__ __launch_bounds__(256) void csr_rhs_fixup_kernel(const int32_t* __res
                                                             const int32_t* __restrict__ multi_part,
                                                             int64_t nmulti, int k, float scale,
                                                             const float* __restrict__ P,
-                                                            float* __restrict__ R) {
+                                                            float* __restrict__ R, int64_t ldr) {
   const int64_t i = blockIdx.x * 4ll + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= nmulti) return;
@@ -127,8 +138,8 @@ __global__ __launch_bounds__(256) void csr_rhs_fixup_kernel(const int32_t* __res
     if (lane < k) a0 += P[(int64_t)p * k + lane];
     if (lane + 64 < k) a1 += P[(int64_t)p * k + lane + 64];
   }
-  if (lane < k) R[row * k + lane] = scale * a0;
-  if (lane + 64 < k) R[row * k + lane + 64] = scale * a1;
+  if (lane < k) R[row * ldr + lane] = scale * a0;
+  if (lane + 64 < k) R[row * ldr + lane + 64] = scale * a1;
 }
 
 // Sketched rows per segment: count the sampled hits of every segment, then
@@ -296,29 +307,33 @@ __global__ __launch_bounds__(256) void csr_cross_kernel(const int64_t* __restric
   float cs = 0.f, cc = 0.f, qs = 0.f, qc = 0.f;
   for (int64_t row = blockIdx.x * 4ll + wave; row < rows; row += nw) {
     const int64_t beg = rowptr[row], end = rowptr[row + 1];
-    float a0 = 0.f, a1 = 0.f, sq = 0.f, sqc = 0.f;
-    for (int64_t base = beg; base < end; base += 64) {
-      const int64_t e = base + lane;
-      int32_t col = 0;
-      float v = 0.f;
-      if (e < end) {
-        col = colidx[e];
-        v = vals[e];
+    float sq = 0.f, sqc = 0.f, dot = 0.f;
+    // the lanes hold two columns each: ranks above 128 in chunks of 128
+    for (int c0 = 0; c0 < k; c0 += 128) {
+      const int kc = k - c0 < 128 ? k - c0 : 128;
+      float a0 = 0.f, a1 = 0.f;
+      for (int64_t base = beg; base < end; base += 64) {
+        const int64_t e = base + lane;
+        int32_t col = 0;
+        float v = 0.f;
+        if (e < end) {
+          col = colidx[e];
+          v = vals[e];
+        }
+        if (c0 == 0) neumaier(sq, sqc, v * v);
+        const int cnt = static_cast<int>(end - base < 64 ? end - base : 64);
+        for (int b = 0; b < cnt; ++b) {
+          const int32_t c = __shfl(col, b, 64);
+          const float x = __shfl(v, b, 64);
+          const float* w = V + (int64_t)c * k + c0;
+          if (lane < kc) a0 += x * w[lane];
+          if (lane + 64 < kc) a1 += x * w[lane + 64];
+        }
       }
-      neumaier(sq, sqc, v * v);
-      const int cnt = static_cast<int>(end - base < 64 ? end - base : 64);
-      for (int b = 0; b < cnt; ++b) {
-        const int32_t c = __shfl(col, b, 64);
-        const float x = __shfl(v, b, 64);
-        const float* w = V + (int64_t)c * k;
-        if (lane < k) a0 += x * w[lane];
-        if (lane + 64 < k) a1 += x * w[lane + 64];
-      }
+      const float* u = U + row * k + c0;
+      if (lane < kc) dot += u[lane] * a0;
+      if (lane + 64 < kc) dot += u[lane + 64] * a1;
     }
-    const float* u = U + row * k;
-    float dot = 0.f;
-    if (lane < k) dot += u[lane] * a0;
-    if (lane + 64 < k) dot += u[lane + 64] * a1;
     for (int off = 32; off > 0; off >>= 1) dot += __shfl_down(dot, off, 64);
     for (int off = 32; off > 0; off >>= 1) {
       const float os = __shfl_down(sq, off, 64), oc = __shfl_down(sqc, off, 64);
@@ -579,8 +594,8 @@ __global__ __launch_bounds__(256) void a_rhs_kernel(const int32_t* __restrict__ 
                                                     int32_t* __restrict__ a_cols,
                                                     float* __restrict__ a_vals, int64_t rows,
                                                     const int32_t* __restrict__ idx,
-                                                    const float* __restrict__ W, int k, float scale,
-                                                    float* __restrict__ R) {
+                                                    const float* __restrict__ W, int k, int64_t ldw,
+                                                    float scale, float* __restrict__ R, int64_t ldr) {
   __shared__ int32_t s_j[4][64 * kShortRow];
   __shared__ float s_v[4][64 * kShortRow];
   __shared__ int32_t s_r[4][64 * kShortRow];
@@ -647,7 +662,7 @@ __global__ __launch_bounds__(256) void a_rhs_kernel(const int32_t* __restrict__ 
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const bool in0 = lane < k, in1 = lane + 64 < k;
   const int col0 = in0 ? lane : k - 1, col1 = in1 ? lane + 64 : k - 1;   // in-row load columns
-  float* Rw = R + row0 * k;
+  float* Rw = R + row0 * ldr;
   float a0 = 0.f, a1 = 0.f;
   int cur = 0;   // next R row of the wave to write
   for (int t0 = 0; t0 < total; t0 += 4) {
@@ -656,7 +671,7 @@ __global__ __launch_bounds__(256) void a_rhs_kernel(const int32_t* __restrict__ 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int t = t0 + q < total ? t0 + q : t0;
-      const float* wr = W + static_cast<int64_t>(s_j[w][t]) * k;
+      const float* wr = W + static_cast<int64_t>(s_j[w][t]) * ldw;
       const float y0 = wr[col0], y1 = wr[col1];
       x0[q] = in0 ? y0 : 0.f;
       x1[q] = in1 ? y1 : 0.f;
@@ -667,8 +682,8 @@ __global__ __launch_bounds__(256) void a_rhs_kernel(const int32_t* __restrict__ 
     for (int q = 0; q < 4; ++q) {
       if (t0 + q < total) {
         while (cur < rr[q]) {
-          if (in0) Rw[static_cast<int64_t>(cur) * k + lane] = scale * a0;
-          if (in1) Rw[static_cast<int64_t>(cur) * k + lane + 64] = scale * a1;
+          if (in0) Rw[static_cast<int64_t>(cur) * ldr + lane] = scale * a0;
+          if (in1) Rw[static_cast<int64_t>(cur) * ldr + lane + 64] = scale * a1;
           a0 = a1 = 0.f;
           ++cur;
         }
@@ -678,8 +693,8 @@ __global__ __launch_bounds__(256) void a_rhs_kernel(const int32_t* __restrict__ 
     }
   }
   while (cur < nrows) {
-    if (in0) Rw[static_cast<int64_t>(cur) * k + lane] = scale * a0;
-    if (in1) Rw[static_cast<int64_t>(cur) * k + lane + 64] = scale * a1;
+    if (in0) Rw[static_cast<int64_t>(cur) * ldr + lane] = scale * a0;
+    if (in1) Rw[static_cast<int64_t>(cur) * ldr + lane + 64] = scale * a1;
     a0 = a1 = 0.f;
     ++cur;
   }
@@ -700,10 +715,10 @@ __global__ __launch_bounds__(64 * NWV) void a_rhs_long_kernel(const int32_t* __r
                                                               const int32_t* __restrict__ a_cols,
                                                               const float* __restrict__ a_vals,
                                                               const int32_t* __restrict__ idx,
-                                                              const float* __restrict__ W, int k, float scale,
-                                                              const int32_t* __restrict__ long_rows,
+                                                              const float* __restrict__ W, int k, int64_t ldw,
+                                                              float scale, const int32_t* __restrict__ long_rows,
                                                               const int32_t* __restrict__ nlong, int min_len,
-                                                              int max_len, float* __restrict__ R) {
+                                                              int max_len, float* __restrict__ R, int64_t ldr) {
   __shared__ float part[NWV][128];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const bool in0 = lane < k, in1 = lane + 64 < k;
@@ -726,7 +741,7 @@ __global__ __launch_bounds__(64 * NWV) void a_rhs_long_kernel(const int32_t* __r
 #pragma unroll
         for (int q = 0; q < kLongBatch; ++q) {
           const int r = r0 + q < cn ? r0 + q : r0;
-          const float* wr = W + static_cast<int64_t>(__shfl(j, r, 64)) * k;
+          const float* wr = W + static_cast<int64_t>(__shfl(j, r, 64)) * ldw;
           const float y0 = wr[col0], y1 = wr[col1];
           x0[q] = in0 ? y0 : 0.f;
           x1[q] = in1 ? y1 : 0.f;
@@ -752,8 +767,8 @@ __global__ __launch_bounds__(64 * NWV) void a_rhs_long_kernel(const int32_t* __r
         s0 += part[q][lane];
         s1 += part[q][lane + 64];
       }
-      if (in0) R[static_cast<int64_t>(row) * k + lane] = scale * s0;
-      if (in1) R[static_cast<int64_t>(row) * k + lane + 64] = scale * s1;
+      if (in0) R[static_cast<int64_t>(row) * ldr + lane] = scale * s0;
+      if (in1) R[static_cast<int64_t>(row) * ldr + lane + 64] = scale * s1;
     }
   }
 }
@@ -773,17 +788,28 @@ dsanls_status launch_csr_sketch_rhs(const int64_t* rowptr, const int32_t* colidx
 
 dsanls_status launch_csr_rhs_seg(const int64_t* rowptr, const int32_t* colidx, const float* vals,
                                  const CsrSegments& sg, const int32_t* slot, const float* W, int64_t k,
-                                 float scale, float* R, float* P, hipStream_t s) {
+                                 float scale, float* R, float* P, hipStream_t s, const int32_t* hbucket,
+                                 const float* hsign) {
   if (sg.nseg <= 0) return DSANLS_OK;
-  if (k > 128) return fail(DSANLS_E_UNSUPPORTED, "CSR path supports k <= 128");
-  csr_rhs_seg_kernel<<<static_cast<unsigned>(ceil_div(sg.nseg, 4)), 256, 0, s>>>(
-      rowptr, colidx, vals, sg.seg_row, sg.seg_beg, sg.seg_part, sg.nseg, slot, W, static_cast<int>(k), scale, R,
-      P);
-  DSANLS_LAUNCHED("csr_rhs_seg_kernel");
-  if (sg.nmulti > 0) {
-    csr_rhs_fixup_kernel<<<static_cast<unsigned>(ceil_div(sg.nmulti, 4)), 256, 0, s>>>(
-        sg.multi_row, sg.multi_part, sg.nmulti, static_cast<int>(k), scale, P, R);
-    DSANLS_LAUNCHED("csr_rhs_fixup_kernel");
+  const unsigned g = static_cast<unsigned>(ceil_div(sg.nseg, 4));
+  // columns of R in chunks of 128 (two per lane); the partials of long rows
+  // are laid out per chunk
+  for (int64_t c0 = 0; c0 < k; c0 += 128) {
+    const int kc = static_cast<int>(std::min<int64_t>(128, k - c0));
+    if (hbucket != nullptr)
+      csr_rhs_seg_kernel<true><<<g, 256, 0, s>>>(rowptr, colidx, vals, sg.seg_row, sg.seg_beg, sg.seg_part,
+                                                 sg.nseg, nullptr, W + c0, kc, k, scale, R + c0, k, P, hbucket,
+                                                 hsign);
+    else
+      csr_rhs_seg_kernel<false><<<g, 256, 0, s>>>(rowptr, colidx, vals, sg.seg_row, sg.seg_beg, sg.seg_part,
+                                                  sg.nseg, slot, W + c0, kc, k, scale, R + c0, k, P, nullptr,
+                                                  nullptr);
+    DSANLS_LAUNCHED("csr_rhs_seg_kernel");
+    if (sg.nmulti > 0) {
+      csr_rhs_fixup_kernel<<<static_cast<unsigned>(ceil_div(sg.nmulti, 4)), 256, 0, s>>>(
+          sg.multi_row, sg.multi_part, sg.nmulti, kc, scale, P, R + c0, k);
+      DSANLS_LAUNCHED("csr_rhs_fixup_kernel");
+    }
   }
   return DSANLS_OK;
 }
@@ -826,16 +852,21 @@ dsanls_status launch_a_rhs(const int32_t* a_rowptr, int32_t* a_cols, float* a_va
                            const int32_t* idx, const float* W, int64_t k, float scale, const int32_t* long_rows,
                            const int32_t* nlong, float* R, hipStream_t s) {
   if (rows <= 0) return DSANLS_OK;
-  if (k > 128) return fail(DSANLS_E_UNSUPPORTED, "CSR path supports k <= 128");
-  a_rhs_kernel<<<static_cast<unsigned>(ceil_div(rows, 256)), 256, 0, s>>>(a_rowptr, a_cols, a_vals, rows, idx, W,
-                                                                         static_cast<int>(k), scale, R);
-  DSANLS_LAUNCHED("a_rhs_kernel");
-  a_rhs_long_kernel<4><<<1024, 256, 0, s>>>(a_rowptr, a_cols, a_vals, idx, W, static_cast<int>(k), scale, long_rows,
-                                            nlong, kShortRow + 1, kVeryLongRow, R);
-  DSANLS_LAUNCHED("a_rhs_long_kernel");
-  a_rhs_long_kernel<16><<<256, 1024, 0, s>>>(a_rowptr, a_cols, a_vals, idx, W, static_cast<int>(k), scale,
-                                             long_rows, nlong, kVeryLongRow + 1, 0x7fffffff, R);
-  DSANLS_LAUNCHED("a_rhs_long_kernel");
+  // the lanes hold two columns of R each: columns in chunks of 128 (the
+  // first chunk also leaves the short rows of A sorted; later ones find
+  // them so)
+  for (int64_t c0 = 0; c0 < k; c0 += 128) {
+    const int kc = static_cast<int>(std::min<int64_t>(128, k - c0));
+    a_rhs_kernel<<<static_cast<unsigned>(ceil_div(rows, 256)), 256, 0, s>>>(a_rowptr, a_cols, a_vals, rows, idx,
+                                                                           W + c0, kc, k, scale, R + c0, k);
+    DSANLS_LAUNCHED("a_rhs_kernel");
+    a_rhs_long_kernel<4><<<1024, 256, 0, s>>>(a_rowptr, a_cols, a_vals, idx, W + c0, kc, k, scale, long_rows,
+                                              nlong, kShortRow + 1, kVeryLongRow, R + c0, k);
+    DSANLS_LAUNCHED("a_rhs_long_kernel");
+    a_rhs_long_kernel<16><<<256, 1024, 0, s>>>(a_rowptr, a_cols, a_vals, idx, W + c0, kc, k, scale,
+                                               long_rows, nlong, kVeryLongRow + 1, 0x7fffffff, R + c0, k);
+    DSANLS_LAUNCHED("a_rhs_long_kernel");
+  }
   return DSANLS_OK;
 }
 
@@ -903,7 +934,6 @@ int64_t csr_cross_partials(int64_t) { return kCrossBlocks; }
 dsanls_status launch_csr_cross(const int64_t* rowptr, const int32_t* colidx, const float* vals,
                                int64_t rows, const float* U, const float* V, int64_t k,
                                float* partials, hipStream_t s) {
-  if (k > 128) return fail(DSANLS_E_UNSUPPORTED, "CSR path supports k <= 128");
   csr_cross_kernel<<<kCrossBlocks, 256, 0, s>>>(rowptr, colidx, vals, rows, U, V,
                                                 static_cast<int>(k), partials);
   DSANLS_LAUNCHED("csr_cross_kernel");

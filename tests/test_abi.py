@@ -49,7 +49,10 @@ def _dense(ld):
 
 @pytest.mark.parametrize("kw,status", [
     (dict(m=0, n=5, k=2, d=3), 2),
-    (dict(m=5, n=5, k=129, d=3), 7),
+    (dict(m=5, n=5, k=513, d=3), 7),
+    (dict(m=5, n=5, k=200, d=3, sweeps=0), 7),
+    (dict(m=5, n=5, k=200, d=3, solver="pgd"), 7),
+    (dict(m=5, n=5, k=200, d=3), 0),
     (dict(m=5, n=5, k=2, d=6, sketch="subsample"), 2),
     (dict(m=5, n=5, k=2, d=4, sketch="identity"), 2),
     (dict(m=5, n=5, k=2, d=3, alpha=-1.0), 1),

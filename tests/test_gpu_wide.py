@@ -1,0 +1,138 @@
+"""Ranks above 128 (the k = 200 and 500 points of the rank sweep in Sec. 5.3,
+"Performance Varying the Value of k"): the block-coupled prox-CD kernel for
+k up to 512 against the FP64 oracle (Alg. 3, eq. entry_sol), and whole
+updates on dense and CSR input at such ranks."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import dsanls as O
+from paper_2009_02845_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_02845_amd import binding
+    binding.load()
+    return torch, binding
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def _f32(x):
+    return x.astype(np.float32).astype(np.float64)
+
+
+def _problem(rows, k, d, seed):
+    g = np.random.default_rng(seed)
+    B = g.standard_normal((k, d))
+    A = g.standard_normal((rows, d)) + 0.2
+    G, R = O.gram_and_rhs(A, B)
+    return _f32(G), _f32(R), _f32(g.random((rows, k))), _f32(g.random((rows, k)))
+
+
+@pytest.mark.parametrize("k", [129, 200, 256, 300, 500, 512])
+@pytest.mark.parametrize("sweeps", [1, 3])
+def test_wide_prox_cd_matches_oracle(env, k, sweeps):
+    # 1000 rows: 15 full workgroups of 64 rows and a last one with a partial
+    # wave and empty waves; d both above and below k (singular G)
+    torch, B = env
+    rows = 1000
+    d = k + 37 if sweeps == 1 else k // 2
+    G, R, U0, C0 = _problem(rows, k, d, k + sweeps)
+    mu = 0.9
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(np.float32))).cuda()
+    Ud = t(U0)
+    used = B.nnls_prox_cd(t(G), t(R), Ud, Ud, mu, sweeps=sweeps, want_sweeps=True)
+    Uo, _ = O.prox_cd_solve(U0, U0, G, R, mu, sweeps)
+    Ug = Ud.cpu().numpy().astype(np.float64)
+    assert _rel(Ug, Uo) < 1e-4
+    rowerr = np.linalg.norm(Ug - Uo, axis=1) / np.maximum(np.linalg.norm(Uo, axis=1), 1e-30)
+    assert rowerr.max() < 1e-3
+    assert (used.cpu().numpy() == sweeps).all()
+    # a centre distinct from the start, and the clip of eq. extra_con
+    Ud = t(U0)
+    B.nnls_prox_cd(t(G), t(R), t(C0), Ud, mu, sweeps=sweeps, upper=0.3)
+    Uo, _ = O.prox_cd_solve(U0, C0, G, R, mu, sweeps, upper=0.3)
+    assert _rel(Ud.cpu().numpy().astype(np.float64), Uo) < 1e-4
+
+
+def test_wide_nonfinite_rows_and_limits(env):
+    torch, B = env
+    rows, k = 200, 300
+    G, R, U0, _ = _problem(rows, k, 250, 1)
+    R[17, 123] = np.nan
+    R[150, 0] = -np.inf
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(np.float32))).cuda()
+    Ud = t(U0)
+    B.nnls_prox_cd(t(G), t(R), Ud, Ud, 1.0, sweeps=1)
+    Ug = Ud.cpu().numpy()
+    assert np.isnan(Ug[[17, 150]]).all()
+    assert np.isfinite(np.delete(Ug, [17, 150], axis=0)).all()
+    with pytest.raises(B.DsanlsError) as e:
+        B.nnls_prox_cd(t(G), t(R), Ud, Ud, 1.0, sweeps=0)      # to tolerance: not above 128
+    assert e.value.status_name == "UNSUPPORTED"
+    with pytest.raises(B.DsanlsError) as e:
+        B.pgd_step(t(G), t(R), Ud, 1.0)
+    assert e.value.status_name == "UNSUPPORTED"
+
+
+def test_sparse_update_and_objective_at_k200(env):
+    # CSR with subsampling at k = 200: the sampled-column gather forms R in
+    # chunks of 128 columns, the wide kernel updates, the objective's nnz term
+    # runs in chunks too
+    torch, B = env
+    m, n, k, d = 2000, 1500, 200, 120
+    g = np.random.default_rng(3)
+    Ms = sp.random(m, n, density=0.02, format="csr", random_state=3, dtype=np.float64)
+    Ms.data = g.lognormal(0, 1, Ms.nnz)
+    Ms = Ms.astype(np.float32).tocsr()
+    Ms.sort_indices()
+    Mt = Ms.T.tocsr()
+    Mt.sort_indices()
+    U0, V0 = synth.init_factors(m, n, k, 3)
+    tt = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a.astype(dt))).cuda()
+    arrs = [tt(Ms.indptr, np.int64), tt(Ms.indices, np.int32), tt(Ms.data, np.float32),
+            tt(Mt.indptr, np.int64), tt(Mt.indices, np.int32), tt(Mt.data, np.float32)]
+    U, V = torch.from_numpy(U0).cuda(), torch.from_numpy(V0).cuda()
+    cfg = B.make_config(m, n, k, d, d, sketch="subsample", solver="prox_cd", sweeps=1, seed=2)
+    s = B.Solver(cfg, B.csr_matrix(*arrs), U, V, tensors=arrs)
+    ocfg = O.Config(k=k, d=d, d_prime=d, sketch=O.SKETCH_SUBSAMPLE, solver=O.SOLVER_PROX_CD, seed=2)
+    M64 = Ms.astype(np.float64)
+    U64, V64 = U0.astype(np.float64), V0.astype(np.float64)
+    s.update_U(0)
+    Ug = U.cpu().numpy().astype(np.float64)
+    assert _rel(Ug, O.update_U(M64, U64, V64, 0, ocfg)) < 1e-4
+    s.update_V(0)
+    Vg = V.cpu().numpy().astype(np.float64)
+    assert _rel(Vg, O.update_V(M64, Ug, V64, 0, ocfg)) < 1e-4
+    assert abs(s.objective() - O.relative_error(M64, Ug, Vg)) < 1e-5
+
+
+@pytest.mark.parametrize("sketch", ["gaussian", "count"])
+def test_dense_update_at_k160(env, sketch):
+    torch, B = env
+    m, n, k, d = 600, 450, 160, 200
+    M = synth.planted_dense(m, n, 24, 4, noise_sd=0.01)
+    U0, V0 = synth.init_factors(m, n, k, 4)
+    Md = torch.from_numpy(M).cuda()
+    U, V = torch.from_numpy(U0).cuda(), torch.from_numpy(V0).cuda()
+    cfg = B.make_config(m, n, k, d, d, sketch=sketch, solver="prox_cd", sweeps=2, seed=3)
+    s = B.Solver(cfg, B.dense_matrix(Md), U, V, tensors=[Md])
+    kind = O.SKETCH_GAUSSIAN if sketch == "gaussian" else O.SKETCH_COUNT
+    ocfg = O.Config(k=k, d=d, d_prime=d, sketch=kind, solver=O.SOLVER_PROX_CD, sweeps=2, seed=3)
+    M64, U64, V64 = M.astype(np.float64), U0.astype(np.float64), V0.astype(np.float64)
+    s.update_U(1)
+    Ug = U.cpu().numpy().astype(np.float64)
+    assert _rel(Ug, O.update_U(M64, U64, V64, 1, ocfg)) < 1e-4
+    s.update_V(1)
+    Vg = V.cpu().numpy().astype(np.float64)
+    assert _rel(Vg, O.update_V(M64, Ug, V64, 1, ocfg)) < 1e-4
+    assert abs(s.objective() - O.relative_error(M64, Ug, Vg)) / O.relative_error(M64, Ug, Vg) < 1e-4
