@@ -40,26 +40,26 @@ PEAK = {"fp32_mfma_tflops": 157.3, "bf16_mfma_tflops": 2500.0, "hbm_gbs": 8000.0
 WORKLOADS = {
     # the small FP64-checkable case (parity configuration)
     "dense-200x150": dict(kind="dense", m=200, n=150, k=10, d=40, iters=20, solver="pgd",
-                          gen="uniform", precision="fp32"),
+                          gen="uniform", precision="fp32", alpha=0.1, beta=1.0),
     # plain FP32 on one GPU (the default bench line)
     "dense-20000x10000": dict(kind="dense", m=20000, n=10000, k=64, d=1024, iters=50, solver="prox_cd",
-                              gen="planted", noise=0.01, noise_relative=False, precision="fp32"),
+                              gen="planted", noise=0.01, noise_relative=False, precision="fp32", alpha=1.0, beta=0.1),
     # precision form: planted rank-128 + 1% noise, FP32 and BF16 sketch GEMM
     "dense-50000x20000-fp32": dict(kind="dense", m=50000, n=20000, k=128, d=4096, iters=30,
                                    solver="prox_cd", gen="planted", noise=0.01, noise_relative=True,
-                                   precision="fp32"),
+                                   precision="fp32", alpha=0.1, beta=10.0),
     "dense-50000x20000-bf16": dict(kind="dense", m=50000, n=20000, k=128, d=4096, iters=30,
                                    solver="prox_cd", gen="planted", noise=0.01, noise_relative=True,
-                                   precision="bf16"),
+                                   precision="bf16", alpha=0.1, beta=10.0),
     # text-shaped CSR row block, subsampling sketch (columns sampled and scaled)
     "sparse-500000x200000": dict(kind="sparse", m=500000, n=200000, k=100, d=2000, iters=30,
-                                 solver="prox_cd", nnz=100_000_000, precision="fp32"),
+                                 solver="prox_cd", nnz=100_000_000, precision="fp32", alpha=0.1, beta=0.1),
     # learned warm start on the same data: pairs from 5 plain to-tolerance
     # runs (sketch seeds 1-5), training, then cold vs warm on sketch seed 6
     "sparse-500000x200000-warm": dict(kind="warm", m=500000, n=200000, k=100, d=2000, iters=10,
                                       solver="prox_cd", nnz=100_000_000, precision="fp32", hidden=256,
                                       pairs=1_000_000, runs=5, run_iters=20, label_tol=1e-6, tol=1e-4,
-                                      max_sweeps=200, epochs=6, batch=4096, lr=1e-4),
+                                      max_sweeps=200, epochs=6, batch=4096, lr=1e-4, alpha=0.1, beta=0.1),
 }
 # the further sketch kinds of Sec. 3.4 on the same data shapes
 WORKLOADS["dense-20000x10000-count"] = dict(WORKLOADS["dense-20000x10000"], sketch="count")
@@ -70,14 +70,20 @@ WORKLOADS["sparse-500000x200000-count"] = dict(WORKLOADS["sparse-500000x200000"]
 WORKLOADS["sparse-500000x200000-ksweep"] = dict(WORKLOADS["sparse-500000x200000"], kind="ksweep",
                                                 ks=(20, 50, 100, 200, 500), iters=10)
 WORKLOADS["pgd-vs-cd"] = dict(kind="pgd_vs_cd", iters=20,
-                              cases=(dict(name="dense-200x150", m=200, n=150, k=10, d=40, gen="uniform", iters=20),
+                              cases=(dict(name="dense-200x150", m=200, n=150, k=10, d=40, gen="uniform", iters=20,
+                                          pgd=dict(alpha=0.1, beta=1.0), prox_cd=dict(alpha=1.0, beta=1.0)),
                                      dict(name="dense-20000x10000", m=20000, n=10000, k=64, d=1024, gen="planted",
                                           noise=0.01, noise_relative=False, iters=50)))
+# the paper's proximal weight grid (Sec. 5.2): mu_t = alpha + beta t with
+# alpha, beta in {0.1, 1, 10}, the best chosen per data set; here per
+# workload, by the relative objective after the workload's iterations
+WORKLOADS["mu-grid"] = dict(kind="mu_grid", iters=None, grid=(0.1, 1.0, 10.0),
+                            cases=("dense-20000x10000", "sparse-500000x200000", "dense-50000x20000-fp32"))
 DEFAULT = "dense-50000x20000"
 # the precision form measured to a fixed relative objective (the default)
 TO_EPS = {"dense-50000x20000": dict(kind="to_eps", m=50000, n=20000, k=128, d=4096, iters=30,
                                     solver="prox_cd", gen="planted", noise=0.01, noise_relative=True,
-                                    seeds=(0, 1, 2), max_factor=3, sample_rows=256)}
+                                    seeds=(0, 1, 2), max_factor=3, sample_rows=256, alpha=0.1, beta=10.0)}
 WORKLOADS.update(TO_EPS)
 
 
@@ -149,7 +155,8 @@ def cpu_baseline(w, M, U0, V0, budget_s=12.0, max_iters=5, Mt=None, half=False):
         cores = os.cpu_count() or 1
     sketch = O.SKETCH_SUBSAMPLE if w["kind"] == "sparse" else O.SKETCH_GAUSSIAN
     sketch = {"count": O.SKETCH_COUNT, "srht": O.SKETCH_SRHT}.get(w.get("sketch"), sketch)
-    cfg = O.Config(k=w["k"], d=w["d"], d_prime=w["d"], sketch=sketch, solver=w["solver"])
+    cfg = O.Config(k=w["k"], d=w["d"], d_prime=w["d"], sketch=sketch, solver=w["solver"],
+                   alpha=w.get("alpha", 1.0), beta=w.get("beta", 1.0))
     M64 = M.astype(np.float64)
     Mt64 = Mt.astype(np.float64) if Mt is not None else None
     U, V = U0.astype(np.float64), V0.astype(np.float64)
@@ -260,7 +267,8 @@ def run_warm(args, w, torch, B):
     def solver(seed, tol, warm_hidden=0):
         U, V = U0d.clone(), V0d.clone()
         cfg = B.make_config(m, n, k, d, d, sketch="subsample", solver="prox_cd", sweeps=0, tol=tol,
-                            max_sweeps=w["max_sweeps"], alpha=1.0, beta=1.0, seed=seed, warm_hidden=warm_hidden)
+                            max_sweeps=w["max_sweeps"], alpha=w.get("alpha", 1.0), beta=w.get("beta", 1.0), seed=seed,
+                            warm_hidden=warm_hidden)
         return B.Solver(cfg, mat, U, V, tensors=keep), U, V
 
     # 1) training pairs (a_i, u_i^t) -> to-tolerance solution u_i*
@@ -401,7 +409,8 @@ def _per_update_error(M, U0, V0, Ug, sel, w, seed_sketch=0):
     of the BF16 form (M and S rounded to bfloat16, products exact)."""
     from oracle import dsanls as O
     k, d = w["k"], w["d"]
-    ocfg = O.Config(k=k, d=d, d_prime=d, sketch=O.SKETCH_GAUSSIAN, solver=O.SOLVER_PROX_CD, seed=seed_sketch)
+    ocfg = O.Config(k=k, d=d, d_prime=d, sketch=O.SKETCH_GAUSSIAN, solver=O.SOLVER_PROX_CD, seed=seed_sketch,
+                    alpha=w.get("alpha", 1.0), beta=w.get("beta", 1.0))
     U64, V64 = U0.astype(np.float64), V0.astype(np.float64)
     plain = O.update_U(M, U64, V64, 0, ocfg, rows=sel)
     ocfg.precision = "bf16"
@@ -427,7 +436,7 @@ def run_to_eps(args, w, torch, B, K, W):
         for form in ("fp32", "bf16"):
             U, V = U0d.clone(), V0d.clone()
             cfg = B.make_config(m, n, k, d, d, sketch="gaussian", solver="prox_cd", precision=form, sweeps=1,
-                                alpha=1.0, beta=1.0, seed=0)
+                                alpha=w.get("alpha", 1.0), beta=w.get("beta", 1.0), seed=0)
             solver = B.Solver(cfg, B.dense_matrix(Md), U, V, tensors=[Md])
             if si == 0:
                 # one U update from U^0, V^0 against the FP64 oracle on sampled rows
@@ -531,7 +540,8 @@ def run_ksweep(args, w, torch, B, K, W):
         U0, V0 = synth.init_factors(m, n, k, args.seed)
         U0d, V0d = torch.from_numpy(U0).to(dev), torch.from_numpy(V0).to(dev)
         U, V = U0d.clone(), V0d.clone()
-        cfg = B.make_config(m, n, k, d, d, sketch="subsample", solver="prox_cd", sweeps=1, alpha=1.0, beta=1.0,
+        cfg = B.make_config(m, n, k, d, d, sketch="subsample", solver="prox_cd", sweeps=1, alpha=w.get("alpha", 1.0),
+                            beta=w.get("beta", 1.0),
                             seed=0)
         solver = B.Solver(cfg, mat, U, V, tensors=keep)
         for t in range(W):
@@ -588,7 +598,9 @@ def run_pgd_vs_cd(args, w, torch, B, W):
         entry = {"case": c["name"], "m": m, "n": n, "k": k, "d": d}
         for solver_name in ("pgd", "prox_cd"):
             U, V = U0d.clone(), V0d.clone()
-            cfg = B.make_config(m, n, k, d, d, sketch="gaussian", solver=solver_name, sweeps=1, alpha=1.0, beta=1.0,
+            mu = dict(dict(alpha=c.get("alpha", 1.0), beta=c.get("beta", 1.0)), **c.get(solver_name, {}))
+            cfg = B.make_config(m, n, k, d, d, sketch="gaussian", solver=solver_name, sweeps=1,
+                                alpha=mu["alpha"], beta=mu["beta"],
                                 seed=0)
             solver = B.Solver(cfg, B.dense_matrix(Md), U, V, tensors=[Md])
             for t in range(W):
@@ -600,6 +612,48 @@ def run_pgd_vs_cd(args, w, torch, B, W):
         print(f"[bench] {c['name']}: PGD {entry['pgd']['rel_objective'][-1]:.4f}, prox-CD "
               f"{entry['prox_cd']['rel_objective'][-1]:.4f}", file=sys.stderr, flush=True)
         out.append(entry)
+    return out
+
+
+def run_mu_grid(args, w, torch, B, W):
+    """Relative objective after each workload's iterations for every
+    (alpha, beta) of the paper's grid, one run per pair from U^0, V^0."""
+    dev = torch.device("cuda", 0)
+    out = []
+    for name in w["cases"]:
+        c = WORKLOADS[name]
+        m, n, k, d = c["m"], c["n"], c["k"], c["d"]
+        print(f"[bench] {name}: generating data", file=sys.stderr, flush=True)
+        if c["kind"] == "dense":
+            M, U0, V0 = make_dense(c, args.seed)
+            Md = torch.from_numpy(M).to(dev)
+            keep, mat, sketch = [Md], B.dense_matrix(Md), "gaussian"
+        else:
+            M, Mt, U0, V0 = make_sparse(c, args.seed)
+            to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a.astype(dt))).to(dev)
+            keep = [to(M.indptr, np.int64), to(M.indices, np.int32), to(M.data, np.float32),
+                    to(Mt.indptr, np.int64), to(Mt.indices, np.int32), to(Mt.data, np.float32)]
+            mat, sketch = B.csr_matrix(*keep), "subsample"
+        U0d, V0d = torch.from_numpy(U0).to(dev), torch.from_numpy(V0).to(dev)
+        table = []
+        for a in w["grid"]:
+            for b in w["grid"]:
+                U, V = U0d.clone(), V0d.clone()
+                cfg = B.make_config(m, n, k, d, d, sketch=sketch, solver="prox_cd", sweeps=1, alpha=a, beta=b, seed=0)
+                solver = B.Solver(cfg, mat, U, V, tensors=keep)
+                objs = []
+                for t in range(c["iters"]):
+                    solver.iteration(t)
+                    objs.append(solver.objective())
+                table.append({"alpha": a, "beta": b, "rel_objective": objs[-1], "trajectory": objs})
+                solver.close()
+        best = min(table, key=lambda r: r["rel_objective"])
+        print(f"[bench] {name}: best alpha={best['alpha']} beta={best['beta']} -> {best['rel_objective']:.5f}",
+              file=sys.stderr, flush=True)
+        out.append({"workload": name, "iterations": c["iters"], "grid": table,
+                    "best": {"alpha": best["alpha"], "beta": best["beta"], "rel_objective": best["rel_objective"]}})
+        del keep, mat, U0d, V0d
+        torch.cuda.empty_cache()
     return out
 
 
@@ -647,6 +701,16 @@ def main():
                "config": {"workload": describe(args.workload, w, K), "m": w["m"], "n": w["n"], "d": w["d"],
                           "iterations": K, "parallelism": "single GPU"}}
         out.update(r)
+        print(json.dumps(out), flush=True)
+        return
+    if w["kind"] == "mu_grid":
+        r = run_mu_grid(args, w, torch, B, W)
+        out = {"metric": "relative objective after each workload's iterations, per (alpha, beta) of mu_t",
+               "unit": "relative error", "n_gpus": 1, "steps": None, "warmup": 0, "higher_is_better": False,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": "mu_t = alpha + beta t grid over " + ", ".join(w["cases"]),
+                          "parallelism": "single GPU"},
+               "value": r[0]["best"]["rel_objective"], "cases": r}
         print(json.dumps(out), flush=True)
         return
     if w["kind"] == "pgd_vs_cd":
@@ -703,7 +767,7 @@ def main():
     U0d, V0d = torch.from_numpy(U0).to(dev), torch.from_numpy(V0).to(dev)
     U, V = U0d.clone(), V0d.clone()
     cfg = B.make_config(m, n, k, d, d, sketch=sketch, solver=w["solver"], precision=w["precision"],
-                        sweeps=1, alpha=1.0, beta=1.0, seed=0)
+                        sweeps=1, alpha=w.get("alpha", 1.0), beta=w.get("beta", 1.0), seed=0)
     solver = B.Solver(cfg, mat, U, V, tensors=keep)
     print(f"[bench] warmup {W} iterations", file=sys.stderr, flush=True)
     for t in range(W):

@@ -145,8 +145,10 @@ typedef struct {
  *   DENSE: dense (m x n, leading dimension ld >= n).  dense_t (n x m, ld_t)
  *          may be NULL, in which case init builds M^T in the workspace.
  *   CSR:   rowptr[m+1] (int64), colidx[nnz] (int32, sorted within each row,
- *          no duplicates), vals[nnz]; plus the same arrays of CSR(M^T)
- *          (t_rowptr[n+1], t_colidx, t_vals), which are required.
+ *          no duplicates, all < n), vals[nnz], nnz < 2^31; plus the same
+ *          arrays of CSR(M^T) (t_rowptr[n+1], t_colidx, t_vals).  With
+ *          t_rowptr NULL, init builds CSR(M^T) in the workspace on the GPU
+ *          (rows of M^T sorted; deterministic).
  * All arrays are device memory, read-only, and must outlive the context.
  */
 typedef struct {

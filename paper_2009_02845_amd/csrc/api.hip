@@ -40,6 +40,12 @@ int64_t r32(int64_t x) { return (x + 31) / 32 * 32; }
 struct Layout {
   float* Mt = nullptr;              // n x ldmt, resident M^T (dense, when not supplied)
   int64_t ldmt = 0;
+  // CSR(M^T) built at init when the caller passes CSR(M) alone
+  int64_t* t_rowptr = nullptr;
+  int32_t* t_colidx = nullptr;
+  float* t_vals = nullptr;
+  void* ct_ws = nullptr;
+  size_t ct_ws_bytes = 0;
   __hip_bfloat16* Mb = nullptr;     // m x ldmb (BF16 copy of M)
   __hip_bfloat16* Mtb = nullptr;    // n x ldmtb
   int64_t ldmb = 0, ldmtb = 0;
@@ -129,6 +135,14 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
   if (is_dense && M.dense_t == nullptr) {
     L.ldmt = r4(m);
     L.Mt = reinterpret_cast<float*>(take(sizeof(float) * n * L.ldmt));
+  }
+  if (!is_dense && M.t_rowptr == nullptr) {
+    const int64_t nnz = std::max<int64_t>(M.nnz, 1);
+    L.t_rowptr = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (n + 1)));
+    L.t_colidx = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * nnz));
+    L.t_vals = reinterpret_cast<float*>(take(sizeof(float) * nnz));
+    L.ct_ws_bytes = csr_transpose_ws_bytes(n);
+    L.ct_ws = take(L.ct_ws_bytes);
   }
   if (is_dense && bf16) {
     L.ldmb = r32(n);
@@ -317,8 +331,10 @@ dsanls_status validate(const dsanls_config* c, const dsanls_matrix* M) {
     if (!M->dense || M->ld < c->n) return fail(DSANLS_E_INVALID_ARG, "dense M: NULL or ld < n");
     if (M->dense_t && M->ld_t < c->m) return fail(DSANLS_E_INVALID_ARG, "dense M^T: ld_t < m");
   } else if (M->format == DSANLS_CSR) {
-    if (!M->rowptr || !M->t_rowptr || M->nnz < 0 || (M->nnz > 0 && (!M->colidx || !M->vals || !M->t_colidx || !M->t_vals)))
-      return fail(DSANLS_E_INVALID_ARG, "CSR M: CSR(M) and CSR(M^T) arrays are required");
+    if (!M->rowptr || M->nnz < 0 || (M->nnz > 0 && (!M->colidx || !M->vals)))
+      return fail(DSANLS_E_INVALID_ARG, "CSR M: rowptr, colidx and vals are required");
+    if (M->t_rowptr != nullptr && M->nnz > 0 && (!M->t_colidx || !M->t_vals))
+      return fail(DSANLS_E_INVALID_ARG, "CSR M^T: t_rowptr given without t_colidx or t_vals");
     if (c->sketch == DSANLS_SKETCH_GAUSSIAN || c->sketch == DSANLS_SKETCH_SRHT)
       return fail(DSANLS_E_UNSUPPORTED, "Gaussian and SRHT sketches on CSR input are not supported");
     if (c->precision != DSANLS_PREC_FP32)
@@ -822,8 +838,17 @@ dsanls_status dsanls_init(const dsanls_config* cfg, const dsanls_matrix* M, floa
       return bail(st);
   } else {
     if (M->nnz > INT32_MAX) return bail(fail(DSANLS_E_SHAPE, "CSR input supports nnz < 2^31"));
+    if (M->t_rowptr == nullptr) {
+      // CSR(M^T) from CSR(M), rows of M^T sorted
+      if ((st = launch_csr_transpose(M->rowptr, M->colidx, M->vals, c.m, c.n, M->nnz, L.t_rowptr, L.t_colidx,
+                                     L.t_vals, L.ct_ws, L.ct_ws_bytes, s)) != DSANLS_OK)
+        return bail(st);
+      ctx->mat.t_rowptr = L.t_rowptr;
+      ctx->mat.t_colidx = L.t_colidx;
+      ctx->mat.t_vals = L.t_vals;
+    }
     for (int sd = 0; sd < 2; ++sd) {
-      if ((st = build_segments(sd == 0 ? M->rowptr : M->t_rowptr, sd == 0 ? c.m : c.n, L.seg_cap[sd],
+      if ((st = build_segments(sd == 0 ? M->rowptr : ctx->mat.t_rowptr, sd == 0 ? c.m : c.n, L.seg_cap[sd],
                                L.multi_cap[sd], ctx->L.seg[sd], s)) != DSANLS_OK)
         return bail(st);
     }

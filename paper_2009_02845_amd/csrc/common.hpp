@@ -265,6 +265,13 @@ dsanls_status launch_csr_select_copy(const int32_t* rowptr, int64_t nrows, const
                                      const float* vals, const int32_t* sel, int64_t nsel,
                                      const int32_t* out_rowptr, int32_t* out_cols, float* out_vals,
                                      hipStream_t s);
+// CSR(M^T) (t_rowptr n + 1 int64, t_colidx, t_vals) from CSR(M) (rows x n,
+// nnz < 2^31), each row of M^T in ascending column order; workspace of
+// csr_transpose_ws_bytes(n) bytes (csr_transpose.hip).
+size_t csr_transpose_ws_bytes(int64_t n);
+dsanls_status launch_csr_transpose(const int64_t* rowptr, const int32_t* colidx, const float* vals, int64_t rows,
+                                   int64_t n, int64_t nnz, int64_t* t_rowptr, int32_t* t_colidx, float* t_vals,
+                                   void* ws, size_t ws_bytes, hipStream_t s);
 // MLP (mlp.hip)
 int64_t mlp_param_count(int d, int k, int hd);
 size_t mlp_ws_bytes(int d, int k, int hd, int64_t rows, bool forward_only);

@@ -32,7 +32,9 @@ __global__ __launch_bounds__(256) void prox_cd_wide_kernel(const float* __restri
                                                            int64_t rows, int k, float mu, int sweeps, float upper,
                                                            int32_t* __restrict__ sweeps_used) {
   typedef float f4 __attribute__((ext_vector_type(4)));
-  constexpr int KP = 16 * NBK, NQ = 4 * NBK, GS = KP + 4, NG = KP / 64;
+  // a G block is 16 x KP floats = 4 KP float4s, NG per thread (the last
+  // round partial when KP is not a multiple of 64)
+  constexpr int KP = 16 * NBK, NQ = 4 * NBK, GS = KP + 4, NG4 = 4 * KP, NG = (NG4 + 255) / 256;
   __shared__ __attribute__((aligned(16))) float gl[2][16 * GS];
   __shared__ float sinv[KP];
   __shared__ float tx[4][16 * 17];
@@ -59,14 +61,14 @@ __global__ __launch_bounds__(256) void prox_cd_wide_kernel(const float* __restri
 #pragma unroll
     for (int r = 0; r < NG; ++r) {
       const int e = tid + 256 * r, i = e / (KP / 4), l4 = e % (KP / 4);
-      gs[r] = gp4[(16 * b + i) * (KP / 4) + l4];
+      if (NG4 % 256 == 0 || e < NG4) gs[r] = gp4[(16 * b + i) * (KP / 4) + l4];
     }
   };
   auto store_g = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < NG; ++r) {
       const int e = tid + 256 * r, i = e / (KP / 4), l4 = e % (KP / 4);
-      *reinterpret_cast<f4*>(&gl[buf][i * GS + 4 * l4]) = gs[r];
+      if (NG4 % 256 == 0 || e < NG4) *reinterpret_cast<f4*>(&gl[buf][i * GS + 4 * l4]) = gs[r];
     }
   };
   load_g(0);

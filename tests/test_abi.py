@@ -75,7 +75,12 @@ def test_validation_matrix_errors():
     cfg_s = B.make_config(m=5, n=6, k=2, d=3, sketch="subsample")
     assert _ws(cfg_s, csr)[0] == 0
     csr.t_rowptr = None
-    assert _ws(cfg_s, csr)[0] == 1                           # CSR(M^T) required
+    st, with_t = _ws(cfg_s, csr)                             # CSR(M^T) built at init: more workspace
+    assert st == 0 and with_t > _ws(cfg_s, B.Matrix(format=B.CSR, rowptr=FAKE, colidx=FAKE, vals=FAKE, nnz=3,
+                                                   t_rowptr=FAKE, t_colidx=FAKE, t_vals=FAKE))[1]
+    csr.t_rowptr = FAKE
+    csr.t_vals = None
+    assert _ws(cfg_s, csr)[0] == 1                           # CSR(M^T) given in part
 
 
 def test_workspace_grows_with_problem():
