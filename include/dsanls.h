@@ -222,15 +222,16 @@ dsanls_status dsanls_get_stats(dsanls_ctx* ctx, dsanls_stats* out);
 /* Install (params != NULL) or remove (NULL) the learned warm start.  params
  * is the packed network of the dsanls_mlp_* calls below (device memory,
  * caller-owned, read at each update), with d = cfg.d = cfg.d_prime, k = cfg.k
- * and hidden = cfg.warm_hidden.  With a warm start, each to-tolerance update
- * first forms the sketched rows a_i of A = X S (CSR), runs the network on
+ * and hidden = cfg.warm_hidden; residual selects the network's form as in
+ * those calls (0: the plain two-layer network).  With a warm start, each
+ * to-tolerance update first forms the sketched rows a_i of A = X S (CSR), runs the network on
  * [a_i; u_i^t] for every row and starts prox-CD from its output, with the
  * proximal centre kept at u_i^t.  A row starts from u_i^t instead when the
- * network's output is not finite or has the larger relative
- * projected-gradient norm of the two (counted in
+ * network's output is not finite, or misses the tolerance and has the larger
+ * relative projected-gradient norm of the two (counted in
  * dsanls_stats.warm_fallbacks).
  * Errors: STATE (the context cannot take a warm start), SHAPE. */
-dsanls_status dsanls_set_warm_start(dsanls_ctx* ctx, const float* params, int32_t hidden);
+dsanls_status dsanls_set_warm_start(dsanls_ctx* ctx, const float* params, int32_t hidden, int32_t residual);
 
 /* Keep the sketched rows A = X S (CSR form) of every subsampling update on
  * CSR input, for dsanls_gather_sketched_rows (used to build training pairs
@@ -315,8 +316,9 @@ dsanls_status dsanls_gemm_nt_bf16(const void* X, int64_t ldx, const void* Y, int
                                   int64_t ldc, int64_t rows, int64_t cols, int64_t K,
                                   void* hip_stream);
 
-/* ---- warm-start network: h = ReLU(a W1a + W1u u + b1),
- *      y = ReLU(u + W2 h + b2) (a correction to the cold start u)
+/* ---- warm-start network: h = ReLU(a W1a + W1u u + b1), y = ReLU(W2 h + b2);
+ *      with residual != 0 the variant y = ReLU(u + W2 h + b2) (its second
+ *      layer predicts a correction to the cold start u)
  * Packed FP32 parameters: W1a (d x H, row c = input column c) | W1u (H x k)
  * | b1 (H) | W2 (k x H) | b2 (k), dsanls_mlp_param_count(d, k, H) floats.
  * A batch: a as CSR (a_rowptr[rows + 1], a_cols, a_vals; int32 offsets),
@@ -325,14 +327,14 @@ dsanls_status dsanls_gemm_nt_bf16(const void* X, int64_t ldx, const void* Y, int
 int64_t dsanls_mlp_param_count(int32_t d, int32_t k, int32_t hidden);
 size_t dsanls_mlp_workspace_bytes(int32_t d, int32_t k, int32_t hidden, int64_t rows);
 /* out (rows x k) = network(a, U). */
-dsanls_status dsanls_mlp_forward(int32_t d, int32_t k, int32_t hidden, const float* params,
-                                 int64_t rows, const int32_t* a_rowptr, const int32_t* a_cols,
+dsanls_status dsanls_mlp_forward(int32_t d, int32_t k, int32_t hidden, int32_t residual,
+                                 const float* params, int64_t rows, const int32_t* a_rowptr, const int32_t* a_cols,
                                  const float* a_vals, const float* U, float* out, void* workspace,
                                  size_t workspace_bytes, void* hip_stream);
 /* grads (packed like params) of L = (1/rows) sum_b ||y_b - Y_b||^2; loss
  * (device, 2 floats) receives L as a (hi, lo) pair. */
-dsanls_status dsanls_mlp_gradients(int32_t d, int32_t k, int32_t hidden, const float* params,
-                                   float* grads, int64_t rows, const int32_t* a_rowptr,
+dsanls_status dsanls_mlp_gradients(int32_t d, int32_t k, int32_t hidden, int32_t residual,
+                                   const float* params, float* grads, int64_t rows, const int32_t* a_rowptr,
                                    const int32_t* a_cols, const float* a_vals,
                                    const int32_t* c_colptr, const int32_t* c_rows,
                                    const float* c_vals, const float* U, const float* Y,
@@ -340,7 +342,7 @@ dsanls_status dsanls_mlp_gradients(int32_t d, int32_t k, int32_t hidden, const f
                                    void* hip_stream);
 /* gradients, then one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, step
  * t >= 1) on params with moments adam_m, adam_v (packed like params). */
-dsanls_status dsanls_mlp_train_step(int32_t d, int32_t k, int32_t hidden, float* params,
+dsanls_status dsanls_mlp_train_step(int32_t d, int32_t k, int32_t hidden, int32_t residual, float* params,
                                     float* grads, float* adam_m, float* adam_v, int64_t step,
                                     float lr, int64_t rows, const int32_t* a_rowptr,
                                     const int32_t* a_cols, const float* a_vals,

@@ -5,10 +5,10 @@ subproblem: a two-layer perceptron maps the sketched row a_i (d values,
 sparse for a subsampling sketch) and the current row u_i^t (k values) to a
 starting point for prox-CD,
     h = ReLU(a_i W1a + W1u u_i + b1)        (hidden width H)
-    y = ReLU(u_i + W2 h + b2)               (k outputs, nonnegative)
-The second layer predicts a correction to u_i^t (a residual connection from
-the input row to the output pre-activation): the cold start of the solve is
-u_i^t itself, so the network starts from it and learns what to change.
+    y = ReLU(W2 h + b2)                     (k outputs, nonnegative)
+With residual=True a variant adds u_i^t to the output pre-activation,
+    y = ReLU(u_i + W2 h + b2),
+so that the second layer predicts a correction to the cold start u_i^t.
 It is trained with the mean squared error against the rows' NNLS solutions and
 the Adam optimiser (Kingma and Ba, "Adam: a method for stochastic
 optimization", ICLR 2015).  The paper has no such network; this module is
@@ -24,11 +24,13 @@ import numpy as np
 PARAMS = ("W1a", "W1u", "b1", "W2", "b2")
 
 
-def forward(p, A, U):
+def forward(p, A, U, residual=False):
     """Returns (Hpre, H, Ypre, Y)."""
     Hpre = np.asarray(A @ p["W1a"]) + U @ p["W1u"].T + p["b1"]
     H = np.maximum(Hpre, 0.0)
-    Ypre = U + H @ p["W2"].T + p["b2"]
+    Ypre = H @ p["W2"].T + p["b2"]
+    if residual:
+        Ypre = Ypre + U
     return Hpre, H, Ypre, np.maximum(Ypre, 0.0)
 
 
@@ -37,9 +39,10 @@ def loss(Yhat, Y):
     return float(np.sum((Yhat - Y) ** 2) / Y.shape[0])
 
 
-def backward(p, A, U, Y):
-    """Gradients of loss(forward(p, A, U)[3], Y) with respect to every parameter."""
-    Hpre, H, Ypre, Yhat = forward(p, A, U)
+def backward(p, A, U, Y, residual=False):
+    """Gradients of loss(forward(p, A, U, residual)[3], Y) with respect to
+    every parameter (u_i^t is an input, so the residual path adds none)."""
+    Hpre, H, Ypre, Yhat = forward(p, A, U, residual)
     B = Y.shape[0]
     dY = (2.0 / B) * (Yhat - Y) * (Ypre > 0)
     g = {"W2": dY.T @ H, "b2": dY.sum(axis=0)}

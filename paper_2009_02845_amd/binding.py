@@ -69,19 +69,19 @@ _SIGS = {
     "dsanls_debug_fetch": (c_int32, [c_vp, c_int32, c_vp, c_size_t]),
     "dsanls_set_timing": (c_int32, [c_vp, c_int32]),
     "dsanls_get_timing": (c_int32, [c_vp, ctypes.POINTER(Timing)]),
-    "dsanls_set_warm_start": (c_int32, [c_vp, c_vp, c_int32]),
+    "dsanls_set_warm_start": (c_int32, [c_vp, c_vp, c_int32, c_int32]),
     "dsanls_set_keep_sketched_rows": (c_int32, [c_vp, c_int32]),
     "dsanls_gather_sketched_rows": (c_int32, [c_vp, c_vp, c_int64, c_vp, c_vp, c_vp, c_int64,
                                               ctypes.POINTER(c_int64)]),
     "dsanls_mlp_param_count": (c_int64, [c_int32, c_int32, c_int32]),
     "dsanls_mlp_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32, c_int64]),
-    "dsanls_mlp_forward": (c_int32, [c_int32, c_int32, c_int32, c_vp, c_int64, c_vp, c_vp, c_vp, c_vp, c_vp,
-                                     c_vp, c_size_t, c_vp]),
-    "dsanls_mlp_gradients": (c_int32, [c_int32, c_int32, c_int32, c_vp, c_vp, c_int64, c_vp, c_vp, c_vp, c_vp,
-                                       c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size_t, c_vp]),
-    "dsanls_mlp_train_step": (c_int32, [c_int32, c_int32, c_int32, c_vp, c_vp, c_vp, c_vp, c_int64, c_float,
-                                        c_int64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
-                                        c_size_t, c_vp]),
+    "dsanls_mlp_forward": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_vp, c_int64, c_vp, c_vp, c_vp, c_vp,
+                                     c_vp, c_vp, c_size_t, c_vp]),
+    "dsanls_mlp_gradients": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_vp, c_vp, c_int64, c_vp, c_vp, c_vp,
+                                       c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size_t, c_vp]),
+    "dsanls_mlp_train_step": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_vp, c_vp, c_vp, c_vp, c_int64,
+                                        c_float, c_int64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                        c_vp, c_size_t, c_vp]),
     "dsanls_destroy": (c_int32, [c_vp]),
     "dsanls_status_string": (ctypes.c_char_p, [c_int32]),
     "dsanls_last_error": (ctypes.c_char_p, []),
@@ -233,10 +233,11 @@ class Solver:
         _check("dsanls_debug_fetch", self.lib.dsanls_debug_fetch(self.ctx, which, out.ctypes.data, out.nbytes))
         return out
 
-    def set_warm_start(self, params, hidden):
+    def set_warm_start(self, params, hidden, residual=False):
         """Install a packed warm-start network (float32 device tensor), or None."""
         self._warm = params
-        _check("dsanls_set_warm_start", self.lib.dsanls_set_warm_start(self.ctx, _ptr(params), hidden))
+        _check("dsanls_set_warm_start", self.lib.dsanls_set_warm_start(self.ctx, _ptr(params), hidden,
+                                                                        int(bool(residual))))
 
     def keep_sketched_rows(self, enable=True):
         _check("dsanls_set_keep_sketched_rows", self.lib.dsanls_set_keep_sketched_rows(self.ctx, int(enable)))
@@ -395,10 +396,11 @@ def mlp_unpack(flat, d, k, hidden):
 class MLP:
     """Device-side warm-start network: forward, gradients and Adam steps."""
 
-    def __init__(self, d, k, hidden, params, max_rows, stream=None):
+    def __init__(self, d, k, hidden, params, max_rows, stream=None, residual=False):
         import torch
         self.lib = load()
         self.d, self.k, self.h = d, k, hidden
+        self.residual = int(bool(residual))
         self.params = params
         self.grads = torch.zeros_like(params)
         self.m = torch.zeros_like(params)
@@ -415,14 +417,14 @@ class MLP:
         rows = U.shape[0]
         out = torch.empty((rows, self.k), dtype=torch.float32, device=U.device)
         _check("dsanls_mlp_forward", self.lib.dsanls_mlp_forward(
-            self.d, self.k, self.h, _ptr(self.params), rows, _ptr(a_rowptr), _ptr(a_cols), _ptr(a_vals),
+            self.d, self.k, self.h, self.residual, _ptr(self.params), rows, _ptr(a_rowptr), _ptr(a_cols), _ptr(a_vals),
             _ptr(U), _ptr(out), _ptr(self.ws), self.ws_bytes, _stream(self.stream)))
         return out
 
     def gradients(self, batch):
         a_rp, a_c, a_v, c_cp, c_r, c_v, U, Y = batch
         _check("dsanls_mlp_gradients", self.lib.dsanls_mlp_gradients(
-            self.d, self.k, self.h, _ptr(self.params), _ptr(self.grads), U.shape[0], _ptr(a_rp), _ptr(a_c),
+            self.d, self.k, self.h, self.residual, _ptr(self.params), _ptr(self.grads), U.shape[0], _ptr(a_rp), _ptr(a_c),
             _ptr(a_v), _ptr(c_cp), _ptr(c_r), _ptr(c_v), _ptr(U), _ptr(Y), _ptr(self.loss), _ptr(self.ws),
             self.ws_bytes, _stream(self.stream)))
         return self.grads
@@ -431,7 +433,7 @@ class MLP:
         a_rp, a_c, a_v, c_cp, c_r, c_v, U, Y = batch
         self.step += 1
         _check("dsanls_mlp_train_step", self.lib.dsanls_mlp_train_step(
-            self.d, self.k, self.h, _ptr(self.params), _ptr(self.grads), _ptr(self.m), _ptr(self.v), self.step,
+            self.d, self.k, self.h, self.residual, _ptr(self.params), _ptr(self.grads), _ptr(self.m), _ptr(self.v), self.step,
             lr, U.shape[0], _ptr(a_rp), _ptr(a_c), _ptr(a_v), _ptr(c_cp), _ptr(c_r), _ptr(c_v), _ptr(U), _ptr(Y),
             _ptr(self.loss), _ptr(self.ws), self.ws_bytes, _stream(self.stream)))
 

@@ -389,6 +389,7 @@ struct dsanls_ctx {
   bool ahead_pending[2] = {false, false};    // side-stream work on that side's buffers may be in flight
   // learned warm start (device parameters, caller-owned) and sketched rows
   const float* warm = nullptr;
+  bool warm_residual = false;
   bool keep_rows = false;
   int64_t rows_kept = -1;   // rows of the kept sketched matrix, -1 if none
   ~dsanls_ctx() {
@@ -682,7 +683,8 @@ dsanls_status half_iteration(dsanls_ctx* ctx, int side, int64_t t) {
   const float* start = nullptr;
   if (warm) {
     CHECK(mark(ctx, kPhSmall));
-    CHECK(mlp_forward(static_cast<int>(d), static_cast<int>(k), c.warm_hidden, ctx->warm, rows, L.a_rowptr[side],
+    CHECK(mlp_forward(static_cast<int>(d), static_cast<int>(k), c.warm_hidden, ctx->warm_residual, ctx->warm, rows,
+                      L.a_rowptr[side],
                       L.a_cols[side], L.a_vals[side], Wself, L.ustart, L.mlp_ws, L.mlp_ws_bytes, s));
     CHECK(mark(ctx, kPhSmall));
     start = L.ustart;
@@ -949,7 +951,7 @@ dsanls_status dsanls_get_stats(dsanls_ctx* ctx, dsanls_stats* out) {
   return DSANLS_OK;
 }
 
-dsanls_status dsanls_set_warm_start(dsanls_ctx* ctx, const float* params, int32_t hidden) {
+dsanls_status dsanls_set_warm_start(dsanls_ctx* ctx, const float* params, int32_t hidden, int32_t residual) {
   if (!ctx) return fail(DSANLS_E_STATE, "set_warm_start: context is NULL");
   if (params == nullptr) {
     ctx->warm = nullptr;
@@ -959,6 +961,7 @@ dsanls_status dsanls_set_warm_start(dsanls_ctx* ctx, const float* params, int32_
     return fail(DSANLS_E_STATE, "set_warm_start: the context was created with warm_hidden = 0");
   if (hidden != ctx->cfg.warm_hidden) return fail(DSANLS_E_SHAPE, "set_warm_start: hidden != cfg.warm_hidden");
   ctx->warm = params;
+  ctx->warm_residual = residual != 0;
   return DSANLS_OK;
 }
 

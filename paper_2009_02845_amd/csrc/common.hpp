@@ -275,7 +275,7 @@ dsanls_status launch_csr_transpose(const int64_t* rowptr, const int32_t* colidx,
 // MLP (mlp.hip)
 int64_t mlp_param_count(int d, int k, int hd);
 size_t mlp_ws_bytes(int d, int k, int hd, int64_t rows, bool forward_only);
-dsanls_status mlp_forward(int d, int k, int hd, const float* params, int64_t rows,
+dsanls_status mlp_forward(int d, int k, int hd, bool residual, const float* params, int64_t rows,
                           const int32_t* a_rowptr, const int32_t* a_cols, const float* a_vals,
                           const float* U, float* out, void* ws, size_t ws_bytes, hipStream_t s);
 // Sparse objective pieces: sum_nnz M_ij <u_i, v_j> and sum_nnz M_ij^2 as

@@ -1,11 +1,12 @@
 // Warm-start network for the to-tolerance NNLS solves: forward, backward
 // and Adam, all on the GPU.
 //
-//   h = ReLU(a W1a + W1u u + b1),  y = ReLU(u + W2 h + b2)
+//   h = ReLU(a W1a + W1u u + b1),  y = ReLU(W2 h + b2)
 //
 // a is the sketched row (sparse CSR for a subsampling sketch), u the
-// current factor row; the output layer adds a correction to u (the cold
-// start of the NNLS solve).  Parameters are one packed FP32 vector:
+// current factor row.  The residual variant adds u to the output
+// pre-activation, y = ReLU(u + W2 h + b2), so that its second layer
+// predicts a correction to u (the cold start of the NNLS solve).  Parameters are one packed FP32 vector:
 //   W1a (d x H, row c = weights of input column c) | W1u (H x k) | b1 (H)
 //   | W2 (k x H) | b2 (k)
 // The dense layers run on the FP32 MFMA GEMM (C = X Y^T); the sparse part
@@ -138,14 +139,14 @@ __global__ __launch_bounds__(256) void l1_sparse_kernel(const int32_t* __restric
   }
 }
 
-// X = ReLU(R + X + b): the output layer with its residual input R.
+// X = ReLU(X + b), or ReLU(R + X + b) with the residual input R (not null).
 __global__ __launch_bounds__(256) void bias_relu_kernel(float* __restrict__ X,
                                                         const float* __restrict__ b,
                                                         const float* __restrict__ R, int64_t rows,
                                                         int cols) {
   const int64_t n = rows * cols;
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    X[i] = relu(R[i] + X[i] + b[i % cols]);
+    X[i] = relu((R != nullptr ? R[i] : 0.f) + X[i] + b[i % cols]);
 }
 
 // dY = (2/B) (Yhat - Y) [Yhat > 0]; per-block compensated partial sums of
@@ -313,7 +314,7 @@ size_t mlp_ws_bytes(int d, int k, int hd, int64_t rows, bool forward_only) {
 
 // Forward pass: out (rows x k) = network(a, u).  H (rows x hd) is left in
 // the workspace for the backward pass.
-dsanls_status mlp_forward(int d, int k, int hd, const float* params, int64_t rows,
+dsanls_status mlp_forward(int d, int k, int hd, bool residual, const float* params, int64_t rows,
                           const int32_t* a_rowptr, const int32_t* a_cols, const float* a_vals,
                           const float* U, float* out, void* ws, size_t ws_bytes, hipStream_t s) {
   MlpWs w = carve(ws, d, k, hd, rows, /*forward_only=*/true);
@@ -327,17 +328,17 @@ dsanls_status mlp_forward(int d, int k, int hd, const float* params, int64_t row
   l1_sparse_kernel<<<static_cast<unsigned>(ceil_div(rows, 4 * kL1Rows)), 256, 0, s>>>(a_rowptr, a_cols, a_vals, p.W1a,
                                                                             p.b1, w.H, rows, hd);
   DSANLS_LAUNCHED("l1_sparse_kernel");
-  // layer 2: out = ReLU(U + H W2^T + b2)
+  // layer 2: out = ReLU(H W2^T + b2) (+ U in the residual variant)
   if ((st = launch_gemm_nt(w.H, hd, p.W2, hd, out, k, rows, k, hd, w.gemm_ws, w.gemm_ws_bytes, s)) != DSANLS_OK)
     return st;
-  bias_relu_kernel<<<grid_of(rows * k), 256, 0, s>>>(out, p.b2, U, rows, k);
+  bias_relu_kernel<<<grid_of(rows * k), 256, 0, s>>>(out, p.b2, residual ? U : nullptr, rows, k);
   DSANLS_LAUNCHED("bias_relu_kernel");
   return DSANLS_OK;
 }
 
 // Gradients of L = (1/B) sum_b ||yhat_b - y_b||^2; loss_out[0..1] gets the
 // loss before any update as a (hi, lo) pair.
-dsanls_status mlp_gradients(int d, int k, int hd, const float* params, float* grads, int64_t rows,
+dsanls_status mlp_gradients(int d, int k, int hd, bool residual, const float* params, float* grads, int64_t rows,
                             const int32_t* a_rowptr, const int32_t* a_cols, const float* a_vals,
                             const int32_t* c_colptr, const int32_t* c_rows, const float* c_vals,
                             const float* U, const float* Ylab, float* loss_out, void* ws,
@@ -349,7 +350,8 @@ dsanls_status mlp_gradients(int d, int k, int hd, const float* params, float* gr
   // H and Y sit at the same offsets in the forward-only layout; its GEMM
   // scratch overlaps dY and later buffers, which are written only after the
   // forward pass has finished on this stream.
-  if ((st = mlp_forward(d, k, hd, params, rows, a_rowptr, a_cols, a_vals, U, w.Y, ws, ws_bytes, s)) != DSANLS_OK)
+  if ((st = mlp_forward(d, k, hd, residual, params, rows, a_rowptr, a_cols, a_vals, U, w.Y, ws, ws_bytes, s)) !=
+      DSANLS_OK)
     return st;
   const Params p = split<Params>(params, d, k, hd);
   const Grads g = split<Grads>(grads, d, k, hd);
@@ -408,20 +410,21 @@ extern "C" size_t dsanls_mlp_workspace_bytes(int32_t d, int32_t k, int32_t hidde
   return (d < 1 || k < 1 || hidden < 1 || rows < 0) ? 0 : mlp_ws_bytes(d, k, hidden, rows, false);
 }
 
-extern "C" dsanls_status dsanls_mlp_forward(int32_t d, int32_t k, int32_t hidden, const float* params,
-                                            int64_t rows, const int32_t* a_rowptr,
+extern "C" dsanls_status dsanls_mlp_forward(int32_t d, int32_t k, int32_t hidden, int32_t residual,
+                                            const float* params, int64_t rows, const int32_t* a_rowptr,
                                             const int32_t* a_cols, const float* a_vals,
                                             const float* U, float* out, void* workspace,
                                             size_t workspace_bytes, void* hip_stream) {
   if (d < 1 || k < 1 || hidden < 1 || rows < 0) return fail(DSANLS_E_SHAPE, "mlp_forward: bad sizes");
   if (rows > 0 && (!params || !a_rowptr || !U || !out || !workspace))
     return fail(DSANLS_E_INVALID_ARG, "mlp_forward: null pointer");
-  return mlp_forward(d, k, hidden, params, rows, a_rowptr, a_cols, a_vals, U, out, workspace,
+  return mlp_forward(d, k, hidden, residual != 0, params, rows, a_rowptr, a_cols, a_vals, U, out, workspace,
                      workspace_bytes, static_cast<hipStream_t>(hip_stream));
 }
 
-extern "C" dsanls_status dsanls_mlp_gradients(int32_t d, int32_t k, int32_t hidden, const float* params,
-                                              float* grads, int64_t rows, const int32_t* a_rowptr,
+extern "C" dsanls_status dsanls_mlp_gradients(int32_t d, int32_t k, int32_t hidden, int32_t residual,
+                                              const float* params, float* grads, int64_t rows,
+                                              const int32_t* a_rowptr,
                                               const int32_t* a_cols, const float* a_vals,
                                               const int32_t* c_colptr, const int32_t* c_rows,
                                               const float* c_vals, const float* U, const float* Y,
@@ -430,12 +433,13 @@ extern "C" dsanls_status dsanls_mlp_gradients(int32_t d, int32_t k, int32_t hidd
   if (d < 1 || k < 1 || hidden < 1 || rows < 1) return fail(DSANLS_E_SHAPE, "mlp_gradients: bad sizes");
   if (!params || !grads || !a_rowptr || !c_colptr || !U || !Y || !loss_out || !workspace)
     return fail(DSANLS_E_INVALID_ARG, "mlp_gradients: null pointer");
-  return mlp_gradients(d, k, hidden, params, grads, rows, a_rowptr, a_cols, a_vals, c_colptr, c_rows,
-                       c_vals, U, Y, loss_out, workspace, workspace_bytes, nullptr,
+  return mlp_gradients(d, k, hidden, residual != 0, params, grads, rows, a_rowptr, a_cols, a_vals, c_colptr,
+                       c_rows, c_vals, U, Y, loss_out, workspace, workspace_bytes, nullptr,
                        static_cast<hipStream_t>(hip_stream));
 }
 
-extern "C" dsanls_status dsanls_mlp_train_step(int32_t d, int32_t k, int32_t hidden, float* params,
+extern "C" dsanls_status dsanls_mlp_train_step(int32_t d, int32_t k, int32_t hidden, int32_t residual,
+                                               float* params,
                                                float* grads, float* adam_m, float* adam_v,
                                                int64_t step, float lr, int64_t rows,
                                                const int32_t* a_rowptr, const int32_t* a_cols,
@@ -446,7 +450,7 @@ extern "C" dsanls_status dsanls_mlp_train_step(int32_t d, int32_t k, int32_t hid
                                                void* hip_stream) {
   if (step < 1 || !(lr > 0.f)) return fail(DSANLS_E_INVALID_ARG, "mlp_train_step: step >= 1 and lr > 0");
   if (!adam_m || !adam_v) return fail(DSANLS_E_INVALID_ARG, "mlp_train_step: null Adam state");
-  dsanls_status st = dsanls_mlp_gradients(d, k, hidden, params, grads, rows, a_rowptr, a_cols, a_vals,
+  dsanls_status st = dsanls_mlp_gradients(d, k, hidden, residual, params, grads, rows, a_rowptr, a_cols, a_vals,
                                           c_colptr, c_rows, c_vals, U, Y, loss_out, workspace,
                                           workspace_bytes, hip_stream);
   if (st != DSANLS_OK) return st;

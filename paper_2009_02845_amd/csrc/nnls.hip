@@ -903,6 +903,12 @@ __global__ __launch_bounds__(64 * NWV) void prox_cd_tol_kernel(const float* __re
     const int ncand = start != nullptr ? 2 : 1;
 #pragma nounroll
     for (int c = 0; c < ncand; ++c) {
+      if (c == 1 && !__any(valid && !(ok && res_w <= tol))) {
+        // every row keeps its warm start (finite and within tolerance): the
+        // cold candidate's KKT pass is skipped
+        res_c = INFINITY;
+        break;
+      }
       if (c == 1) load_rows<KC, W, SW, true>(panel, C, row0, nrows, k, true, u);
       float gc = 0.f;
       const float r = kkt<KC, W, SW, true>(qp, sg, den, R, C, row0, nrows, k, mu, u, gc);
@@ -912,7 +918,9 @@ __global__ __launch_bounds__(64 * NWV) void prox_cd_tol_kernel(const float* __re
     }
     res = res_w;
     if (start != nullptr) {
-      const bool warm = ok && res_w < res_c;
+      // a finite warm start within tolerance is kept; otherwise the
+      // candidate with the smaller residual
+      const bool warm = ok && (res_w <= tol || res_w < res_c);
       fell_back = valid && !warm;
       if (__any(warm)) load_rows<KC, W, SW, true>(panel, start, row0, nrows, k, warm, u);
       res = warm ? res_w : res_c;
@@ -1158,12 +1166,17 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
     const float res_w = kkt_pass(start != nullptr ? gw : gd);
     float res_c = 0.f;
     if (start != nullptr) {
-      load_ub(C, ~0ull);
-      res_c = kkt_pass(gd);
+      if (__any(valid && !(ok && res_w <= tol))) {
+        load_ub(C, ~0ull);
+        res_c = kkt_pass(gd);
+      } else {
+        // every row keeps its warm start (finite and within tolerance)
+        res_c = INFINITY;
+      }
     }
     res = res_w;
     if (start != nullptr) {
-      const bool warm = ok && res_w < res_c;
+      const bool warm = ok && (res_w <= tol || res_w < res_c);
       fell_back = valid && !warm;
       const unsigned long long wm = __ballot(warm);
       if (wm != 0ull) load_ub(start, wm);
