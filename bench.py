@@ -189,15 +189,15 @@ def cpu_baseline(w, M, U0, V0, budget_s=12.0, max_iters=5, Mt=None, half=False):
 # after any change to them the traffic is reported as null.
 CAL_FETCH, CAL_WRITE = 2.0, 1.0
 TRAFFIC = {
-    "dense-20000x10000": {"files": ["gemm.hip", "common.hpp"],
-                          "sha256": "477d98a43fd4e6bed56ce09f6405edee400d8b73fe09c36268615e925d203e15",
+    "dense-20000x10000": {"files": ["gemm.hip"],
+                          "sha256": "528bbd6a909efc6db290b4aa3aadad6fff075009e7c6bd17c23241f09d68dd09",
                           "fetch_kib": 2419643.13, "write_kib": 120000.0},
     "sparse-500000x200000": {"files": ["nnls.hip", "common.hpp"],
                              "sha256": "2635fe2dd953aac9dd633be9b88361725cdb69ed43d1a98dabd3a0d3a4eb3e53",
                              "fetch_kib": 182695.75, "write_kib": 144235.05},
-    "dense-50000x20000-bf16": {"files": ["gemm.hip", "common.hpp"],
-                               "sha256": "477d98a43fd4e6bed56ce09f6405edee400d8b73fe09c36268615e925d203e15",
-                               "fetch_kib": 20248669.94, "write_kib": 1120000.0},
+    "dense-50000x20000-bf16": {"files": ["gemm.hip"],
+                               "sha256": "528bbd6a909efc6db290b4aa3aadad6fff075009e7c6bd17c23241f09d68dd09",
+                               "fetch_kib": 19776476.63, "write_kib": 1120000.0},
 }
 
 
@@ -297,14 +297,10 @@ def run_warm(args, w, torch, B):
     t_pairs = time.perf_counter() - t0
     print(f"[bench] {A_all.shape[0]} pairs in {t_pairs:.1f} s", file=sys.stderr, flush=True)
 
-    # 2) training on the GPU (the library's forward/backward/Adam kernels)
+    # 2) training on the GPU (the library's forward/backward/Adam kernels):
+    # the plain two-layer network (the specified form) and the residual
+    # variant y = ReLU(u + W2 h + b2), same data, batches and schedule
     from paper_2009_02845_amd import synth
-    t0 = time.perf_counter()
-    p0 = synth.mlp_init(d, k, H, args.seed)
-    # data-dependent scale of the sparse first layer: the sketched values are
-    # sqrt(n/d) M_ij, far from unit scale, so W1a starts divided by their mean
-    p0["W1a"] = (p0["W1a"] / max(float(np.mean(np.abs(A_all.data))), 1e-12)).astype(np.float32)
-    params = B.mlp_pack(p0, device=dev)
     bs = w["batch"]
     perm = np.random.default_rng(5).permutation(A_all.shape[0])
     batches = []
@@ -315,26 +311,39 @@ def run_warm(args, w, torch, B):
         batches.append((to(Ab.indptr, np.int32), to(Ab.indices, np.int32), to(Ab.data, np.float32),
                         to(Cb.indptr, np.int32), to(Cb.indices, np.int32), to(Cb.data, np.float32),
                         to(Ut_all[idx], np.float32), to(Ys_all[idx], np.float32)))
-    net = B.MLP(d, k, H, params, max_rows=bs)
-    losses = []
-    for ep in range(w["epochs"]):
-        tot = 0.0
-        for bt in batches:
-            net.train_step(bt, w["lr"])
-            tot += net.last_loss()
-        losses.append(tot / len(batches))
-        print(f"[bench] epoch {ep}: mean loss {losses[-1]:.4g}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
+    nets, training = {}, {}
+    for form in ("plain", "residual"):
+        t0 = time.perf_counter()
+        p0 = synth.mlp_init(d, k, H, args.seed)
+        # data-dependent scales: the sketched values are sqrt(n/d) M_ij, far
+        # from unit scale, so W1a starts divided by their mean; the plain
+        # network's output bias starts at the mean label (the residual one
+        # starts at u_i^t itself)
+        p0["W1a"] = (p0["W1a"] / max(float(np.mean(np.abs(A_all.data))), 1e-12)).astype(np.float32)
+        if form == "plain":
+            p0["b2"] = np.mean(Ys_all, axis=0).astype(np.float32)
+        params = B.mlp_pack(p0, device=dev)
+        net = B.MLP(d, k, H, params, max_rows=bs, residual=form == "residual")
+        losses = []
+        for ep in range(w["epochs"]):
+            tot = 0.0
+            for bt in batches:
+                net.train_step(bt, w["lr"])
+                tot += net.last_loss()
+            losses.append(tot / len(batches))
+            print(f"[bench] {form} epoch {ep}: mean loss {losses[-1]:.4g}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        nets[form] = params
+        training[form] = {"epoch_loss": losses, "training_s": time.perf_counter() - t0}
     # identity baseline of the loss: predicting u_i^t itself
     ident = float(np.mean(np.sum((Ut_all - Ys_all) ** 2, axis=1)))
 
-    # 3) cold vs warm on an unseen sketch seed
+    # 3) cold vs warm (both forms) on an unseen sketch seed
     res = {}
-    for mode in ("cold", "warm"):
-        s, U, V = solver(6, w["tol"], warm_hidden=H if mode == "warm" else 0)
-        if mode == "warm":
-            s.set_warm_start(params, H)
+    for mode in ("cold", "plain", "residual"):
+        s, U, V = solver(6, w["tol"], warm_hidden=0 if mode == "cold" else H)
+        if mode != "cold":
+            s.set_warm_start(nets[mode], H, residual=mode == "residual")
         s.iteration(0)
         torch.cuda.synchronize()
         U.copy_(U0d)
@@ -358,7 +367,10 @@ def run_warm(args, w, torch, B):
                      "nnls_rows_per_s": rows / (tm["nnls_ms"] / 1e3),
                      "phase_ms_per_step": {p: tm[p + "_ms"] / w["iters"] for p in ("sketch", "product", "small", "nnls")},
                      "rel_objective": s.objective()}
+        print(f"[bench] {mode}: {res[mode]['iterations_per_s']:.2f} it/s, {res[mode]['sweeps_per_row']:.2f} sweeps/row, "
+              f"fallback {res[mode]['fallback_rate']:.2f}", file=sys.stderr, flush=True)
         s.close()
+    res["warm"] = res["plain"]
     # 2 k^2 flop per row-sweep and per KKT test of a row (one test after
     # each sweep and one before the first), mean over the two sides; at
     # k % 4 == 0, 64 < k <= 100 both run on the matrix cores (block form)
@@ -372,9 +384,13 @@ def run_warm(args, w, torch, B):
         "value": res["warm"]["iterations_per_s"], "ms_per_step": res["warm"]["ms_per_step"],
         "rel_objective": res["warm"]["rel_objective"],
         "nnls_rows_per_s": res["warm"]["nnls_rows_per_s"],
-        "warm_start": {"cold": res["cold"], "warm": res["warm"], "pairs": int(A_all.shape[0]),
-                       "pair_generation_s": t_pairs, "training_s": t_train, "epoch_loss": losses,
-                       "identity_loss": ident, "label_tol": w["label_tol"]},
+        "warm_start": {"cold": res["cold"], "warm_plain": res["plain"], "warm_residual": res["residual"],
+                       "pairs": int(A_all.shape[0]), "pair_generation_s": t_pairs, "training": training,
+                       "identity_loss": ident, "label_tol": w["label_tol"],
+                       "sweeps_saved_per_row": {f: res["cold"]["sweeps_per_row"] - res[f]["sweeps_per_row"]
+                                                for f in ("plain", "residual")},
+                       "speedup_vs_cold": {f: res[f]["iterations_per_s"] / res["cold"]["iterations_per_s"]
+                                           for f in ("plain", "residual")}},
         "roofline": {"kernel": f"prox-CD to tolerance ({kern}, all passes of one update)",
                      "bound": "mfma" if block else "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                      "frac": ach / peak, "traffic": None, "flops_per_launch": flops,
@@ -438,7 +454,7 @@ def run_to_eps(args, w, torch, B, K, W):
             cfg = B.make_config(m, n, k, d, d, sketch="gaussian", solver="prox_cd", precision=form, sweeps=1,
                                 alpha=w.get("alpha", 1.0), beta=w.get("beta", 1.0), seed=0)
             solver = B.Solver(cfg, B.dense_matrix(Md), U, V, tensors=[Md])
-            if si == 0:
+            if si == 0 and not args.no_oracle_error:
                 # one U update from U^0, V^0 against the FP64 oracle on sampled rows
                 solver.update_U(0)
                 torch.cuda.synchronize()
@@ -664,6 +680,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-error", action="store_true",
+                    help="skip the per-update comparison with the FP64 oracle (profiler runs)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--seeds", type=int, default=None,
                     help="data seeds of the to-eps* workload (default: the workload's three)")
