@@ -371,14 +371,15 @@ def run_warm(args, w, torch, B):
               f"fallback {res[mode]['fallback_rate']:.2f}", file=sys.stderr, flush=True)
         s.close()
     res["warm"] = res["plain"]
-    # 2 k^2 flop per row-sweep and per KKT test of a row (one test after
-    # each sweep and one before the first), mean over the two sides; at
-    # k % 4 == 0, 64 < k <= 100 both run on the matrix cores (block form)
-    flops = 2.0 * k * k * (m + n) / 2 * (2.0 * res["warm"]["sweeps_per_row"] + 1.0)
+    # algorithmic work of a to-tolerance update: 2 k^2 flop per row-sweep and
+    # 2 k^2 per row for its first gradient u Q - q (the block form carries
+    # the gradient, so a stopping test is O(k)); mean over the two sides.
+    # At k % 4 == 0, 64 < k <= 100 the sweeps run on the matrix cores.
+    flops = 2.0 * k * k * (m + n) / 2 * (res["warm"]["sweeps_per_row"] + 1.0)
     nnls_avg = res["warm"]["phase_ms_per_step"]["nnls"] / 2 / 1e3
     ach = flops / nnls_avg / 1e12
     block = k % 4 == 0 and 64 < k <= 100
-    kern = "prox_cd_mfma_tol_kernel" if block else "prox_cd_tol_kernel"
+    kern = "prox_cd_grad_tol_kernel" if block else "prox_cd_tol_kernel"
     peak = PEAK["fp32_mfma_tflops"] if block else PEAK["fp32_valu_tflops"]
     return {
         "value": res["warm"]["iterations_per_s"], "ms_per_step": res["warm"]["ms_per_step"],

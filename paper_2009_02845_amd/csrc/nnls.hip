@@ -971,36 +971,56 @@ __global__ __launch_bounds__(256) void qsum_kernel(const float4* __restrict__ R,
   }
 }
 
-// One pass of the to-tolerance solve in the block form of
-// prox_cd_mfma_kernel: the same passes, start choice, per-row stopping and
-// bookkeeping as prox_cd_tol_kernel, with every sweep and every KKT test
-// taking the coupling between 16-coordinate blocks on the matrix cores.  A
-// row that is done (or has no budget left) keeps its values: all rows of
-// the wave enter the products, only running rows take new values.  With
-// WITHC, q = r + mu c is formed panel by panel from R and C; without, R
-// already holds q (formed once for all passes) and C is read only as the
-// cold start of the first pass, each row before its wave writes it (so C
-// may alias U).  A run-time flag in place of WITHC made the passes 25%
-// slower.
+// One pass of the to-tolerance solve in the block form, carrying each row's
+// gradient g = u Q - q (Q = G + mu I, the row problem of eq. reg_sub
+// divided by 2) in registers instead of re-forming it for every stopping
+// test.  The passes, start choice, per-row stopping and bookkeeping are
+// those of prox_cd_tol_kernel.  Coordinate j's prox-CD step (eq. entry_sol)
+// is u_j <- max(u_j - g_j / Q_jj, 0) with g_j current, the same Gauss-Seidel
+// update written through the gradient.  Per coordinate block b (16
+// coordinates, all in order):
+//   - the block's u and g go to one lane per row through the LDS tile; the
+//     16 coordinates step in order, each step delta_j moving the g of the
+//     block's later coordinates by delta_j Q_jl (the block's own 16 x 16 part
+//     of Q read by LDS broadcast);
+//   - the block's new u returns to the operand layout, and every block of g
+//     takes g_bb += delta_b Q_{b,bb}, one (16 x 16) x (16 x 64) product per
+//     block on v_mfma_f32_16x16x4f32 (16 MFMAs each, the operand read from Q
+//     in LDS).
+// After the sweep g is exact (up to rounding) at the new iterate, so the
+// stopping test, ||pg|| / ||q|| <= tol with pg_j = g_j where u_j > 0 and
+// min(g_j, 0) where u_j = 0, costs O(k) per row instead of a pass of 2 k^2
+// flop.  Each pass forms g afresh (the same products, from u and q), so the
+// rounding carried in g is that of at most one pass's sweeps.  Rows that are
+// done (or out of budget) enter the products with delta = 0 and keep their
+// values.  Registers: u and g of 64 rows in the operand layout (lane (m, g)
+// holds rows 16 r + m, coordinates 16 b + 4 g .. + 3), 2 KP floats a lane,
+// so one wave per SIMD; the block loop is unrolled so every index is
+// static.  With WITHC, q = r + mu c is read from R and C when g is formed;
+// without, R already holds q.  C (the cold start of the first pass) is read
+// before the wave writes its rows, so it may alias U.
 template <int KC, bool WITHC>
-__global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void prox_cd_grad_tol_kernel(
     const float* __restrict__ gp, const float* __restrict__ den, const float* __restrict__ inv,
     const float* __restrict__ R, const float* C, const float* start, float* U, int64_t rows, int k,
     float mu, float tol, int max_sweeps, float upper, TolPass pass) {
   typedef float f4 __attribute__((ext_vector_type(4)));
-  constexpr int NBK = MfmaCd<KC>::NBK, KP = MfmaCd<KC>::KP, NWV = MfmaCd<KC>::NWV;
-  __shared__ __attribute__((aligned(16))) float sd[NBK * 256];
-  __shared__ float sinv[KP];
-  __shared__ float sden[KP];
-  __shared__ QPanel<16> qps[NWV];
+  constexpr int NBK = MfmaCd<KC>::NBK, KP = MfmaCd<KC>::KP, NWV = 4, QS = KP + 4;
+  // Q (row j: G_jl, G_jj + mu on the diagonal, zero outside KC x KC; rows
+  // padded to QS floats), 1 / Q_jj and its indicator (0 where Q_jj = 0 or
+  // past k: such a coordinate is set to 0), and one transpose tile per wave
+  __shared__ __attribute__((aligned(16))) float sq[KP * QS];
+  __shared__ __attribute__((aligned(16))) float sinv[KP];
+  __shared__ __attribute__((aligned(16))) float sone[KP];
   __shared__ __attribute__((aligned(16))) float xs[NWV][64 * 16];
-  for (int i = threadIdx.x; i < NBK * 256; i += 64 * NWV) {
-    const int bk = i >> 8, j = 16 * bk + ((i >> 4) & 15), l = 16 * bk + (i & 15);
-    sd[i] = j < KC && l < KC ? gp[j * KC + l] : 0.f;
+  for (int i = threadIdx.x; i < KP * QS; i += 64 * NWV) {
+    const int j = i / QS, l = i - j * QS;
+    sq[i] = j < KC && l < KC ? (j == l ? den[j] : gp[j * KC + l]) : 0.f;
   }
   for (int i = threadIdx.x; i < KP; i += 64 * NWV) {
-    sinv[i] = i < KC ? inv[i] : 0.f;
-    sden[i] = i < KC ? den[i] : 0.f;
+    const float v = i < KC ? inv[i] : 0.f;
+    sinv[i] = v;
+    sone[i] = v != 0.f ? 1.f : 0.f;
   }
   __syncthreads();
   const int wib = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -1024,128 +1044,178 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
   const bool valid = lane < nrows;
   const int64_t myrow = valid ? (rmap != nullptr ? static_cast<int64_t>(rmap[lane]) : row0 + lane) : 0;
   const float ubnd = upper > 0.f ? upper : INFINITY;
-  QPanel<16>& qp = qps[wib];
   float* X = xs[wib];
 
-  f4 ub[NBK][4];
-  // rows of P into the operand layout, for the rows whose bit is set in take
-  auto load_ub = [&](const float* P, unsigned long long take) {
+  // offset of row 16 r + m of the wave in the row-major matrices (-1: past
+  // the wave's rows)
+  int64_t roff[4];
 #pragma unroll
-    for (int b = 0; b < NBK; ++b)
+  for (int r = 0; r < 4; ++r) {
+    const int n = 16 * r + m;
+    roff[r] = n < nrows ? (rmap != nullptr ? static_cast<int64_t>(rmap[n]) : row0 + n) * k : -1;
+  }
+  f4 ub[NBK][4], gb[NBK][4];
+  // every row into the operand layout: from P1 where the row's bit is set in
+  // take, else from P0 (one load per value either way)
+  auto load_ub = [&](const float* P0, const float* P1, unsigned long long take) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float* P = (take >> (16 * r + m)) & 1ull ? P1 : P0;
+#pragma unroll
+      for (int b = 0; b < NBK; ++b) {
+        const int c = 16 * b + 4 * g;
+        ub[b][r] = roff[r] >= 0 && c < k ? *reinterpret_cast<const f4*>(P + roff[r] + c) : f4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  };
+  // per-row sums (lane per row) of per-(lane, quarter) partial sums: the
+  // four lanes of a row quarter add up, lane 16 g + m keeps quarter g
+  auto row_sum = [&](float (&s)[4]) -> float {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      s[r] += __shfl_xor(s[r], 16, 64);
+      s[r] += __shfl_xor(s[r], 32, 64);
+    }
+    return g == 0 ? s[0] : g == 1 ? s[1] : g == 2 ? s[2] : s[3];
+  };
+  // g = u Q - q for the wave's rows, and ||q||^2 of each row (lane per row)
+  float q2 = 0.f;
+  auto form_g = [&]() {
+    float qs[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int bb = 0; bb < NBK; ++bb) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int n = 16 * r + m, c = 16 * b + 4 * g;
-        if ((take >> n) & 1ull) {
-          if (n < nrows && c < k) {
-            const int64_t row = rmap != nullptr ? static_cast<int64_t>(rmap[n]) : row0 + n;
-            ub[b][r] = *reinterpret_cast<const f4*>(P + row * k + c);
-          } else {
-            ub[b][r] = f4{0.f, 0.f, 0.f, 0.f};
+        const int c = 16 * bb + 4 * g;
+        f4 q = f4{0.f, 0.f, 0.f, 0.f};
+        if (roff[r] >= 0 && c < k) {
+          q = *reinterpret_cast<const f4*>(R + roff[r] + c);
+          if (WITHC) q += mu * *reinterpret_cast<const f4*>(C + roff[r] + c);
+        }
+        qs[r] += (q[0] * q[0] + q[1] * q[1]) + (q[2] * q[2] + q[3] * q[3]);
+        gb[bb][r] = -q;
+      }
+#pragma unroll
+      for (int b = 0; b < NBK; ++b) {
+        const f4 a = *reinterpret_cast<const f4*>(sq + (16 * bb + m) * QS + 16 * b + 4 * g);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            gb[bb][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], ub[b][r][e], gb[bb][r], 0, 0, 0);
+      }
+      // one block of g at a time (the scheduler would otherwise hoist every
+      // block's loads, beyond the register file)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    q2 = row_sum(qs);
+  };
+  // relative projected-gradient norm of each row (lane per row) from the
+  // carried g; gk takes the non-finite guard of the row's g
+  auto kkt = [&](float& gk) -> float {
+    float s[4] = {0.f, 0.f, 0.f, 0.f}, z[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int bb = 0; bb < NBK; ++bb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          // coordinates past k hold g = 0 exactly
+          const float gv = gb[bb][r][e];
+          z[r] = __builtin_fmaf(gv, 0.f, z[r]);
+          const float pg = ub[bb][r][e] > 0.f ? gv : fminf(gv, 0.f);
+          s[r] = __builtin_fmaf(pg, pg, s[r]);
+        }
+    guard(gk, row_sum(z));
+    return sqrtf(row_sum(s)) / fmaxf(sqrtf(q2), 1e-30f);
+  };
+  float gd = 0.f;   // non-finite guard of this lane's row (a warm start's own values are not folded in)
+  auto sweep = [&](bool run) {
+#pragma unroll
+    for (int b = 0; b < NBK; ++b) {
+      f4 ur[4], gr[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) *reinterpret_cast<f4*>(X + cd_chunk(16 * r + m, g)) = ub[b][r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ur[c] = *reinterpret_cast<const f4*>(X + cd_chunk(lane, c));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) *reinterpret_cast<f4*>(X + cd_chunk(16 * r + m, g)) = gb[b][r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) gr[c] = *reinterpret_cast<const f4*>(X + cd_chunk(lane, c));
+      // the block's coordinates in order (the last block of a rank that is
+      // not a multiple of 16 has only KC % 16 of them)
+      constexpr int NL = KC % 16 != 0 ? KC % 16 : 16;
+      const int nj = b == NBK - 1 ? NL : 16;
+      const float* qb = sq + (16 * b) * QS + 16 * b;
+      // row jj of the block's part of Q, one row ahead of its use
+      f4 qr[4], qn[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) qr[c] = *reinterpret_cast<const f4*>(qb + 4 * c);
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        if (jj < nj) {
+          if (jj + 1 < nj) {
+#pragma unroll
+            for (int c = (jj + 1) / 4; c < 4; ++c) qn[c] = *reinterpret_cast<const f4*>(qb + (jj + 1) * QS + 4 * c);
+          }
+          const float uj = ur[jj / 4][jj % 4];
+          const float x = __builtin_fmaf(-gr[jj / 4][jj % 4], sinv[16 * b + jj], uj * sone[16 * b + jj]);
+          guard(gd, x);
+          const float v = fminf(fmaxf(x, 0.f), ubnd);
+          const float dl = run ? v - uj : 0.f;
+          if (run) ur[jj / 4][jj % 4] = v;
+          // the later coordinates of the block see the step
+#pragma unroll
+          for (int l = jj + 1; l < 16; ++l)
+            if (l < nj) gr[l / 4][l % 4] = __builtin_fmaf(dl, qr[l / 4][l % 4], gr[l / 4][l % 4]);
+          if (jj + 1 < nj) {
+#pragma unroll
+            for (int c = (jj + 1) / 4; c < 4; ++c) qr[c] = qn[c];
           }
         }
       }
-  };
-  f4 an[NBK - 1];
-  auto fetch_a = [&](int b) {
-#pragma unroll
-    for (int i = 1; i < NBK; ++i) {
-      const int bb = b + i < NBK ? b + i : b + i - NBK;
-      const int j = 16 * b + m, l = 16 * bb + 4 * g;
-      const bool in = j < KC && l < KC;
-      an[i - 1] = *reinterpret_cast<const f4*>(gp + (in ? j * KC + l : 0));
-      if (!in) an[i - 1] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-  };
-  // T of block b (in ub[0]) from the other blocks, then block b's u and T
-  // to one lane per row, and its right-hand side
-  auto block_in = [&](int b, f4 (&ur)[4], f4 (&tr)[4], typename RowBlocks<16, 16>::vec& qb) {
-    f4 a[NBK - 1];
-#pragma unroll
-    for (int i = 0; i + 1 < NBK; ++i) a[i] = an[i];
-    f4 acc[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int i = 1; i < NBK; ++i)
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i - 1][e], ub[i][r][e], acc[r], 0, 0, 0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) *reinterpret_cast<f4*>(X + cd_chunk(16 * r + m, g)) = ub[0][r];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) ur[c] = *reinterpret_cast<const f4*>(X + cd_chunk(lane, c));
-#pragma unroll
-    for (int r = 0; r < 4; ++r) *reinterpret_cast<f4*>(X + cd_chunk(16 * r + m, g)) = acc[r];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) tr[c] = *reinterpret_cast<const f4*>(X + cd_chunk(lane, c));
-    q_read<16>(qp, mu, 16 * b, k, WITHC, qb);
-    wait_lds_reads();
-    if (b + 1 < NBK) q_issue<16>(qp, R, C, row0, nrows, k, 16 * (b + 1), WITHC, rmap);
-    fetch_a(b + 1 < NBK ? b + 1 : 0);
-  };
-  // rotate the blocks by one, block b's (new) values taking the last slot
-  auto block_out = [&](const f4 (&nb)[4]) {
-#pragma unroll
-    for (int i = 0; i + 1 < NBK; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) ub[i][r] = ub[i + 1][r];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) ub[NBK - 1][r] = nb[r];
-  };
-  float gd = 0.f;   // non-finite guard of this lane's row (a warm start's own values are not folded in)
-  auto sweep_pass = [&](bool run) {
-    wait_lds_reads();
-    q_issue<16>(qp, R, C, row0, nrows, k, 0, WITHC, rmap);
-#pragma nounroll
-    for (int b = 0; b < NBK; ++b) {
-      f4 ur[4], tr[4];
-      typename RowBlocks<16, 16>::vec qb;
-      block_in(b, ur, tr, qb);
-      const float* gb = sd + 256 * b;
-      if (KC % 16 != 0 && b == NBK - 1)
-        cd_block<(KC % 16 != 0 ? KC % 16 : 16), 16>(gb, sinv + 16 * b, mu, ubnd, false, run, qb, tr, ur, gd);
-      else
-        cd_block<16, 16>(gb, sinv + 16 * b, mu, ubnd, false, run, qb, tr, ur, gd);
+      __builtin_amdgcn_sched_barrier(0);
+      // the new values back to the operand layout; the step of the block
 #pragma unroll
       for (int c = 0; c < 4; ++c) *reinterpret_cast<f4*>(X + cd_chunk(lane, c)) = ur[c];
-      f4 nb[4];
+      f4 dlt[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) nb[r] = *reinterpret_cast<const f4*>(X + cd_chunk(16 * r + m, g));
-      block_out(nb);
-    }
-  };
-  auto kkt_pass = [&](float& gk) -> float {
-    float pg2 = 0.f, q2 = 0.f;
-    wait_lds_reads();
-    q_issue<16>(qp, R, C, row0, nrows, k, 0, WITHC, rmap);
-#pragma nounroll
-    for (int b = 0; b < NBK; ++b) {
-      f4 ur[4], tr[4];
-      typename RowBlocks<16, 16>::vec qb;
-      block_in(b, ur, tr, qb);
-      const float* gb = sd + 256 * b;
-      if (KC % 16 != 0 && b == NBK - 1)
-        kkt_block<(KC % 16 != 0 ? KC % 16 : 16)>(gb, sden + 16 * b, 16 * b, k, qb, tr, ur, pg2, q2, gk);
-      else
-        kkt_block<16>(gb, sden + 16 * b, 16 * b, k, qb, tr, ur, pg2, q2, gk);
-      f4 nb[4];
+      for (int r = 0; r < 4; ++r) {
+        const f4 nb = *reinterpret_cast<const f4*>(X + cd_chunk(16 * r + m, g));
+        dlt[r] = nb - ub[b][r];
+        ub[b][r] = nb;
+      }
+      // g_bb += delta_b Q_{b, bb} for every block (the operand: Q[16 bb +
+      // m][16 b + 4 g + e], by symmetry)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) nb[r] = ub[0][r];
-      block_out(nb);
+      for (int bb = 0; bb < NBK; ++bb) {
+        const f4 a = *reinterpret_cast<const f4*>(sq + (16 * bb + m) * QS + 16 * b + 4 * g);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            gb[bb][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], dlt[r][e], gb[bb][r], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
-    return sqrtf(pg2) / fmaxf(sqrtf(q2), 1e-30f);
   };
 
-  fetch_a(0);
   int used = 0;
   bool fell_back = false;
   float res = INFINITY;   // a listed row is pending
-  if (rmap == nullptr) {
-    load_ub(start != nullptr ? start : U, ~0ull);
-    bool ok = valid;
-    if (start != nullptr) {
+  // g of the start.  A listed row resumes (pending).  In the first pass
+  // with a warm start: the warm start's g and test, then (unless every row
+  // keeps its finite warm start, within tolerance) the cold start's, then
+  // (rows mixed) g of the chosen starts.  Each phase loads every row anew.
+  const bool cand = rmap == nullptr && start != nullptr;
+  const float* src0 = cand ? start : U;
+  const float* src1 = nullptr;
+  unsigned long long take = 0ull;
+  bool ok = valid;
+  float gw = 0.f, res_w = 0.f;
+  for (int phase = 0;; ++phase) {
+    load_ub(src0, src1, take);
+    if (cand && phase == 0) {
       // a row is finite when none of its four lanes' values is not
       unsigned long long bad[4];
 #pragma unroll
@@ -1162,29 +1232,32 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
       const unsigned long long mine = (br >> mm) | (br >> (mm + 16)) | (br >> (mm + 32)) | (br >> (mm + 48));
       ok = ok && !(mine & 1ull);
     }
-    float gw = 0.f;
-    const float res_w = kkt_pass(start != nullptr ? gw : gd);
-    float res_c = 0.f;
-    if (start != nullptr) {
-      if (__any(valid && !(ok && res_w <= tol))) {
-        load_ub(C, ~0ull);
-        res_c = kkt_pass(gd);
-      } else {
-        // every row keeps its warm start (finite and within tolerance)
-        res_c = INFINITY;
-      }
+    form_g();
+    if (rmap != nullptr) {
+      used = valid && pass.used != nullptr ? pass.used[myrow] : 0;
+      break;
     }
-    res = res_w;
-    if (start != nullptr) {
-      const bool warm = ok && (res_w <= tol || res_w < res_c);
-      fell_back = valid && !warm;
-      const unsigned long long wm = __ballot(warm);
-      if (wm != 0ull) load_ub(start, wm);
-      res = warm ? res_w : res_c;
+    if (phase == 2) break;
+    const float r = kkt(cand && phase == 0 ? gw : gd);
+    if (!cand) {
+      res = r;
+      break;
     }
-  } else {
-    load_ub(U, ~0ull);
-    used = valid && pass.used != nullptr ? pass.used[myrow] : 0;
+    if (phase == 0) {
+      res_w = r;
+      res = r;
+      if (!__any(valid && !(ok && res_w <= tol))) break;
+      src0 = C;
+      continue;
+    }
+    // a finite warm start within tolerance is kept; otherwise the
+    // candidate with the smaller residual
+    const bool warm = ok && (res_w <= tol || res_w < r);
+    fell_back = valid && !warm;
+    res = warm ? res_w : r;
+    take = __ballot(warm);
+    if (take == 0ull) break;
+    src1 = start;
   }
   int here = 0;
   bool pend = false;
@@ -1192,12 +1265,12 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
     if (valid) pend = res > tol;
     const bool run = valid && pend && used < max_sweeps && here < pass.budget;
     if (!__any(run)) break;
-    sweep_pass(run);
+    sweep(run);
     if (run) {
       ++used;
       ++here;
     }
-    res = kkt_pass(gd);
+    res = kkt(gd);
   }
   const unsigned long long badm = __ballot(gd != gd);
   const f4 nanv = f4{__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
@@ -1205,11 +1278,8 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_tol_kernel(
   for (int b = 0; b < NBK; ++b)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int n = 16 * r + m, c = 16 * b + 4 * g;
-      if (n < nrows && c < k) {
-        const int64_t row = rmap != nullptr ? static_cast<int64_t>(rmap[n]) : row0 + n;
-        *reinterpret_cast<f4*>(U + row * k + c) = (badm >> n) & 1ull ? nanv : ub[b][r];
-      }
+      const int c = 16 * b + 4 * g;
+      if (roff[r] >= 0 && c < k) *reinterpret_cast<f4*>(U + roff[r] + c) = (badm >> (16 * r + m)) & 1ull ? nanv : ub[b][r];
     }
   const bool keep = valid && pend && used < max_sweeps && pass.wave_cnt != nullptr;
   if (valid) {
@@ -1360,9 +1430,10 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
     DSANLS_LAUNCHED("prox_cd_lds_kernel");
     return DSANLS_OK;
   }
-  // one pass of the to-tolerance solve: in the block form (coupling on the
-  // matrix cores) where the fixed sweeps take it and every row source is
-  // 16-byte aligned, else one dot product per coordinate
+  // one pass of the to-tolerance solve: in the block form carrying the
+  // gradient (coupling on the matrix cores) where the fixed sweeps take the
+  // block form and every row source is 16-byte aligned, else one dot
+  // product per coordinate
   bool block = false;
   if constexpr (KC == 96 || KC == 100) {
     const uintptr_t al = reinterpret_cast<uintptr_t>(U) | reinterpret_cast<uintptr_t>(C) |
@@ -1376,14 +1447,14 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
   auto tol_pass = [&](const TolPass& ps, const float* Cc) -> dsanls_status {
     if constexpr (KC == 96 || KC == 100) {
       if (block) {
-        constexpr int NM = MfmaCd<KC>::NWV;
+        constexpr int NG = 4;   // waves per workgroup of prox_cd_grad_tol_kernel
         if (qc)
-          prox_cd_mfma_tol_kernel<KC, true><<<static_cast<unsigned>(ceil_div(nw, NM)), 64 * NM, 0, s>>>(
+          prox_cd_grad_tol_kernel<KC, true><<<static_cast<unsigned>(ceil_div(nw, NG)), 64 * NG, 0, s>>>(
               p.gp, p.den, p.inv, Rq, Cc, start, U, rows, k, mu, tol, max_sweeps, upper, ps);
         else
-          prox_cd_mfma_tol_kernel<KC, false><<<static_cast<unsigned>(ceil_div(nw, NM)), 64 * NM, 0, s>>>(
+          prox_cd_grad_tol_kernel<KC, false><<<static_cast<unsigned>(ceil_div(nw, NG)), 64 * NG, 0, s>>>(
               p.gp, p.den, p.inv, Rq, Cc, start, U, rows, k, mu, tol, max_sweeps, upper, ps);
-        DSANLS_LAUNCHED("prox_cd_mfma_tol_kernel");
+        DSANLS_LAUNCHED("prox_cd_grad_tol_kernel");
         return DSANLS_OK;
       }
     }
@@ -1401,8 +1472,8 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
   // max_sweeps and lists nothing.  Each pass writes U, so a centre that
   // aliases U is copied first.
   if (block) {
-    // q = r + mu c once for all passes: the passes read one panel instead of
-    // two per sweep and per KKT test (4% on the warm-start workload)
+    // q = r + mu c once for all passes (each pass reads it when it forms
+    // the gradient)
     const int64_t n4 = rows * k / 4;
     const unsigned qg = static_cast<unsigned>(std::min<int64_t>(ceil_div(n4, 256), 4096));
     qsum_kernel<<<qg, 256, 0, s>>>(reinterpret_cast<const float4*>(R), reinterpret_cast<const float4*>(C), mu, n4,
