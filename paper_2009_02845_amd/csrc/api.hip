@@ -257,7 +257,7 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
   L.counters = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * 8));
   L.tol.counters = L.counters;
   if (c.solver == DSANLS_SOLVER_PROX_CD && c.sweeps == 0) {
-    const int64_t nw = (rowsmax + 63) / 64;
+    const int64_t nw = (rowsmax + 15) / 16;   // waves of 16 to 64 rows, 64 slots each
     L.tol.used = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * rowsmax));
     L.tol.flags = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * rowsmax));
     L.tol.wave_cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * nw));

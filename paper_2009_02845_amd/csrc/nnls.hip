@@ -993,41 +993,55 @@ __global__ __launch_bounds__(256) void qsum_kernel(const float4* __restrict__ R,
 // flop.  Each pass forms g afresh (the same products, from u and q), so the
 // rounding carried in g is that of at most one pass's sweeps.  Rows that are
 // done (or out of budget) enter the products with delta = 0 and keep their
-// values.  Registers: u and g of 64 rows in the operand layout (lane (m, g)
-// holds rows 16 r + m, coordinates 16 b + 4 g .. + 3), 2 KP floats a lane,
-// so one wave per SIMD; the block loop is unrolled so every index is
-// static.  With WITHC, q = r + mu c is read from R and C when g is formed;
-// without, R already holds q.  C (the cold start of the first pass) is read
-// before the wave writes its rows, so it may alias U.
-template <int KC, bool WITHC>
+// values (a step clamped to [u_j, u_j]).  A non-finite value anywhere in a
+// row's problem reaches its g, which every stopping test folds into the
+// row's guard.  Registers: u and g of the wave's 16 RQ rows in the operand
+// layout (lane (m, g) holds rows 16 r + m, r < RQ, coordinates 16 b + 4 g ..
+// + 3), 2 RQ KP / 4 floats a lane, one wave per SIMD; the block loop is
+// unrolled so every index is static.  With WITHC, q = r + mu c is read from
+// R and C when g is formed; without, R already holds q.  C (the cold start
+// of the first pass) is read before the wave writes its rows, so it may
+// alias U.
+template <int KC, bool WITHC, int RQ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void prox_cd_grad_tol_kernel(
     const float* __restrict__ gp, const float* __restrict__ den, const float* __restrict__ inv,
     const float* __restrict__ R, const float* C, const float* start, float* U, int64_t rows, int k,
     float mu, float tol, int max_sweeps, float upper, TolPass pass) {
   typedef float f4 __attribute__((ext_vector_type(4)));
-  constexpr int NBK = MfmaCd<KC>::NBK, KP = MfmaCd<KC>::KP, NWV = 4, QS = KP + 4;
+  constexpr int NBK = MfmaCd<KC>::NBK, KP = MfmaCd<KC>::KP, NWV = 4, QS = KP + 4, NR = 16 * RQ;
   // Q (row j: G_jl, G_jj + mu on the diagonal, zero outside KC x KC; rows
-  // padded to QS floats), 1 / Q_jj and its indicator (0 where Q_jj = 0 or
-  // past k: such a coordinate is set to 0), and one transpose tile per wave
+  // padded to QS floats), its diagonal blocks for the coordinate steps, and
+  // one transpose tile per wave
   __shared__ __attribute__((aligned(16))) float sq[KP * QS];
-  __shared__ __attribute__((aligned(16))) float sinv[KP];
-  __shared__ __attribute__((aligned(16))) float sone[KP];
-  __shared__ __attribute__((aligned(16))) float xs[NWV][64 * 16];
+  __shared__ __attribute__((aligned(16))) float sdb[NBK * 16 * 20];
+  __shared__ __attribute__((aligned(16))) float xs[NWV][NR * 16];
+  // a workgroup past the pass's rows leaves before staging Q
+  if (blockIdx.x * static_cast<int64_t>(NWV * NR) >= (pass.list_in != nullptr ? *pass.count_in : rows)) {
+    if (pass.wave_cnt != nullptr && threadIdx.x % 64 == 0) {
+      const int64_t w = blockIdx.x * static_cast<int64_t>(NWV) + threadIdx.x / 64;
+      if (w * NR < rows) pass.wave_cnt[w] = 0;
+    }
+    return;
+  }
   for (int i = threadIdx.x; i < KP * QS; i += 64 * NWV) {
     const int j = i / QS, l = i - j * QS;
     sq[i] = j < KC && l < KC ? (j == l ? den[j] : gp[j * KC + l]) : 0.f;
   }
-  for (int i = threadIdx.x; i < KP; i += 64 * NWV) {
-    const float v = i < KC ? inv[i] : 0.f;
-    sinv[i] = v;
-    sone[i] = v != 0.f ? 1.f : 0.f;
+  // the diagonal blocks of Q for the coordinate steps, row j = 16 b + jj at
+  // sdb + j * 20: Q_jl for l != j in the block, 1 / Q_jj (0: a zero Q_jj,
+  // or past k) on the diagonal
+  for (int i = threadIdx.x; i < NBK * 16 * 20; i += 64 * NWV) {
+    const int j = i / 20, l = 16 * (j / 16) + i % 20;
+    float v = 0.f;
+    if (i % 20 < 16 && j < KC && l < KC) v = j == l ? inv[j] : gp[j * KC + l];
+    sdb[i] = v;
   }
   __syncthreads();
   const int wib = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   const int64_t wave = blockIdx.x * static_cast<int64_t>(NWV) + wib;
-  if (wave * 64 >= rows) return;   // past the last wave (its per-wave slots do not exist)
+  if (wave * NR >= rows) return;   // past the last wave (its per-wave slots do not exist)
   const int lane = lane_id(), m = lane & 15, g = lane >> 4;
-  const int64_t row0 = wave * 64;
+  const int64_t row0 = wave * NR;
   const int32_t* rmap = nullptr;
   int nrows;
   if (pass.list_in != nullptr) {
@@ -1036,10 +1050,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       if (pass.wave_cnt != nullptr && lane == 0) pass.wave_cnt[wave] = 0;
       return;
     }
-    nrows = static_cast<int>(cnt - row0 < 64 ? cnt - row0 : 64);
+    nrows = static_cast<int>(cnt - row0 < NR ? cnt - row0 : NR);
     rmap = pass.list_in + row0;
   } else {
-    nrows = static_cast<int>(rows - row0 < 64 ? rows - row0 : 64);
+    nrows = static_cast<int>(rows - row0 < NR ? rows - row0 : NR);
   }
   const bool valid = lane < nrows;
   const int64_t myrow = valid ? (rmap != nullptr ? static_cast<int64_t>(rmap[lane]) : row0 + lane) : 0;
@@ -1048,18 +1062,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 
   // offset of row 16 r + m of the wave in the row-major matrices (-1: past
   // the wave's rows)
-  int64_t roff[4];
+  int64_t roff[RQ];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
+  for (int r = 0; r < RQ; ++r) {
     const int n = 16 * r + m;
     roff[r] = n < nrows ? (rmap != nullptr ? static_cast<int64_t>(rmap[n]) : row0 + n) * k : -1;
   }
-  f4 ub[NBK][4], gb[NBK][4];
+  f4 ub[NBK][RQ], gb[NBK][RQ];
   // every row into the operand layout: from P1 where the row's bit is set in
   // take, else from P0 (one load per value either way)
   auto load_ub = [&](const float* P0, const float* P1, unsigned long long take) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < RQ; ++r) {
       const float* P = (take >> (16 * r + m)) & 1ull ? P1 : P0;
 #pragma unroll
       for (int b = 0; b < NBK; ++b) {
@@ -1070,22 +1084,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   };
   // per-row sums (lane per row) of per-(lane, quarter) partial sums: the
   // four lanes of a row quarter add up, lane 16 g + m keeps quarter g
-  auto row_sum = [&](float (&s)[4]) -> float {
+  auto row_sum = [&](float (&s)[RQ]) -> float {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < RQ; ++r) {
       s[r] += __shfl_xor(s[r], 16, 64);
       s[r] += __shfl_xor(s[r], 32, 64);
     }
-    return g == 0 ? s[0] : g == 1 ? s[1] : g == 2 ? s[2] : s[3];
+    float v = 0.f;
+#pragma unroll
+    for (int r = 0; r < RQ; ++r)
+      if (g == r) v = s[r];
+    return v;
   };
   // g = u Q - q for the wave's rows, and ||q||^2 of each row (lane per row)
   float q2 = 0.f;
   auto form_g = [&]() {
-    float qs[4] = {0.f, 0.f, 0.f, 0.f};
+    float qs[RQ];
+#pragma unroll
+    for (int r = 0; r < RQ; ++r) qs[r] = 0.f;
 #pragma unroll
     for (int bb = 0; bb < NBK; ++bb) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < RQ; ++r) {
         const int c = 16 * bb + 4 * g;
         f4 q = f4{0.f, 0.f, 0.f, 0.f};
         if (roff[r] >= 0 && c < k) {
@@ -1101,7 +1121,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
+          for (int r = 0; r < RQ; ++r)
             gb[bb][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], ub[b][r][e], gb[bb][r], 0, 0, 0);
       }
       // one block of g at a time (the scheduler would otherwise hoist every
@@ -1113,11 +1133,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   // relative projected-gradient norm of each row (lane per row) from the
   // carried g; gk takes the non-finite guard of the row's g
   auto kkt = [&](float& gk) -> float {
-    float s[4] = {0.f, 0.f, 0.f, 0.f}, z[4] = {0.f, 0.f, 0.f, 0.f};
+    float s[RQ], z[RQ];
+#pragma unroll
+    for (int r = 0; r < RQ; ++r) s[r] = z[r] = 0.f;
 #pragma unroll
     for (int bb = 0; bb < NBK; ++bb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < RQ; ++r)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           // coordinates past k hold g = 0 exactly
@@ -1133,54 +1155,66 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   auto sweep = [&](bool run) {
 #pragma unroll
     for (int b = 0; b < NBK; ++b) {
+      // (lanes past the wave's NR rows read row lane % NR and write nothing)
       f4 ur[4], gr[4];
+      const int me = lane & (NR - 1);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) *reinterpret_cast<f4*>(X + cd_chunk(16 * r + m, g)) = ub[b][r];
+      for (int r = 0; r < RQ; ++r) *reinterpret_cast<f4*>(X + cd_chunk(16 * r + m, g)) = ub[b][r];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) ur[c] = *reinterpret_cast<const f4*>(X + cd_chunk(lane, c));
+      for (int c = 0; c < 4; ++c) ur[c] = *reinterpret_cast<const f4*>(X + cd_chunk(me, c));
 #pragma unroll
-      for (int r = 0; r < 4; ++r) *reinterpret_cast<f4*>(X + cd_chunk(16 * r + m, g)) = gb[b][r];
+      for (int r = 0; r < RQ; ++r) *reinterpret_cast<f4*>(X + cd_chunk(16 * r + m, g)) = gb[b][r];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) gr[c] = *reinterpret_cast<const f4*>(X + cd_chunk(lane, c));
+      for (int c = 0; c < 4; ++c) gr[c] = *reinterpret_cast<const f4*>(X + cd_chunk(me, c));
       // the block's coordinates in order (the last block of a rank that is
       // not a multiple of 16 has only KC % 16 of them)
       constexpr int NL = KC % 16 != 0 ? KC % 16 : 16;
       const int nj = b == NBK - 1 ? NL : 16;
-      const float* qb = sq + (16 * b) * QS + 16 * b;
-      // row jj of the block's part of Q, one row ahead of its use
-      f4 qr[4], qn[4];
+      // row jj of the block's part of Q (1 / Q_jj on the diagonal), one row
+      // ahead of its use, alternating between two buffers
+      const float* qb = sdb + (16 * b) * 20;
+      f4 qv[2][4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) qr[c] = *reinterpret_cast<const f4*>(qb + 4 * c);
+      for (int c = 0; c < 4; ++c) qv[0][c] = *reinterpret_cast<const f4*>(qb + 4 * c);
 #pragma unroll
       for (int jj = 0; jj < 16; ++jj) {
         if (jj < nj) {
           if (jj + 1 < nj) {
 #pragma unroll
-            for (int c = (jj + 1) / 4; c < 4; ++c) qn[c] = *reinterpret_cast<const f4*>(qb + (jj + 1) * QS + 4 * c);
+            for (int c = (jj + 1) / 4; c < 4; ++c)
+              qv[(jj + 1) & 1][c] = *reinterpret_cast<const f4*>(qb + (jj + 1) * 20 + 4 * c);
           }
+          const f4(&q)[4] = qv[jj & 1];
           const float uj = ur[jj / 4][jj % 4];
-          const float x = __builtin_fmaf(-gr[jj / 4][jj % 4], sinv[16 * b + jj], uj * sone[16 * b + jj]);
-          guard(gd, x);
-          const float v = fminf(fmaxf(x, 0.f), ubnd);
-          const float dl = run ? v - uj : 0.f;
-          if (run) ur[jj / 4][jj % 4] = v;
+          const float iv = q[jj / 4][jj % 4];
+          // off the chain: a zero 1 / Q_jj sets the coordinate to 0, and a
+          // row that does not run keeps u_j (clamped to [u_j, u_j])
+          const float u0 = iv != 0.f ? uj : 0.f;
+          const float lo = run ? 0.f : uj, hi = run ? ubnd : uj;
+          // (a non-finite step comes from a non-finite g, caught by the
+          // stopping test's guard after the sweep)
+          const float x = __builtin_fmaf(-gr[jj / 4][jj % 4], iv, u0);
+          const float v = __builtin_amdgcn_fmed3f(x, lo, hi);
+          const float dl = v - uj;
+          ur[jj / 4][jj % 4] = v;
           // the later coordinates of the block see the step
 #pragma unroll
           for (int l = jj + 1; l < 16; ++l)
-            if (l < nj) gr[l / 4][l % 4] = __builtin_fmaf(dl, qr[l / 4][l % 4], gr[l / 4][l % 4]);
-          if (jj + 1 < nj) {
-#pragma unroll
-            for (int c = (jj + 1) / 4; c < 4; ++c) qr[c] = qn[c];
-          }
+            if (l < nj) gr[l / 4][l % 4] = __builtin_fmaf(dl, q[l / 4][l % 4], gr[l / 4][l % 4]);
+          // one coordinate at a time (hoisting the later rows' reads would
+          // outgrow the registers)
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
       __builtin_amdgcn_sched_barrier(0);
       // the new values back to the operand layout; the step of the block
+      if (lane < NR) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) *reinterpret_cast<f4*>(X + cd_chunk(lane, c)) = ur[c];
-      f4 dlt[4];
+        for (int c = 0; c < 4; ++c) *reinterpret_cast<f4*>(X + cd_chunk(lane, c)) = ur[c];
+      }
+      f4 dlt[RQ];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < RQ; ++r) {
         const f4 nb = *reinterpret_cast<const f4*>(X + cd_chunk(16 * r + m, g));
         dlt[r] = nb - ub[b][r];
         ub[b][r] = nb;
@@ -1193,7 +1227,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
+          for (int r = 0; r < RQ; ++r)
             gb[bb][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], dlt[r][e], gb[bb][r], 0, 0, 0);
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -1217,9 +1251,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     load_ub(src0, src1, take);
     if (cand && phase == 0) {
       // a row is finite when none of its four lanes' values is not
-      unsigned long long bad[4];
+      unsigned long long bad[4] = {0ull, 0ull, 0ull, 0ull};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < RQ; ++r) {
         bool fin = true;
 #pragma unroll
         for (int b = 0; b < NBK; ++b)
@@ -1277,7 +1311,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
   for (int b = 0; b < NBK; ++b)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < RQ; ++r) {
       const int c = 16 * b + 4 * g;
       if (roff[r] >= 0 && c < k) *reinterpret_cast<f4*>(U + roff[r] + c) = (badm >> (16 * r + m)) & 1ull ? nanv : ub[b][r];
     }
@@ -1434,6 +1468,11 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
   // gradient (coupling on the matrix cores) where the fixed sweeps take the
   // block form and every row source is 16-byte aligned, else one dot
   // product per coordinate
+  // row quarters (16 rows) per wave of prox_cd_grad_tol_kernel (waves of
+  // 16 rows in the passes after the first cut a wave's latency per sweep
+  // but cost throughput where many rows remain: slower overall on the
+  // sparse text workload)
+  constexpr int kRQ = 4;
   bool block = false;
   if constexpr (KC == 96 || KC == 100) {
     const uintptr_t al = reinterpret_cast<uintptr_t>(U) | reinterpret_cast<uintptr_t>(C) |
@@ -1448,11 +1487,12 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
     if constexpr (KC == 96 || KC == 100) {
       if (block) {
         constexpr int NG = 4;   // waves per workgroup of prox_cd_grad_tol_kernel
+        const unsigned gg = static_cast<unsigned>(ceil_div(ceil_div(rows, 16 * kRQ), NG));
         if (qc)
-          prox_cd_grad_tol_kernel<KC, true><<<static_cast<unsigned>(ceil_div(nw, NG)), 64 * NG, 0, s>>>(
+          prox_cd_grad_tol_kernel<KC, true, kRQ><<<gg, 64 * NG, 0, s>>>(
               p.gp, p.den, p.inv, Rq, Cc, start, U, rows, k, mu, tol, max_sweeps, upper, ps);
         else
-          prox_cd_grad_tol_kernel<KC, false><<<static_cast<unsigned>(ceil_div(nw, NG)), 64 * NG, 0, s>>>(
+          prox_cd_grad_tol_kernel<KC, false, kRQ><<<gg, 64 * NG, 0, s>>>(
               p.gp, p.den, p.inv, Rq, Cc, start, U, rows, k, mu, tol, max_sweeps, upper, ps);
         DSANLS_LAUNCHED("prox_cd_grad_tol_kernel");
         return DSANLS_OK;
@@ -1485,18 +1525,22 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
     DSANLS_HIP(hipMemcpyAsync(tw->centre, C, sizeof(float) * rows * k, hipMemcpyDeviceToDevice, s));
     C = tw->centre;
   }
+  // waves of the passes (16 kRQ rows in the block form; every wave has 64
+  // slots in wave_rows)
+  auto waves = [&](int) -> int64_t { return block ? ceil_div(rows, 16 * kRQ) : nw; };
   int budget = 16, spent = 0;
   for (int pass_no = 0;; ++pass_no) {
     const bool last = spent + budget >= max_sweeps;
-    TolPass ps{pass_no == 0 ? nullptr : tw->list[pass_no & 1], pass_no == 0 ? nullptr : tw->wave_off + nw,
+    const int64_t nwp = waves(pass_no);
+    TolPass ps{pass_no == 0 ? nullptr : tw->list[pass_no & 1], pass_no == 0 ? nullptr : tw->wave_off + waves(pass_no - 1),
                last ? max_sweeps : budget, tw->used, tw->flags, last ? nullptr : tw->wave_cnt, tw->wave_rows};
     dsanls_status st = tol_pass(ps, C);
     if (st != DSANLS_OK) return st;
     if (last) break;
-    st = launch_exclusive_scan(tw->wave_cnt, tw->wave_off, nw, tw->scan_ws, s);
+    st = launch_exclusive_scan(tw->wave_cnt, tw->wave_off, nwp, tw->scan_ws, s);
     if (st != DSANLS_OK) return st;
-    tol_compact_kernel<<<static_cast<unsigned>(ceil_div(nw * 64, 256)), 256, 0, s>>>(
-        tw->wave_cnt, tw->wave_off, tw->wave_rows, nw, tw->list[(pass_no + 1) & 1]);
+    tol_compact_kernel<<<static_cast<unsigned>(ceil_div(nwp * 64, 256)), 256, 0, s>>>(
+        tw->wave_cnt, tw->wave_off, tw->wave_rows, nwp, tw->list[(pass_no + 1) & 1]);
     DSANLS_LAUNCHED("tol_compact_kernel");
     spent += budget;
     if (pass_no > 0) budget *= 2;
