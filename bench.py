@@ -89,6 +89,12 @@ WORKLOADS.update(TO_EPS)
 
 def describe(name, w, K=None):
     iters = K if K is not None else w["iters"]
+    if "alpha" in w and w["kind"] in ("to_eps", "warm", "sparse", "dense"):
+        return _describe(name, w, iters) + f", mu_t = {w['alpha']:g} + {w['beta']:g} t"
+    return _describe(name, w, iters)
+
+
+def _describe(name, w, iters):
     if w["kind"] == "ksweep":
         return (f"CSR {w['m']}x{w['n']}, {w['nnz']:.0e} nnz text-shaped, subsampling d=d'={w['d']}, prox-CD 1 sweep, "
                 f"k in {list(w['ks'])}, {iters} iterations each")
@@ -686,6 +692,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--seeds", type=int, default=None,
                     help="data seeds of the to-eps* workload (default: the workload's three)")
+    ap.add_argument("--alpha", type=float, default=None,
+                    help="override the workload's mu_t = alpha + beta t (Sec. 5.2; default: its frozen grid winner)")
+    ap.add_argument("--beta", type=float, default=None)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES bytes device-to-device three times (calibrates the HBM "
                          "traffic counters against a transfer of known size) and exit")
@@ -709,7 +718,10 @@ def main():
         print(json.dumps({"copy_probe_bytes": src.numel() * 4, "copies": 3}), flush=True)
         return
     B.load()
-    w = WORKLOADS[args.workload]
+    w = dict(WORKLOADS[args.workload])
+    for key in ("alpha", "beta"):
+        if getattr(args, key) is not None:
+            w[key] = getattr(args, key)
     K = args.steps if args.steps is not None else w["iters"]
     W = args.warmup
     if w["kind"] == "ksweep":
