@@ -247,6 +247,22 @@ def sparse_roofline(w, M, tm, launches, workload):
     moved = (24.0 * (e_u + e_v) + (4.0 * k + 8.0) * (m + n)) / 2
     pach = moved / prod_avg / 1e9
     kern = "prox_cd_mfma_kernel" if k % 4 == 0 and 64 < k <= 100 else "prox_cd_lds_kernel"
+    if w.get("sketch") == "count":
+        # the count sketch keeps every nonzero: R = (X S) B^T streams all nnz
+        # of X, each adding s_j M_ij B^T[h_j, :] (k FMAs, the row of B^T
+        # from L2) - 2 nnz k flop per side on the VALU, the dominant phase;
+        # HBM moves the CSR (8 B per nnz, 8 B per row) and R (4 k B per row)
+        flops_p = 2.0 * nnz * k
+        hbm_p = 8.0 * nnz + (8.0 + 4.0 * k) * (m + n) / 2
+        tf = flops_p / prod_avg / 1e12
+        return {"kernel": "count-sketch product R = (X S) B^T from the nnz stream (csr_rhs_seg_kernel, hashed)",
+                "bound": "alu", "achieved": tf, "peak": PEAK["fp32_valu_tflops"], "unit": "TFLOP/s",
+                "frac": tf / PEAK["fp32_valu_tflops"], "traffic": None, "flops_per_launch": flops_p,
+                "hbm_bytes_per_launch": hbm_p, "hbm_gbs": hbm_p / prod_avg / 1e9,
+                "avg_launch_ms": prod_avg * 1e3, "sides_timed": half * 2,
+                "nnls": {"kernel": f"prox-CD sweep ({kern})", "bound": "hbm", "achieved": ach,
+                         "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": ach / PEAK["hbm_gbs"],
+                         "avg_launch_ms": nnls_avg * 1e3}}
     return {"kernel": f"prox-CD sweep ({kern})", "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"],
             "unit": "GB/s", "frac": ach / PEAK["hbm_gbs"], "traffic": traffic_bytes(workload),
             "bytes_per_launch": nbytes, "flops_per_launch": flops, "tflops": tflops,

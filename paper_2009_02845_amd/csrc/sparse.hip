@@ -106,13 +106,39 @@ __global__ __launch_bounds__(256) void csr_rhs_seg_kernel(const int64_t* __restr
     }
     unsigned long long mask = __ballot(col >= 0);
     while (mask != 0ull) {
-      const int b = __ffsll(mask) - 1;
-      mask &= mask - 1ull;
-      const int32_t c = __shfl(col, b, 64);
-      const float x = __shfl(v, b, 64);
-      const float* w = W + (int64_t)c * ldw;
-      if (lane < k) a0 += x * w[lane];
-      if (lane + 64 < k) a1 += x * w[lane + 64];
+      // up to 8 hits at a time (wave-uniform: read from their lanes into
+      // scalar registers), their rows of W loaded together so that the
+      // loads overlap; the FMAs follow in the hits' order
+      constexpr int U = 8;
+      int32_t cs[U];
+      float xs[U];
+      int cnt = 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        cs[u] = 0;
+        xs[u] = 0.f;
+        if (mask != 0ull) {
+          const int b = __ffsll(mask) - 1;
+          mask &= mask - 1ull;
+          cs[u] = __builtin_amdgcn_readlane(col, b);
+          xs[u] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), b));
+          cnt = u + 1;
+        }
+      }
+      float w0[U], w1[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const float* w = W + (int64_t)cs[u] * ldw;
+        w0[u] = u < cnt && lane < k ? w[lane] : 0.f;
+        w1[u] = u < cnt && lane + 64 < k ? w[lane + 64] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (u < cnt) {
+          a0 += xs[u] * w0[u];
+          a1 += xs[u] * w1[u];
+        }
+      }
     }
   }
   const int32_t part = seg_part[sg];
