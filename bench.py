@@ -620,7 +620,14 @@ def run_ksweep(args, w, torch, B, K, W):
         solver.close()
         del solver, U, V, U0d, V0d
     main_k = [r for r in res if r["k"] == 100] or res
-    return {"value": main_k[0]["iterations_per_s"], "ms_per_step": main_k[0]["ms_per_step"], "k_sweep": res}
+    r0 = main_k[0]
+    # the line's roofline: the NNLS sweep at the headline rank (HBM-bound at
+    # k = 100, k / 6 flop per byte); every rank's figures are in k_sweep
+    roof = {"kernel": f"prox-CD sweep ({r0['nnls_kernel']}, k = {r0['k']})", "bound": "hbm",
+            "achieved": r0["nnls_gbs"], "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+            "frac": r0["nnls_gbs"] / PEAK["hbm_gbs"], "traffic": None,
+            "avg_launch_ms": r0["nnls_avg_launch_ms"]}
+    return {"value": r0["iterations_per_s"], "ms_per_step": r0["ms_per_step"], "k_sweep": res, "roofline": roof}
 
 
 def run_pgd_vs_cd(args, w, torch, B, W):
