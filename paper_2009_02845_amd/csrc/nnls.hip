@@ -562,8 +562,21 @@ __global__ __launch_bounds__(64 * NWV) void prox_cd_lds_kernel(const float* __re
   constexpr int kWords = Panel<SW>::WORDS > 2 * 64 * SW ? Panel<SW>::WORDS : 2 * 64 * SW;
   __shared__ __attribute__((aligned(16))) float sg[KC * KC];
   __shared__ float lds[NWV][kWords];
-  for (int i = threadIdx.x * 4; i < KC * KC; i += 64 * NWV * 4)
-    *reinterpret_cast<float4*>(sg + i) = *reinterpret_cast<const float4*>(gp + i);
+  {
+    // every chunk of a thread loaded before the first is stored
+    constexpr int N4 = KC * KC / 4, P = (N4 + 64 * NWV - 1) / (64 * NWV);
+    float4 t[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int i = threadIdx.x + 64 * NWV * p;
+      if (i < N4) t[p] = reinterpret_cast<const float4*>(gp)[i];
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int i = threadIdx.x + 64 * NWV * p;
+      if (i < N4) reinterpret_cast<float4*>(sg)[i] = t[p];
+    }
+  }
   __syncthreads();
   // wave-uniform (scalar) wave index: the row addressing lives in SGPRs
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -706,9 +719,24 @@ __global__ __launch_bounds__(64 * MfmaCd<KC>::NWV) void prox_cd_mfma_kernel(
   __shared__ float sinv[KP];
   __shared__ QPanel<16> qps[NWV];
   __shared__ __attribute__((aligned(16))) float xs[NWV][64 * 16];
-  for (int i = threadIdx.x; i < NBK * 256; i += 64 * NWV) {
-    const int bk = i >> 8, j = 16 * bk + ((i >> 4) & 15), l = 16 * bk + (i & 15);
-    sd[i] = j < KC && l < KC ? gp[j * KC + l] : 0.f;
+  {
+    // 16-byte chunks (G rows are 16-byte aligned, KC % 4 == 0), every
+    // chunk of a thread loaded before the first is stored: one round of L2
+    // latency per workgroup instead of one per element
+    constexpr int N4 = NBK * 64, P = (N4 + 64 * NWV - 1) / (64 * NWV);
+    f4 t[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int i = 4 * (threadIdx.x + 64 * NWV * p);
+      const int bk = i >> 8, j = 16 * bk + ((i >> 4) & 15), l = 16 * bk + (i & 15);
+      t[p] = i < 4 * N4 && j < KC && l < KC ? *reinterpret_cast<const f4*>(gp + j * KC + l)
+                                             : f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int i = 4 * (threadIdx.x + 64 * NWV * p);
+      if (i < 4 * N4) *reinterpret_cast<f4*>(sd + i) = t[p];
+    }
   }
   for (int i = threadIdx.x; i < KP; i += 64 * NWV) sinv[i] = i < KC ? inv[i] : 0.f;
   __syncthreads();
@@ -861,8 +889,21 @@ __global__ __launch_bounds__(64 * NWV) void prox_cd_tol_kernel(const float* __re
   constexpr int kWords = Panel<SW>::WORDS > 2 * 64 * SW ? Panel<SW>::WORDS : 2 * 64 * SW;
   __shared__ __attribute__((aligned(16))) float sg[KC * KC];
   __shared__ float lds[NWV][kWords];
-  for (int i = threadIdx.x * 4; i < KC * KC; i += 64 * NWV * 4)
-    *reinterpret_cast<float4*>(sg + i) = *reinterpret_cast<const float4*>(gp + i);
+  {
+    // every chunk of a thread loaded before the first is stored
+    constexpr int N4 = KC * KC / 4, P = (N4 + 64 * NWV - 1) / (64 * NWV);
+    float4 t[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int i = threadIdx.x + 64 * NWV * p;
+      if (i < N4) t[p] = reinterpret_cast<const float4*>(gp)[i];
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int i = threadIdx.x + 64 * NWV * p;
+      if (i < N4) reinterpret_cast<float4*>(sg)[i] = t[p];
+    }
+  }
   __syncthreads();
   const int wib = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   const int64_t wave = blockIdx.x * static_cast<int64_t>(NWV) + wib;
@@ -1023,18 +1064,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     }
     return;
   }
-  for (int i = threadIdx.x; i < KP * QS; i += 64 * NWV) {
-    const int j = i / QS, l = i - j * QS;
-    sq[i] = j < KC && l < KC ? (j == l ? den[j] : gp[j * KC + l]) : 0.f;
-  }
-  // the diagonal blocks of Q for the coordinate steps, row j = 16 b + jj at
-  // sdb + j * 20: Q_jl for l != j in the block, 1 / Q_jj (0: a zero Q_jj,
-  // or past k) on the diagonal
-  for (int i = threadIdx.x; i < NBK * 16 * 20; i += 64 * NWV) {
-    const int j = i / 20, l = 16 * (j / 16) + i % 20;
-    float v = 0.f;
-    if (i % 20 < 16 && j < KC && l < KC) v = j == l ? inv[j] : gp[j * KC + l];
-    sdb[i] = v;
+  {
+    // Both copies in 16-byte chunks, every chunk of a thread loaded before
+    // the first is stored (one round of L2 latency per workgroup instead of
+    // one per element).  Rows of the prepared Gram are 16-byte aligned
+    // (KC % 4 == 0); a chunk lies wholly inside or outside KC.  sdb: row j =
+    // 16 b + jj at sdb + 20 j: Q_jl for l != j in the block, 1 / Q_jj (0: a
+    // zero Q_jj, or past k) on the diagonal.
+    constexpr int C1 = QS / 4, N1 = KP * C1, C2 = 5, N2 = NBK * 16 * C2;
+    constexpr int P1 = (N1 + 64 * NWV - 1) / (64 * NWV), P2 = (N2 + 64 * NWV - 1) / (64 * NWV);
+    f4 t1[P1], t2[P2];
+#pragma unroll
+    for (int p = 0; p < P1; ++p) {
+      const int i = threadIdx.x + 64 * NWV * p, j = i / C1, l = 4 * (i - j * C1);
+      f4 v = f4{0.f, 0.f, 0.f, 0.f};
+      if (i < N1 && j < KC && l < KC) {
+        v = *reinterpret_cast<const f4*>(gp + j * KC + l);
+        if (j >= l && j < l + 4) v[j - l] = den[j];
+      }
+      t1[p] = v;
+    }
+#pragma unroll
+    for (int p = 0; p < P2; ++p) {
+      const int i = threadIdx.x + 64 * NWV * p, j = i / C2, c = i - j * C2, l = 16 * (j / 16) + 4 * c;
+      f4 v = f4{0.f, 0.f, 0.f, 0.f};
+      if (i < N2 && c < 4 && j < KC && l < KC) {
+        v = *reinterpret_cast<const f4*>(gp + j * KC + l);
+        if (j >= l && j < l + 4) v[j - l] = inv[j];
+      }
+      t2[p] = v;
+    }
+#pragma unroll
+    for (int p = 0; p < P1; ++p) {
+      const int i = threadIdx.x + 64 * NWV * p;
+      if (i < N1) *reinterpret_cast<f4*>(sq + 4 * i) = t1[p];
+    }
+#pragma unroll
+    for (int p = 0; p < P2; ++p) {
+      const int i = threadIdx.x + 64 * NWV * p;
+      if (i < N2) *reinterpret_cast<f4*>(sdb + 4 * i) = t2[p];
+    }
   }
   __syncthreads();
   const int wib = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
