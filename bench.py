@@ -198,9 +198,9 @@ TRAFFIC = {
     "dense-20000x10000": {"files": ["gemm.hip"],
                           "sha256": "528bbd6a909efc6db290b4aa3aadad6fff075009e7c6bd17c23241f09d68dd09",
                           "fetch_kib": 2419643.13, "write_kib": 120000.0},
-    "sparse-500000x200000": {"files": ["nnls.hip", "common.hpp"],
-                             "sha256": "2635fe2dd953aac9dd633be9b88361725cdb69ed43d1a98dabd3a0d3a4eb3e53",
-                             "fetch_kib": 182695.75, "write_kib": 144235.05},
+    "sparse-500000x200000": {"files": ["nnls.hip"],
+                             "sha256": "1f8a80c0735981e2892fab1e06855151c788483af348b4f0e7be43bf25eddbdc",
+                             "fetch_kib": 192424.13, "write_kib": 147452.68},
     "dense-50000x20000-bf16": {"files": ["gemm.hip"],
                                "sha256": "528bbd6a909efc6db290b4aa3aadad6fff075009e7c6bd17c23241f09d68dd09",
                                "fetch_kib": 19776476.63, "write_kib": 1120000.0},
