@@ -59,7 +59,7 @@ WORKLOADS = {
     "sparse-500000x200000-warm": dict(kind="warm", m=500000, n=200000, k=100, d=2000, iters=10,
                                       solver="prox_cd", nnz=100_000_000, precision="fp32", hidden=256,
                                       pairs=1_000_000, runs=5, run_iters=20, label_tol=1e-6, tol=1e-4,
-                                      max_sweeps=200, epochs=6, batch=4096, lr=1e-4, alpha=0.1, beta=0.1),
+                                      max_sweeps=200, epochs=20, batch=4096, lr=1e-4, alpha=0.1, beta=0.1),
 }
 # the further sketch kinds of Sec. 3.4 on the same data shapes
 WORKLOADS["dense-20000x10000-count"] = dict(WORKLOADS["dense-20000x10000"], sketch="count")
