@@ -197,7 +197,7 @@ def test_cold_to_tolerance_update_matches_oracle(env):
 
 @pytest.mark.parametrize("k", [10, 33, 100])
 def test_to_tolerance_passes_match_oracle(env, k):
-    # to tolerance through all the passes (budgets 16, 16, 32, 64, then to
+    # to tolerance through all the passes (budgets 8, 8, 16, 32, 64, then to
     # the cap, pending rows compacted between passes); k = 100 > d keeps G
     # singular (mu = 1 + t makes Q definite), so many rows need far more
     # than 32 sweeps.  Against the oracle with the same tolerance and sweep
