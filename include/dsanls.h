@@ -46,7 +46,7 @@ typedef enum {
   DSANLS_E_HIP = 4,          /* a HIP runtime call failed                      */
   DSANLS_E_NONFINITE = 5,    /* NaN/Inf found in M, U or V                     */
   DSANLS_E_STATE = 6,        /* call out of order (e.g. before init)           */
-  DSANLS_E_UNSUPPORTED = 7,  /* valid request this build does not implement    */
+  DSANLS_E_UNSUPPORTED = 7,  /* valid request the library does not implement   */
   DSANLS_E_INTERNAL = 8      /* a device-side step failed (reported later, see
                                 dsanls_objective)                              */
 } dsanls_status;
