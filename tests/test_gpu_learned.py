@@ -83,7 +83,7 @@ def test_adam_steps_match_oracle(env):
         assert _rel(got[name], p[name]) < 1e-4, name
 
 
-def _sparse_ctx(env, m, n, k, d, seed, warm_hidden=0, tol=1e-5):
+def _sparse_ctx(env, m, n, k, d, seed, warm_hidden=0, tol=1e-5, max_sweeps=400):
     torch, Bd = env
     g = np.random.default_rng(seed)
     Ms = sp.random(m, n, density=0.02, format="csr", random_state=seed, dtype=np.float64)
@@ -98,9 +98,38 @@ def _sparse_ctx(env, m, n, k, d, seed, warm_hidden=0, tol=1e-5):
             t(Mt.indptr, np.int64), t(Mt.indices, np.int32), t(Mt.data, np.float32)]
     U, V = torch.from_numpy(U0).cuda(), torch.from_numpy(V0).cuda()
     cfg = Bd.make_config(m, n, k, d, d, sketch="subsample", solver="prox_cd", sweeps=0, tol=tol,
-                         max_sweeps=400, alpha=1.0, beta=1.0, seed=7, warm_hidden=warm_hidden)
+                         max_sweeps=max_sweeps, alpha=1.0, beta=1.0, seed=7, warm_hidden=warm_hidden)
     s = Bd.Solver(cfg, Bd.csr_matrix(*arrs), U, V, tensors=arrs)
     return s, Ms.astype(np.float64), U, V, U0, V0
+
+
+@pytest.mark.parametrize("cap", [1, 8, 9, 17, 70])
+def test_to_tolerance_sweep_cap_across_passes(env, cap):
+    # a tolerance no row meets: every row runs exactly max_sweeps sweeps,
+    # however the cap falls across the pass budgets (8, 8, 16, 32, ...:
+    # inside the first pass, at its end, one into the second, inside the
+    # third, inside the fifth), and the update equals the oracle's fixed
+    # number of sweeps from the same start and centre; k = 100 takes the
+    # block form carrying the gradient
+    torch, Bd = env
+    m, n, k, d = 700, 500, 100, 80
+    s, M64, U, V, U0, V0 = _sparse_ctx(env, m, n, k, d, 13, tol=1e-30, max_sweeps=cap)
+    s.update_U(0)
+    st = s.stats()
+    assert st["sweeps_total"] == cap * m and st["rows_unconverged"] == m
+    Ug = U.cpu().numpy().astype(np.float64)
+
+    def fixed(sweeps):
+        c = O.Config(k=k, d=d, d_prime=d, sketch=O.SKETCH_SUBSAMPLE, solver=O.SOLVER_PROX_CD, sweeps=sweeps, seed=7)
+        return O.update_U(M64, U0.astype(np.float64), V0.astype(np.float64), 0, c)
+    # d < k: G is singular and Q = G + I has a condition number near 1e4, so
+    # FP32 rounding of the carried gradient moves u by about eps32 * 1e4
+    # over the sweeps; one sweep more or fewer moves it far more
+    e = _rel(Ug, fixed(cap))
+    assert e < 2e-3
+    assert e < 0.2 * _rel(Ug, fixed(cap + 1))
+    if cap > 1:
+        assert e < 0.2 * _rel(Ug, fixed(cap - 1))
 
 
 def test_sketched_rows_match_oracle(env):
