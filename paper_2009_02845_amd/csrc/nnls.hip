@@ -1044,12 +1044,12 @@ __global__ __launch_bounds__(256) void qsum_kernel(const float4* __restrict__ R,
 // of the first pass) is read before the wave writes its rows, so it may
 // alias U.
 template <int KC, bool WITHC, int RQ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void prox_cd_grad_tol_kernel(
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) void prox_cd_grad_tol_kernel(
     const float* __restrict__ gp, const float* __restrict__ den, const float* __restrict__ inv,
     const float* __restrict__ R, const float* C, const float* start, float* U, int64_t rows, int k,
     float mu, float tol, int max_sweeps, float upper, TolPass pass) {
   typedef float f4 __attribute__((ext_vector_type(4)));
-  constexpr int NBK = MfmaCd<KC>::NBK, KP = MfmaCd<KC>::KP, NWV = 4, QS = KP + 4, NR = 16 * RQ;
+  constexpr int NBK = MfmaCd<KC>::NBK, KP = MfmaCd<KC>::KP, NWV = 2, QS = KP + 4, NR = 16 * RQ;
   // Q (row j: G_jl, G_jj + mu on the diagonal, zero outside KC x KC; rows
   // padded to QS floats), its diagonal blocks for the coordinate steps, and
   // one transpose tile per wave
@@ -1555,7 +1555,11 @@ dsanls_status run_kc(bool pgd, const float* G, const float* R, const float* C, f
   auto tol_pass = [&](const TolPass& ps, const float* Cc) -> dsanls_status {
     if constexpr (KC == 96 || KC == 100) {
       if (block) {
-        constexpr int NG = 4;   // waves per workgroup of prox_cd_grad_tol_kernel
+        // waves per workgroup of prox_cd_grad_tol_kernel: two (a workgroup
+        // holds its LDS until its last wave ends, so with one wave per SIMD a
+        // slow wave keeps fewer SIMDs idle than with four: 75.3 vs 71.8 it/s
+        // on the sparse warm-start workload, cold)
+        constexpr int NG = 2;
         const unsigned gg = static_cast<unsigned>(ceil_div(ceil_div(rows, 16 * kRQ), NG));
         if (qc)
           prox_cd_grad_tol_kernel<KC, true, kRQ><<<gg, 64 * NG, 0, s>>>(
