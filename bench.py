@@ -199,8 +199,8 @@ TRAFFIC = {
                           "sha256": "528bbd6a909efc6db290b4aa3aadad6fff075009e7c6bd17c23241f09d68dd09",
                           "fetch_kib": 2419643.13, "write_kib": 120000.0},
     "sparse-500000x200000": {"files": ["nnls.hip"],
-                             "sha256": "1f8a80c0735981e2892fab1e06855151c788483af348b4f0e7be43bf25eddbdc",
-                             "fetch_kib": 192424.13, "write_kib": 147452.68},
+                             "sha256": "1f70c9e0ef0a11b1bf1f049d0fe273e332f1c5d0590c79c98b9edd13d5d9d146",
+                             "fetch_kib": 192211.72, "write_kib": 146972.8},
     "dense-50000x20000-bf16": {"files": ["gemm.hip"],
                                "sha256": "528bbd6a909efc6db290b4aa3aadad6fff075009e7c6bd17c23241f09d68dd09",
                                "fetch_kib": 19776476.63, "write_kib": 1120000.0},
