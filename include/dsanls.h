@@ -255,7 +255,11 @@ dsanls_status dsanls_gather_sketched_rows(dsanls_ctx* ctx, const int32_t* sel, i
  *               columns (dense subsample), or R from the CSR stream (sparse)
  *   small    -- B = W^T S, G = B B^T, R = A B^T and the transposes
  *   nnls     -- the batched NNLS update (prox-CD or PGD)
- * launches counts the half-iterations timed.  get_timing synchronises. */
+ * launches counts the half-iterations timed.  get_timing synchronises.
+ * With the environment variable DSANLS_TRACE set (to anything but "" or
+ * "0") when dsanls_init runs, timing is on from the start and
+ * dsanls_destroy writes one line to stderr with these four totals and the
+ * update count. */
 typedef struct {
   double sketch_ms, product_ms, small_ms, nnls_ms;
   int64_t launches;

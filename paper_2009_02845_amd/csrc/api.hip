@@ -2,6 +2,8 @@
 // of kernels of one half-iteration (Alg. 2 with N = 1).
 #include "common.hpp"
 
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -369,6 +371,9 @@ struct dsanls_ctx {
   dsanls_stats stats{};
   // phase timing: per phase, event pairs recorded while timing is on
   bool timing = false;
+  // DSANLS_TRACE in the environment at init: timing on from the start and a
+  // per-phase summary on stderr when the context is released
+  bool trace = false;
   std::vector<hipEvent_t> ev[4];
   int64_t timed_updates = 0;
   // outer iteration whose V-side sketch product A' = M^T S'^t is already in
@@ -795,6 +800,8 @@ dsanls_status dsanls_init(const dsanls_config* cfg, const dsanls_matrix* M, floa
   ctx->U = U;
   ctx->V = V;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
+  if (const char* tr = std::getenv("DSANLS_TRACE"); tr != nullptr && tr[0] != '\0' && std::strcmp(tr, "0") != 0)
+    ctx->timing = ctx->trace = true;
   ctx->L = plan(*cfg, *M, static_cast<char*>(workspace));
   const Layout& L = ctx->L;
   hipStream_t s = ctx->stream;
@@ -1060,6 +1067,15 @@ dsanls_status dsanls_debug_fetch(dsanls_ctx* ctx, int32_t which, void* dst, size
 
 dsanls_status dsanls_destroy(dsanls_ctx* ctx) {
   if (!ctx) return fail(DSANLS_E_STATE, "destroy: context is NULL");
+  if (ctx->trace) {
+    dsanls_timing t{};
+    if (dsanls_get_timing(ctx, &t) == DSANLS_OK) {
+      std::fprintf(stderr,
+                   "[dsanls] %lld updates: sketch %.3f ms, product %.3f ms, small %.3f ms, nnls %.3f ms\n",
+                   static_cast<long long>(t.launches), t.sketch_ms, t.product_ms, t.small_ms, t.nnls_ms);
+      std::fflush(stderr);
+    }
+  }
   delete ctx;
   return DSANLS_OK;
 }

@@ -443,3 +443,27 @@ def test_lookahead_reuse_matches_separate_calls(env):
     _, Vg2 = prob.get()
     V1 = O.update_V(M64, U, V, 4, ocfg)
     assert _rel(Vg2, O.update_V(M64, U, V1, 4, ocfg)) < 1e-4
+
+
+def test_trace_env_writes_phase_totals_at_release(env, monkeypatch, capfd):
+    # DSANLS_TRACE set at init: timing is on without set_timing, and releasing
+    # the context writes one stderr line with the update count and the four
+    # phase totals; without it nothing is written
+    M, U0, V0, ocfg = _c1(env)
+    monkeypatch.setenv("DSANLS_TRACE", "1")
+    prob = Dense(env, M, U0, V0, ocfg)
+    for t in range(3):
+        prob.solver.iteration(t)
+    tm = prob.solver.timing()
+    assert tm["launches"] == 6 and tm["product_ms"] > 0 and tm["nnls_ms"] > 0
+    capfd.readouterr()
+    prob.solver.close()
+    lines = [s for s in capfd.readouterr().err.splitlines() if s.startswith("[dsanls]")]
+    assert len(lines) == 1 and lines[0].startswith("[dsanls] 6 updates: sketch "), lines
+    assert all(f" {ph} " in lines[0] for ph in ("sketch", "product", "small", "nnls"))
+    monkeypatch.setenv("DSANLS_TRACE", "0")
+    quiet = Dense(env, M, U0, V0, ocfg)
+    quiet.solver.iteration(0)
+    assert quiet.solver.timing()["launches"] == 0
+    quiet.solver.close()
+    assert "[dsanls]" not in capfd.readouterr().err
