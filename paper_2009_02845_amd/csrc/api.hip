@@ -255,7 +255,8 @@ Layout plan(const dsanls_config& c, const dsanls_matrix& M, char* base) {
   L.partials = reinterpret_cast<float*>(take(sizeof(float) * 4 * np));
   L.red = reinterpret_cast<float*>(take(sizeof(float) * 64));
   L.err = reinterpret_cast<int*>(take(sizeof(int) * 16));
-  for (int sd = 0; sd < 2; ++sd) L.cs[sd].err = L.err + 1;
+  // (a sizing pass has no base: no pointer arithmetic on null)
+  for (int sd = 0; sd < 2; ++sd) L.cs[sd].err = L.err != nullptr ? L.err + 1 : nullptr;
   L.counters = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * 8));
   L.tol.counters = L.counters;
   if (c.solver == DSANLS_SOLVER_PROX_CD && c.sweeps == 0) {
